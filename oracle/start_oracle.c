@@ -1,0 +1,772 @@
+/*
+ * start_oracle.c -- CPU FP64 reference for the photoionization-rate path of
+ * START (Hasegawa & Umemura 2010).  TEST INFRASTRUCTURE ONLY: the checker the
+ * HIP library is compared against.  It shares no code with that library.
+ *
+ * What it computes, in the paper's order:
+ *   1. the octree of the radiation sources: the cube is split into 8 sub-cubes
+ *      until a cube holds a single source (section 2.2.2); capped at level 21,
+ *      where a cube with several sources is a bucket whose sources are used
+ *      one by one;
+ *   2. the virtual source of every cell: total luminosity, eq. (14), at the
+ *      centre of luminosity, eq. (15);
+ *   3. for every target particle the cells that pass the opening test
+ *      l^n / d^n <= theta (eq. 12) while their parent fails it (eq. 13), with d
+ *      the distance to the closest point of the cell, found top-down;
+ *   4. the optical depth from each (virtual) source to the target, integrated
+ *      along the straight ray (sections 2.2.1-2.2.2) through the neutral
+ *      hydrogen field, here a grid of SPH-interpolated densities (section 2.1
+ *      kernel), with exact chord lengths;
+ *   5. the rate per H I atom, the monochromatic form of Appendix A eq. (A2)
+ *      with on-the-spot attenuation (eq. 7):
+ *         Gamma_i = sigma / (4 pi) * sum_alpha L_alpha exp(-tau_alpha) / d_alpha^2,
+ *      excluding the target's own emission (k_other of eqs. 25-26).
+ *
+ * Built with -O2 -ffp-contract=off and no fast-math: every rounding is the
+ * one written here.
+ */
+#include "start_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int32_t level;
+    int32_t nchild;
+    int64_t c[3];
+    int64_t first, count;   /* members: t->idx[first .. first+count) */
+    int64_t child[8];       /* cell index per octant, -1 when empty */
+    double lum;             /* eq. (14) */
+    double com[3];          /* eq. (15) */
+} or_cell;
+
+struct or_tree {
+    or_box box;
+    int64_t n;
+    double *x;      /* [3][n] physical positions */
+    double *u;      /* [3][n] normalised positions */
+    double *lum;    /* [n] */
+    int64_t *idx;   /* [n] source indices grouped cell by cell */
+    or_cell *cells;
+    int64_t ncells, cap;
+};
+
+static int finite3(const double *xyz, int64_t n, int64_t i)
+{
+    return isfinite(xyz[i]) && isfinite(xyz[n + i]) && isfinite(xyz[2 * n + i]);
+}
+
+static int in_box(const or_box *b, const double *xyz, int64_t n, int64_t i)
+{
+    for (int k = 0; k < 3; ++k) {
+        double v = xyz[(int64_t)k * n + i];
+        if (v < b->lo[k] || v > b->lo[k] + b->size) return 0;
+    }
+    return 1;
+}
+
+static int check_box(const or_box *b)
+{
+    if (!b) return OR_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(b->lo[k])) return OR_ENONFINITE;
+    if (!isfinite(b->size) || !isfinite(b->unit_cm)) return OR_ENONFINITE;
+    if (!(b->size > 0) || !(b->unit_cm > 0)) return OR_EINVAL;
+    return OR_OK;
+}
+
+static int check_points(const or_box *b, int64_t n, const double *xyz)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (!finite3(xyz, n, i)) return OR_ENONFINITE;
+        if (!in_box(b, xyz, n, i)) return OR_EOUTOFBOX;
+    }
+    return OR_OK;
+}
+
+void or_normalise(const or_box *box, const double x[3], double u[3])
+{
+    double inv = 1.0 / box->size;
+    for (int k = 0; k < 3; ++k) {
+        double v = (x[k] - box->lo[k]) * inv;
+        u[k] = v > 1.0 ? 1.0 : v;
+    }
+}
+
+/* ---------------------------------------------------------------- tree --- */
+
+static int64_t new_cell(or_tree *t)
+{
+    if (t->ncells == t->cap) {
+        int64_t nc = t->cap ? 2 * t->cap : 1024;
+        or_cell *p = (or_cell *)realloc(t->cells, (size_t)nc * sizeof(or_cell));
+        if (!p) return -1;
+        t->cells = p;
+        t->cap = nc;
+    }
+    return t->ncells++;
+}
+
+/* Make the cell (level, c) holding idx[first..first+count) and, unless it is
+ * a single source or a level-21 bucket, its 8 sub-cubes (section 2.2.2). */
+static int64_t build_cell(or_tree *t, int32_t level, const int64_t c[3], int64_t first,
+                          int64_t count, int64_t *tmp)
+{
+    int64_t ci = new_cell(t);
+    if (ci < 0) return -1;
+    or_cell *cell = &t->cells[ci];
+    cell->level = level;
+    cell->nchild = 0;
+    for (int k = 0; k < 3; ++k) cell->c[k] = c[k];
+    cell->first = first;
+    cell->count = count;
+    for (int o = 0; o < 8; ++o) cell->child[o] = -1;
+
+    /* eqs. (14)-(15): summed over the members in ascending source index */
+    double L = 0.0, S[3] = {0.0, 0.0, 0.0};
+    for (int64_t m = first; m < first + count; ++m) {
+        int64_t j = t->idx[m];
+        L += t->lum[j];
+        for (int k = 0; k < 3; ++k) S[k] += t->lum[j] * t->x[(int64_t)k * t->n + j];
+    }
+    cell->lum = L;
+    for (int k = 0; k < 3; ++k) cell->com[k] = L > 0.0 ? S[k] / L : 0.0;
+
+    if (count < 2 || level >= OR_MAX_LEVEL) return ci;
+
+    /* split the cube at its mid-planes; octant o = 4*bx + 2*by + bz */
+    double mid[3];
+    for (int k = 0; k < 3; ++k) mid[k] = ldexp((double)(2 * c[k] + 1), -(level + 1));
+    int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t m = first; m < first + count; ++m) {
+        int64_t j = t->idx[m];
+        int o = 0;
+        for (int k = 0; k < 3; ++k) o = 2 * o + (t->u[(int64_t)k * t->n + j] >= mid[k]);
+        tmp[m] = o;
+    }
+    for (int64_t m = first; m < first + count; ++m) cnt[tmp[m]]++;
+    int64_t start[8], pos[8];
+    start[0] = first;
+    for (int o = 1; o < 8; ++o) start[o] = start[o - 1] + cnt[o - 1];
+    for (int o = 0; o < 8; ++o) pos[o] = start[o];
+    /* stable partition keeps each child's members in ascending index order */
+    int64_t *moved = (int64_t *)malloc((size_t)count * sizeof(int64_t));
+    if (!moved) return -1;
+    for (int64_t m = first; m < first + count; ++m) moved[pos[tmp[m]]++ - first] = t->idx[m];
+    memcpy(t->idx + first, moved, (size_t)count * sizeof(int64_t));
+    free(moved);
+
+    int nchild = 0;
+    for (int o = 0; o < 8; ++o) {
+        if (!cnt[o]) continue;
+        int64_t cc[3] = {2 * c[0] + ((o >> 2) & 1), 2 * c[1] + ((o >> 1) & 1), 2 * c[2] + (o & 1)};
+        int64_t ch = build_cell(t, level + 1, cc, start[o], cnt[o], tmp);
+        if (ch < 0) return -1;
+        t->cells[ci].child[o] = ch;   /* t->cells may have moved */
+        ++nchild;
+    }
+    t->cells[ci].nchild = nchild;
+    return ci;
+}
+
+int or_tree_build(const or_box *box, int64_t n, const double *xyz, const double *lum,
+                  or_tree **out)
+{
+    int rc = check_box(box);
+    if (rc) return rc;
+    if (!out || n < 0 || (n > 0 && (!xyz || !lum))) return OR_EINVAL;
+    rc = check_points(box, n, xyz);
+    if (rc) return rc;
+    for (int64_t j = 0; j < n; ++j) {
+        if (!isfinite(lum[j])) return OR_ENONFINITE;
+        if (lum[j] < 0.0) return OR_EINVAL;
+    }
+    or_tree *t = (or_tree *)calloc(1, sizeof(or_tree));
+    if (!t) return OR_ENOMEM;
+    t->box = *box;
+    t->n = n;
+    size_t nb = (size_t)(n > 0 ? n : 1);
+    t->x = (double *)malloc(3 * nb * sizeof(double));
+    t->u = (double *)malloc(3 * nb * sizeof(double));
+    t->lum = (double *)malloc(nb * sizeof(double));
+    t->idx = (int64_t *)malloc(nb * sizeof(int64_t));
+    int64_t *tmp = (int64_t *)malloc(nb * sizeof(int64_t));
+    if (!t->x || !t->u || !t->lum || !t->idx || !tmp) {
+        free(tmp);
+        or_tree_free(t);
+        return OR_ENOMEM;
+    }
+    if (n > 0) {
+        memcpy(t->x, xyz, 3 * (size_t)n * sizeof(double));
+        memcpy(t->lum, lum, (size_t)n * sizeof(double));
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double x[3] = {xyz[j], xyz[n + j], xyz[2 * n + j]}, u[3];
+        or_normalise(box, x, u);
+        for (int k = 0; k < 3; ++k) t->u[(int64_t)k * n + j] = u[k];
+        t->idx[j] = j;
+    }
+    if (n > 0) {
+        int64_t root[3] = {0, 0, 0};
+        if (build_cell(t, 0, root, 0, n, tmp) < 0) {
+            free(tmp);
+            or_tree_free(t);
+            return OR_ENOMEM;
+        }
+    }
+    free(tmp);
+    *out = t;
+    return OR_OK;
+}
+
+void or_tree_free(or_tree *t)
+{
+    if (!t) return;
+    free(t->x);
+    free(t->u);
+    free(t->lum);
+    free(t->idx);
+    free(t->cells);
+    free(t);
+}
+
+int64_t or_tree_ncells(const or_tree *t) { return t ? t->ncells : 0; }
+
+int or_tree_export(const or_tree *t, int32_t *level, int64_t *coord, int64_t *count,
+                   int32_t *nchild, double *lum, double *com, int64_t *member_off,
+                   int64_t *member_idx)
+{
+    if (!t) return OR_EINVAL;
+    for (int64_t i = 0; i < t->ncells; ++i) {
+        const or_cell *c = &t->cells[i];
+        if (level) level[i] = c->level;
+        if (nchild) nchild[i] = c->nchild;
+        if (count) count[i] = c->count;
+        if (lum) lum[i] = c->lum;
+        if (member_off) member_off[i] = c->first;
+        for (int k = 0; k < 3; ++k) {
+            if (coord) coord[3 * i + k] = c->c[k];
+            if (com) com[3 * i + k] = c->com[k];
+        }
+    }
+    if (member_idx && t->n > 0) memcpy(member_idx, t->idx, (size_t)t->n * sizeof(int64_t));
+    return OR_OK;
+}
+
+/* ---------------------------------------------------------------- walk --- */
+
+/* Eq. (12) with l the side of the level-n cube and d the distance from the
+ * target to the closest point of the closed cube (0 inside).  Normalised
+ * units, so l = 2^-n and the cube is [c 2^-n, (c+1) 2^-n] per axis exactly. */
+int or_accept(int32_t level, const int64_t coord[3], const double u[3], double theta)
+{
+    double l = ldexp(1.0, -level);
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+        double lo = ldexp((double)coord[k], -level);
+        double hi = ldexp((double)(coord[k] + 1), -level);
+        double a = lo - u[k];
+        double b = u[k] - hi;
+        double m = a > b ? a : b;
+        d[k] = m > 0.0 ? m : 0.0;
+    }
+    double d2 = fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+    double theta2 = theta * theta;
+    return l * l <= theta2 * d2;
+}
+
+typedef struct {
+    int64_t cell;   /* >= 0: virtual source in this cell; -1: individual source */
+    int64_t src;
+} or_entry;
+
+typedef struct {
+    or_entry *e;
+    int64_t n, cap;
+    int64_t ntest;
+    int failed;
+} or_list;
+
+static void push(or_list *L, int64_t cell, int64_t src)
+{
+    if (L->failed) return;
+    if (L->n == L->cap) {
+        int64_t nc = L->cap ? 2 * L->cap : 256;
+        or_entry *p = (or_entry *)realloc(L->e, (size_t)nc * sizeof(or_entry));
+        if (!p) {
+            L->failed = 1;
+            return;
+        }
+        L->e = p;
+        L->cap = nc;
+    }
+    L->e[L->n].cell = cell;
+    L->e[L->n].src = src;
+    L->n++;
+}
+
+/* A cell whose members all sit in one sub-cube has the same member set as
+ * that sub-cube; the entry is named by the deepest such cell. */
+static int64_t deepest_same_set(const or_tree *t, int64_t ci)
+{
+    for (;;) {
+        const or_cell *c = &t->cells[ci];
+        if (c->nchild != 1) return ci;
+        for (int o = 0; o < 8; ++o)
+            if (c->child[o] >= 0) {
+                ci = c->child[o];
+                break;
+            }
+    }
+}
+
+static void emit_source(const or_tree *t, or_list *L, int64_t j, int64_t self)
+{
+    if (j != self && t->lum[j] > 0.0) push(L, -1, j);
+}
+
+/* Top-down: a cell passing eq. (12) is used as one virtual source and its
+ * sub-cubes are not looked at, so every used cell also satisfies eq. (13).
+ * A single source is used as itself; a level-21 bucket that fails the test
+ * gives its sources one by one.  The target's own source is never used, and
+ * sources or cells of zero luminosity contribute nothing and are left out. */
+static void walk(const or_tree *t, int64_t ci, const double u[3], int64_t self,
+                 double theta, or_list *L)
+{
+    const or_cell *c = &t->cells[ci];
+    if (c->count == 1) {
+        emit_source(t, L, t->idx[c->first], self);
+        return;
+    }
+    int acc = or_accept(c->level, c->c, u, theta);
+    /* count tests as a walk over the tree without single-child chains does */
+    if (acc || c->nchild != 1) L->ntest++;
+    if (acc) {
+        if (c->lum > 0.0) push(L, deepest_same_set(t, ci), -1);
+        return;
+    }
+    if (c->nchild == 0) {   /* level-21 bucket */
+        for (int64_t m = c->first; m < c->first + c->count; ++m) emit_source(t, L, t->idx[m], self);
+        return;
+    }
+    for (int o = 0; o < 8; ++o)
+        if (c->child[o] >= 0) walk(t, c->child[o], u, self, theta, L);
+}
+
+static int list_for(const or_tree *t, const double x[3], int64_t self, double theta, or_list *L)
+{
+    L->n = 0;
+    L->ntest = 0;
+    L->failed = 0;
+    if (t->ncells == 0) return OR_OK;
+    double u[3];
+    or_normalise(&t->box, x, u);
+    walk(t, 0, u, self, theta, L);
+    return L->failed ? OR_ENOMEM : OR_OK;
+}
+
+static int check_targets(const or_box *b, int64_t n_t, const double *tgt, const int64_t *self_src,
+                         int64_t n_s, double theta)
+{
+    if (n_t < 0 || (n_t > 0 && !tgt)) return OR_EINVAL;
+    if (!isfinite(theta)) return OR_ENONFINITE;
+    if (theta < 0.0) return OR_EINVAL;
+    int rc = check_points(b, n_t, tgt);
+    if (rc) return rc;
+    if (self_src)
+        for (int64_t i = 0; i < n_t; ++i)
+            if (self_src[i] < -1 || self_src[i] >= n_s) return OR_EINVAL;
+    return OR_OK;
+}
+
+int or_interaction_lists(const or_tree *t, int64_t n_t, const double *tgt_xyz,
+                         const int64_t *self_src, double theta, int64_t *offsets,
+                         int64_t *entries, int64_t capacity)
+{
+    if (!t || !offsets) return OR_EINVAL;
+    int rc = check_targets(&t->box, n_t, tgt_xyz, self_src, t->n, theta);
+    if (rc) return rc;
+    or_list L = {0};
+    offsets[0] = 0;
+    int over = 0;
+    for (int64_t i = 0; i < n_t; ++i) {
+        double x[3] = {tgt_xyz[i], tgt_xyz[n_t + i], tgt_xyz[2 * n_t + i]};
+        rc = list_for(t, x, self_src ? self_src[i] : -1, theta, &L);
+        if (rc) {
+            free(L.e);
+            return rc;
+        }
+        int64_t base = offsets[i];
+        offsets[i + 1] = base + L.n;
+        if (offsets[i + 1] > capacity || !entries) {
+            over = 1;
+            continue;
+        }
+        for (int64_t k = 0; k < L.n; ++k) {
+            int64_t *e = entries + 4 * (base + k);
+            if (L.e[k].cell >= 0) {
+                const or_cell *c = &t->cells[L.e[k].cell];
+                e[0] = c->level;
+                e[1] = c->c[0];
+                e[2] = c->c[1];
+                e[3] = c->c[2];
+            } else {
+                e[0] = -1;
+                e[1] = L.e[k].src;
+                e[2] = 0;
+                e[3] = 0;
+            }
+        }
+    }
+    free(L.e);
+    return over ? OR_ECAPACITY : OR_OK;
+}
+
+/* ---------------------------------------------------------------- grid --- */
+
+/* Cubic spline of section 2.1 (Monaghan 1992): support 2h,
+ * W = f(r/h) / (pi h^3), f = 1 - 1.5 q^2 + 0.75 q^3 (q <= 1),
+ * 0.25 (2 - q)^3 (1 < q <= 2), 0 beyond. */
+double or_kernel_w(double r, double h)
+{
+    double q = r / h;
+    double f;
+    if (q <= 1.0)
+        f = 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+    else if (q <= 2.0)
+        f = 0.25 * (2.0 - q) * (2.0 - q) * (2.0 - q);
+    else
+        f = 0.0;
+    return f / (M_PI * h * h * h);
+}
+
+static int check_gas(const or_box *box, int64_t n, const double *xyz, const double *h,
+                     const double *nhi, int grid_log2)
+{
+    int rc = check_box(box);
+    if (rc) return rc;
+    if (n < 0 || grid_log2 < 0 || grid_log2 > 10) return OR_EINVAL;
+    if (n > 0 && (!xyz || !h || !nhi)) return OR_EINVAL;
+    rc = check_points(box, n, xyz);
+    if (rc) return rc;
+    for (int64_t k = 0; k < n; ++k) {
+        if (!isfinite(h[k]) || !isfinite(nhi[k])) return OR_ENONFINITE;
+        if (!(h[k] > 0.0) || nhi[k] < 0.0) return OR_EINVAL;
+    }
+    return OR_OK;
+}
+
+static void cell_centre(const or_box *box, int G, int64_t lin, double xc[3])
+{
+    int64_t ia = lin / ((int64_t)G * G), ib = (lin / G) % G, ic = lin % G;
+    int64_t a[3] = {ia, ib, ic};
+    double delta = box->size / G;
+    for (int k = 0; k < 3; ++k) xc[k] = box->lo[k] + ((double)a[k] + 0.5) * delta;
+}
+
+static double dist3(const double a[3], const double *xyz, int64_t n, int64_t k)
+{
+    double dx = a[0] - xyz[k], dy = a[1] - xyz[n + k], dz = a[2] - xyz[2 * n + k];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Shepard-normalised SPH interpolant at the cell centres:
+ *   n_c = sum_k nhi_k W(|x_c - r_k|, h_k) / sum_k W(|x_c - r_k|, h_k),
+ * summed in ascending particle index; 0 where no kernel reaches.  Particles
+ * are binned only to skip those whose kernel cannot reach a centre. */
+int or_grid_build(const or_box *box, int64_t n, const double *xyz, const double *h,
+                  const double *nhi, int grid_log2, double *out)
+{
+    int rc = check_gas(box, n, xyz, h, nhi, grid_log2);
+    if (rc) return rc;
+    if (!out) return OR_EINVAL;
+    const int G = 1 << grid_log2;
+    const int64_t ncell = (int64_t)G * G * G;
+    if (n == 0) {
+        memset(out, 0, (size_t)ncell * sizeof(double));
+        return OR_OK;
+    }
+    double rmax = 0.0;
+    for (int64_t k = 0; k < n; ++k) rmax = fmax(rmax, 2.0 * h[k]);
+    int64_t nb = (int64_t)floor(box->size / (rmax * 1.000001));
+    if (nb < 1) nb = 1;
+    if (nb > 256) nb = 256;
+    double w = box->size / (double)nb;
+    int64_t nbins = nb * nb * nb;
+    int64_t *head = (int64_t *)calloc((size_t)nbins + 1, sizeof(int64_t));
+    int64_t *bin = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *sorted = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!head || !bin || !sorted) {
+        free(head);
+        free(bin);
+        free(sorted);
+        return OR_ENOMEM;
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t b[3];
+        for (int a = 0; a < 3; ++a) {
+            int64_t v = (int64_t)floor((xyz[(int64_t)a * n + k] - box->lo[a]) / w);
+            b[a] = v < 0 ? 0 : (v >= nb ? nb - 1 : v);
+        }
+        bin[k] = (b[0] * nb + b[1]) * nb + b[2];
+        head[bin[k] + 1]++;
+    }
+    for (int64_t b = 0; b < nbins; ++b) head[b + 1] += head[b];
+    {
+        int64_t *fill = (int64_t *)malloc((size_t)nbins * sizeof(int64_t));
+        if (!fill) {
+            free(head);
+            free(bin);
+            free(sorted);
+            return OR_ENOMEM;
+        }
+        memcpy(fill, head, (size_t)nbins * sizeof(int64_t));
+        for (int64_t k = 0; k < n; ++k) sorted[fill[bin[k]]++] = k;
+        free(fill);
+    }
+    int err = 0;
+#pragma omp parallel
+    {
+        int64_t cap = 1024;
+        int64_t *cand = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+        if (!cand) {
+#pragma omp atomic write
+            err = 1;
+        }
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t lin = 0; lin < ncell; ++lin) {
+            if (!cand) continue;
+            double xc[3];
+            cell_centre(box, G, lin, xc);
+            int64_t cb[3];
+            for (int a = 0; a < 3; ++a) {
+                int64_t v = (int64_t)floor((xc[a] - box->lo[a]) / w);
+                cb[a] = v < 0 ? 0 : (v >= nb ? nb - 1 : v);
+            }
+            int64_t m = 0;
+            for (int64_t i0 = cb[0] - 1; i0 <= cb[0] + 1; ++i0)
+                for (int64_t i1 = cb[1] - 1; i1 <= cb[1] + 1; ++i1)
+                    for (int64_t i2 = cb[2] - 1; i2 <= cb[2] + 1; ++i2) {
+                        if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nb || i1 >= nb || i2 >= nb)
+                            continue;
+                        int64_t b = (i0 * nb + i1) * nb + i2;
+                        for (int64_t s = head[b]; s < head[b + 1]; ++s) {
+                            int64_t k = sorted[s];
+                            if (dist3(xc, xyz, n, k) < 2.0 * h[k]) {
+                                if (m == cap) {
+                                    int64_t *p = (int64_t *)realloc(cand, (size_t)(2 * cap) * sizeof(int64_t));
+                                    if (!p) {
+#pragma omp atomic write
+                                        err = 1;
+                                        goto next_cell;
+                                    }
+                                    cand = p;
+                                    cap *= 2;
+                                }
+                                cand[m++] = k;
+                            }
+                        }
+                    }
+            qsort(cand, (size_t)m, sizeof(int64_t), cmp_i64);
+            {
+                double num = 0.0, den = 0.0;
+                for (int64_t s = 0; s < m; ++s) {
+                    int64_t k = cand[s];
+                    double wk = or_kernel_w(dist3(xc, xyz, n, k), h[k]);
+                    num += nhi[k] * wk;
+                    den += wk;
+                }
+                out[lin] = den > 0.0 ? num / den : 0.0;
+            }
+        next_cell:;
+        }
+        free(cand);
+    }
+    free(head);
+    free(bin);
+    free(sorted);
+    return err ? OR_ENOMEM : OR_OK;
+}
+
+int or_grid_cells(const or_box *box, int64_t n, const double *xyz, const double *h,
+                  const double *nhi, int grid_log2, int64_t m, const int64_t *cells,
+                  double *out)
+{
+    int rc = check_gas(box, n, xyz, h, nhi, grid_log2);
+    if (rc) return rc;
+    const int G = 1 << grid_log2;
+    const int64_t ncell = (int64_t)G * G * G;
+    if (m < 0 || (m > 0 && (!cells || !out))) return OR_EINVAL;
+    for (int64_t s = 0; s < m; ++s)
+        if (cells[s] < 0 || cells[s] >= ncell) return OR_EINVAL;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < m; ++s) {
+        double xc[3];
+        cell_centre(box, G, cells[s], xc);
+        double num = 0.0, den = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            double wk = or_kernel_w(dist3(xc, xyz, n, k), h[k]);
+            num += nhi[k] * wk;
+            den += wk;
+        }
+        out[s] = den > 0.0 ? num / den : 0.0;
+    }
+    return OR_OK;
+}
+
+/* ----------------------------------------------------------- ray column --- */
+
+static int cmp_dbl(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Exact integral of the piecewise-constant grid field along a -> b.  In grid
+ * units g = (x - lo) G / size the ray is P(t) = A + t (B - A), t in [0, 1].
+ * Every crossing of an integer plane splits it; each piece lies in the cell
+ * holding its midpoint and contributes n_cell * (t_b - t_a).  The sum times
+ * |b - a| is the column in cm^-3 x length units. */
+static double column_buf(const or_box *box, int grid_log2, const double *grid, const double a[3],
+                         const double b[3], int64_t *ncells, double *ts)
+{
+    const int G = 1 << grid_log2;
+    const double s = (double)G / box->size;
+    double A[3], B[3], D[3];
+    for (int k = 0; k < 3; ++k) {
+        A[k] = (a[k] - box->lo[k]) * s;
+        B[k] = (b[k] - box->lo[k]) * s;
+        D[k] = B[k] - A[k];
+    }
+    int64_t m = 0;
+    ts[m++] = 0.0;
+    ts[m++] = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        if (D[k] == 0.0) continue;
+        double lo = A[k] < B[k] ? A[k] : B[k];
+        double hi = A[k] < B[k] ? B[k] : A[k];
+        for (double p = floor(lo) + 1.0; p < hi; p += 1.0) {
+            double t = (p - A[k]) / D[k];
+            if (t > 0.0 && t < 1.0) ts[m++] = t;
+        }
+    }
+    qsort(ts, (size_t)m, sizeof(double), cmp_dbl);
+    double sum = 0.0;
+    int64_t nc = 0;
+    for (int64_t q = 0; q + 1 < m; ++q) {
+        double ta = ts[q], tb = ts[q + 1];
+        if (!(tb > ta)) continue;
+        double tm = 0.5 * (ta + tb);
+        int64_t c[3];
+        for (int k = 0; k < 3; ++k) {
+            double p = A[k] + tm * D[k];
+            int64_t v = (int64_t)floor(p);
+            c[k] = v < 0 ? 0 : (v >= G ? G - 1 : v);
+        }
+        sum += grid[(c[0] * G + c[1]) * G + c[2]] * (tb - ta);
+        ++nc;
+    }
+    if (ncells) *ncells = nc;
+    double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+    return sum * sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+double or_column(const or_box *box, int grid_log2, const double *grid, const double a[3],
+                 const double b[3], int64_t *ncells)
+{
+    const int G = 1 << grid_log2;
+    double *ts = (double *)malloc((size_t)(3 * G + 4) * sizeof(double));
+    if (!ts) return NAN;
+    double v = column_buf(box, grid_log2, grid, a, b, ncells, ts);
+    free(ts);
+    return v;
+}
+
+/* --------------------------------------------------------------- rates --- */
+
+int or_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n_t,
+             const double *tgt_xyz, const int64_t *self_src, double theta, double sigma,
+             double *gamma_out, int64_t *counters, int nthreads)
+{
+    if (!t || !gamma_out || grid_log2 < 0 || grid_log2 > 10 || !grid) return OR_EINVAL;
+    if (!isfinite(sigma)) return OR_ENONFINITE;
+    if (sigma < 0.0) return OR_EINVAL;
+    int rc = check_targets(&t->box, n_t, tgt_xyz, self_src, t->n, theta);
+    if (rc) return rc;
+    const int G = 1 << grid_log2;
+    const double ucm = t->box.unit_cm;
+    const double four_pi = 4.0 * M_PI;
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        or_list L = {0};
+        double *ts = (double *)malloc((size_t)(3 * G + 4) * sizeof(double));
+        if (!ts) {
+#pragma omp atomic write
+            err = OR_ENOMEM;
+        }
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n_t; ++i) {
+            if (!ts) continue;
+            double x[3] = {tgt_xyz[i], tgt_xyz[n_t + i], tgt_xyz[2 * n_t + i]};
+            if (list_for(t, x, self_src ? self_src[i] : -1, theta, &L) != OR_OK) {
+#pragma omp atomic write
+                err = OR_ENOMEM;
+                continue;
+            }
+            double sum = 0.0;
+            int64_t ncell_tot = 0, nzero = 0;
+            for (int64_t e = 0; e < L.n; ++e) {
+                const double *r;
+                double ra[3], La;
+                if (L.e[e].cell >= 0) {
+                    const or_cell *c = &t->cells[L.e[e].cell];
+                    r = c->com;
+                    La = c->lum;
+                } else {
+                    int64_t j = L.e[e].src;
+                    for (int k = 0; k < 3; ++k) ra[k] = t->x[(int64_t)k * t->n + j];
+                    r = ra;
+                    La = t->lum[j];
+                }
+                double dx = x[0] - r[0], dy = x[1] - r[1], dz = x[2] - r[2];
+                double dist = sqrt(dx * dx + dy * dy + dz * dz);
+                if (dist == 0.0) {
+                    ++nzero;
+                    continue;
+                }
+                int64_t nc = 0;
+                double col = column_buf(&t->box, grid_log2, grid, r, x, &nc, ts);
+                ncell_tot += nc;
+                double tau = sigma * col * ucm;
+                double dcm = dist * ucm;
+                sum += La * exp(-tau) / (dcm * dcm);
+            }
+            gamma_out[i] = sigma / four_pi * sum;
+            if (counters) {
+                counters[4 * i + 0] = L.ntest;
+                counters[4 * i + 1] = L.n;
+                counters[4 * i + 2] = ncell_tot;
+                counters[4 * i + 3] = nzero;
+            }
+        }
+        free(ts);
+        free(L.e);
+    }
+    return err;
+}

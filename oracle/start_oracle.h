@@ -1,0 +1,114 @@
+/*
+ * start_oracle.h -- CPU FP64 reference for the photoionization-rate path of
+ * START (Hasegawa & Umemura 2010, "START: smoothed particle hydrodynamics
+ * with tree-based accelerated radiative transfer", MNRAS 407, 2632).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the checker that the HIP library is
+ * compared against.  It is plain, slow and written to be read against the
+ * paper: recursive geometric subdivision of the source cube (section 2.2.2),
+ * the opening test of eqs. (12)-(13), virtual sources of eqs. (14)-(15),
+ * on-the-spot attenuation (eq. 7) with the optical depth integrated exactly
+ * along each ray, and the sum over sources of Appendix A, eq. (A2), for a
+ * single frequency.  It shares no code with the HIP library.  Only tests, the
+ * smoke check and the CPU-baseline leg of the benchmark may call it.
+ *
+ * Conventions: positions are structure-of-arrays [3][n] in any length unit;
+ * box_unit_cm converts that unit to cm.  All arithmetic is IEEE FP64 with
+ * contraction disabled; fma() is used only where written.
+ */
+#ifndef START_ORACLE_H
+#define START_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-2)
+#define OR_EOUTOFBOX (-4)
+#define OR_ENONFINITE (-5)
+#define OR_ECAPACITY (-6)
+
+#define OR_MAX_LEVEL 21
+
+typedef struct or_tree or_tree;
+
+/* Cubic box [lo, lo+size]^3.  unit_cm: cm per length unit. */
+typedef struct {
+    double lo[3];
+    double size;
+    double unit_cm;
+} or_box;
+
+/* Octree over the sources: cubes split into 8 until one source remains or
+ * level 21 is reached (section 2.2.2).  xyz is [3][n]; lum[n] >= 0. */
+int or_tree_build(const or_box *box, int64_t n, const double *xyz, const double *lum,
+                  or_tree **out);
+void or_tree_free(or_tree *t);
+
+/* Number of cells of the full octree (every cell holding >= 1 source). */
+int64_t or_tree_ncells(const or_tree *t);
+
+/* Export of every cell: level, integer coordinates [3], member count,
+ * number of non-empty children, luminosity and centre of luminosity [3]
+ * (eqs. 14-15), and the offset of its members in member_idx.  The members
+ * of a cell are contiguous, in depth-first octant order of its sub-cubes;
+ * a cell that is not split (one source or a level-21 bucket) lists them in
+ * ascending source index. */
+int or_tree_export(const or_tree *t, int32_t *level, int64_t *coord, int64_t *count,
+                   int32_t *nchild, double *lum, double *com, int64_t *member_off,
+                   int64_t *member_idx);
+
+/* Normalised position u = min((x - lo) / size, 1) as used for the tree. */
+void or_normalise(const or_box *box, const double x[3], double u[3]);
+
+/* Opening test of eqs. (12)-(13) for one cell and one normalised point:
+ * returns 1 when l^2 <= theta^2 d^2 with d the distance to the closest point
+ * of the cell. */
+int or_accept(int32_t level, const int64_t coord[3], const double u[3], double theta);
+
+/* Interaction lists: for each target, the sequence of entries of the walk in
+ * depth-first octant order.  Each entry is 4 int64: (level, c0, c1, c2) for a
+ * virtual source (the deepest cell with the same member set) or
+ * (-1, source_index, 0, 0) for an individual source.  offsets has n_t+1
+ * elements; entries capacity is counted in entries.  Returns OR_ECAPACITY
+ * (with offsets filled) when the lists do not fit. */
+int or_interaction_lists(const or_tree *t, int64_t n_t, const double *tgt_xyz,
+                         const int64_t *self_src, double theta, int64_t *offsets,
+                         int64_t *entries, int64_t capacity);
+
+/* SPH kernel of section 2.1: cubic spline with support 2h, 3-D normalisation. */
+double or_kernel_w(double r, double h);
+
+/* Neutral-hydrogen density at the centres of a G^3 grid over the box:
+ * Shepard-normalised SPH interpolant, 0 where no kernel reaches.
+ * out[(ix*G + iy)*G + iz]. */
+int or_grid_build(const or_box *box, int64_t n, const double *xyz, const double *h,
+                  const double *nhi, int grid_log2, double *out);
+
+/* Same value for a subset of cells given by linear index (brute force over
+ * all particles, used to check sampled cells of large grids). */
+int or_grid_cells(const or_box *box, int64_t n, const double *xyz, const double *h,
+                  const double *nhi, int grid_log2, int64_t m, const int64_t *cells,
+                  double *out);
+
+/* Column integral of n_HI (cm^-3 times length units) along the segment a->b
+ * of the piecewise-constant grid field; ncells (may be NULL) receives the
+ * number of cells with a chord of positive length. */
+double or_column(const or_box *box, int grid_log2, const double *grid, const double a[3],
+                 const double b[3], int64_t *ncells);
+
+/* Photoionization rate per H I atom (s^-1) of each target:
+ *   Gamma_i = sigma/(4 pi) sum_alpha L_alpha exp(-tau_alpha) / d_alpha^2
+ * over the entries of the target's interaction list.
+ * counters (may be NULL): [n_t][4] = tests, entries, grid cells, zero-distance skips. */
+int or_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n_t,
+             const double *tgt_xyz, const int64_t *self_src, double theta, double sigma,
+             double *gamma_out, int64_t *counters, int nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
