@@ -1,0 +1,275 @@
+#!/usr/bin/env python3
+"""Throughput of the START photoionization-rate path on one MI355X.
+
+One step = the whole hot path over one synthetic snapshot, inputs resident
+in HBM: source octree (Morton keys, radix sort, cells, virtual-source
+moments), neutral-hydrogen grid, target ordering, and the tree walk with ray
+marches that produces Gamma for every particle.  value = particles / step time.
+
+Also measured in the same run: the rate call alone with tree and grid
+resident (FP32C and FP64), the walk kernel's duration from HIP events on the
+library's stream (roofline against HBM bandwidth with the algorithmic byte
+model), and the CPU FP64 checker on a bounded sample (cpu_baseline).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload diffuse]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-rate evals/s at θ_crit=1 (FP32 vs FP64 GPU); serve p50/p99 latency"
+WORKLOAD_TEXT = {
+    "diffuse": "diffuse recombination: N_p = 2^20 emitting SPH particles + central 1e50/s star "
+               "(N_s = 2^20 + 1), HII sphere r = 0.3 box, theta_crit = 1, G = 128",
+    "shadow": "shadowing: N_p = 2^21 emitters + 1e50/s star, 16 clumps (200x, r = 0.05 box), theta_crit = 1, G = 128",
+    "clumpy": "clumpy: N_p = 2^18 lognormal medium, N_s = 1024 log-uniform sources, theta_crit = 1, G = 64",
+    "small": "small: N_p = 4096 uniform neutral medium, N_s = 16, theta_crit = 1, G = 16",
+}
+# algorithmic bytes per target (FP32C and FP64): target position + Gamma,
+# per opening test (cell key|level 8 B + subtree link 4 B), per entry
+# (centre + luminosity), per grid cell crossed (one density value)
+BYTES = {"fp32c": dict(base=24 + 4, test=12, entry=16, cell=4),
+         "fp64": dict(base=24 + 8, test=12, entry=32, cell=8)}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(counters, prec):
+    b = BYTES[prec]
+    c = counters.sum(axis=0).astype(np.float64)
+    n = counters.shape[0]
+    return b["base"] * n + b["test"] * c[0] + b["entry"] * c[1] + b["cell"] * c[2]
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(os.path.join(ROOT, "paper_1005_5312_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1005_5312_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload, prec, sha):
+    """HBM bytes per walk launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"walk_{prec}_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha") != sha:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, sample, seed=17):
+    """The CPU FP64 checker on this host: tree and grid built in full, rates
+    on a seeded sample of targets, whole step extrapolated linearly in the
+    number of targets."""
+    from oracle import oracle as O
+    from paper_1005_5312_amd import workloads as W
+    threads = os.cpu_count() or 1
+    box = O.make_box(w.box_lo, w.box_size, w.length_unit_cm)
+    t0 = time.perf_counter()
+    tree = O.Tree(box, w.src_xyz, w.src_lum)
+    t1 = time.perf_counter()
+    grid = O.grid(box, w.gas_xyz, w.gas_h, w.gas_nhi, w.grid_log2)
+    t2 = time.perf_counter()
+    idx = W.sample_indices(w.n_tgt, sample, seed)
+    ss = None if w.self_src is None else w.self_src[idx]
+    O.rates(tree, w.grid_log2, grid, w.tgt_xyz[:, idx], ss, 1.0, w.sigma, nthreads=threads)
+    t3 = time.perf_counter()
+    step = (t1 - t0) + (t2 - t1) + (t3 - t2) * w.n_tgt / len(idx)
+    return {"value": w.n_tgt / step, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 checker, {threads} threads: full tree ({t1 - t0:.2f} s) and grid ({t2 - t1:.2f} s), "
+                      f"rates for {len(idx)} of {w.n_tgt} targets ({t3 - t2:.2f} s); step time extrapolated "
+                      f"to all targets = {step:.1f} s",
+            "rates_only_evals_per_s": len(idx) / (t3 - t2)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="diffuse", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--theta", type=float, default=1.0)
+    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rates-only", action="store_true",
+                    help="time only the rate call (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        log(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+            "the rate path would shard targets across GPUs, which is not built here.")
+        sys.exit(2)
+
+    import torch
+    import paper_1005_5312_amd as S
+    from paper_1005_5312_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU")
+        sys.exit(1)
+    S.lib()   # fail loudly if the HIP library is missing
+
+    log(f"[bench] generating workload {args.workload}")
+    w = W.make(args.workload)
+    box = S.Box(tuple(float(v) for v in w.box_lo), float(w.box_size), float(w.length_unit_cm))
+    dev = torch.device("cuda", 0)
+    src_xyz = torch.from_numpy(w.src_xyz).to(dev)
+    src_lum = torch.from_numpy(w.src_lum).to(dev)
+    gas_xyz = torch.from_numpy(w.gas_xyz).to(dev)
+    gas_h = torch.from_numpy(w.gas_h).to(dev)
+    gas_nhi = torch.from_numpy(w.gas_nhi).to(dev)
+    tgt = torch.from_numpy(np.ascontiguousarray(w.tgt_xyz)).to(dev)
+    ss = None if w.self_src is None else torch.from_numpy(w.self_src).to(dev)
+    out32 = torch.empty(w.n_tgt, dtype=torch.float32, device=dev)
+    out64 = torch.empty(w.n_tgt, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    ctx = S.Context(0)
+    stream = ctx.stream
+    theta = args.theta
+
+    def step():
+        tree = ctx.build_source_tree(box, src_xyz, src_lum)
+        grid = ctx.build_gas_grid(box, gas_xyz, gas_h, gas_nhi, w.grid_log2)
+        ctx.compute_rates(tree, grid, tgt, ss, theta, w.sigma, "fp32c", out=out32)
+        return tree, grid
+
+    result = {}
+    if not args.rates_only:
+        log(f"[bench] warmup {args.warmup} full steps")
+        for _ in range(args.warmup):
+            t, g = step()
+            ctx.synchronize()
+            t.free()
+            g.free()
+        torch.cuda.synchronize()
+        log(f"[bench] timing {args.steps} full steps")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            t, g = step()
+            t.free()
+            g.free()
+        ctx.synchronize()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+        result["ms_per_step"] = ms_step
+        log(f"[bench] full step {ms_step:.3f} ms")
+
+    # resident tree and grid: phase times and the rate call alone
+    ta = time.perf_counter()
+    tree = ctx.build_source_tree(box, src_xyz, src_lum)
+    tb = time.perf_counter()
+    grid = ctx.build_gas_grid(box, gas_xyz, gas_h, gas_nhi, w.grid_log2)
+    tc = time.perf_counter()
+    rates = {}
+    kern = {}
+    for prec, out in (("fp32c", out32), ("fp64", out64)):
+        for _ in range(max(1, args.warmup)):
+            ctx.compute_rates(tree, grid, tgt, ss, theta, w.sigma, prec, out=out)
+        ctx.synchronize()
+        ctx.profile(True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.compute_rates_raw(tree, grid, tgt, ss, theta, w.sigma, prec, out)
+        e1.record(stream)
+        ctx.synchronize()
+        ms = e0.elapsed_time(e1) / max(args.steps, 1)
+        n, tot, mx = ctx.profile_read()
+        ctx.profile(False)
+        rates[prec] = {"ms_per_call": ms, "evals_per_s": w.n_tgt / (ms * 1e-3)}
+        kern[prec] = {"launches": n, "avg_ms": tot / max(n, 1), "max_ms": mx}
+        log(f"[bench] rates {prec}: {ms:.3f} ms/call, walk kernel avg {tot / max(n, 1):.3f} ms")
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    log("[bench] work counters")
+    cnt = {p: ctx.rate_counters(tree, grid, tgt, ss, theta, p) for p in ("fp32c",)}
+    c = cnt["fp32c"]
+    sha = source_sha()
+    alg = {p: algorithmic_bytes(c, p) for p in ("fp32c", "fp64")}
+    prec = "fp32c"
+    ach = alg[prec] / (kern[prec]["avg_ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(args.workload, prec, sha),
+                "kernel": "walk_kernel<FP32C> (tree walk + ray march + Gamma)",
+                "algorithmic_bytes_per_launch": alg[prec], "kernel_avg_ms": round(kern[prec]["avg_ms"], 4)}
+    ach64 = alg["fp64"] / (kern["fp64"]["avg_ms"] * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline and not args.rates_only:
+        log(f"[bench] CPU baseline (oracle) on {args.cpu_sample} sampled targets")
+        cpu = cpu_baseline(w, args.cpu_sample)
+
+    ms_step = result.get("ms_per_step", rates["fp32c"]["ms_per_call"])
+    line = {
+        "metric": METRIC,
+        "value": w.n_tgt / (ms_step * 1e-3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[args.workload], "n_targets": w.n_tgt, "n_sources": w.n_src,
+                   "grid": 1 << w.grid_log2, "theta_crit": theta, "precision": "fp32c (fp64 opening test)",
+                   "step": "tree build + gas grid + target order + walk/march/Gamma"
+                   if not args.rates_only else "rate call only"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phases_ms": {"tree_build": (tb - ta) * 1e3, "grid_build": (tc - tb) * 1e3,
+                      "rates_fp32c": rates["fp32c"]["ms_per_call"], "rates_fp64": rates["fp64"]["ms_per_call"]},
+        "rates_only": {"fp32c_evals_per_s": rates["fp32c"]["evals_per_s"],
+                       "fp64_evals_per_s": rates["fp64"]["evals_per_s"],
+                       "fp64_walk_kernel_ms": round(kern["fp64"]["avg_ms"], 4),
+                       "fp64_roofline_frac": round(ach64 / HBM_PEAK_GBS, 4)},
+        "work_per_target": {"opening_tests": float(c[:, 0].mean()), "entries": float(c[:, 1].mean()),
+                            "grid_cells": float(c[:, 2].mean())},
+        "source_sha": sha,
+    }
+    print(json.dumps(line), flush=True)
+    tree.free()
+    grid.free()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

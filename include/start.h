@@ -1,0 +1,188 @@
+/*
+ * start.h -- C-ABI of libstart: photoionization rates of SPH particles lit by
+ * many radiation sources, with the tree acceleration of START (Hasegawa &
+ * Umemura 2010, "START: smoothed particle hydrodynamics with tree-based
+ * accelerated radiative transfer", MNRAS 407, 2632), on AMD MI355X (gfx950).
+ *
+ * What is computed (one frequency, the Lyman limit, cross-section sigma):
+ *
+ *   Gamma_i = sigma / (4 pi) * sum_alpha L_alpha exp(-tau_alpha) / d_alpha^2
+ *
+ * for every target particle i: the photoionization rate per H I atom of
+ * Appendix A eq. (A2) with on-the-spot attenuation (eq. 7).  The sum runs over
+ * the virtual sources of section 2.2.2: the source octree is walked from the
+ * root and a cell of side l at distance d (to the cell's closest point) is
+ * used whole when l/d <= theta_crit (eq. 12) while its parent was not
+ * (eq. 13); it then shines with the summed luminosity (eq. 14) from its centre
+ * of luminosity (eq. 15).  Single sources are used as themselves.  The
+ * target's own source (self_src) is never used: k_other of eqs. (25)-(26).
+ * tau_alpha = sigma * integral of n_HI along the straight segment between the
+ * (virtual) source and the target, through a G^3 grid of Shepard-normalised
+ * SPH densities (kernel of section 2.1) that is integrated exactly cell by
+ * cell.  k_ion,i = n_HI,i * Gamma_i if the caller needs the rate per volume.
+ *
+ * Conventions for every call:
+ *  - Positions are structure-of-arrays [3][n] (all x, then all y, then all z)
+ *    in any length unit; start_box.length_unit_cm converts it to cm.  Every
+ *    position must lie in the closed cube [lo, lo + size]^3.
+ *  - Array arguments are DEVICE pointers (hipMalloc'd or torch tensors on the
+ *    context's device) unless marked "host or device"; the caller owns them
+ *    and must keep them alive until the context stream has passed the call.
+ *  - Calls are asynchronous on the context stream unless stated otherwise.
+ *    Argument errors are returned at once.  Problems in device data found by
+ *    an asynchronous call (non-finite or out-of-box targets, self_src out of
+ *    range) are reported by the next start_synchronize.
+ *  - Errors are status codes; nothing aborts and no exception crosses the
+ *    ABI.  start_last_error gives a message for the last failing call.
+ *  - A context is used by one host thread at a time.
+ *  - n = 0 is a valid no-op (Gamma is not written).
+ */
+#ifndef START_H
+#define START_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    START_OK = 0,
+    START_EINVAL = -1,       /* bad argument: null pointer, n < 0, theta < 0, L < 0, h <= 0 ... */
+    START_ENOMEM = -2,       /* device allocation failed */
+    START_EHIP = -3,         /* HIP runtime error */
+    START_EOUTOFBOX = -4,    /* a position outside the box */
+    START_ENONFINITE = -5,   /* NaN or Inf in the input */
+    START_EBUDGET = -6,      /* allocation would exceed the context's HBM budget */
+    START_ENOTIMPL = -7,     /* not implemented */
+    START_ECAPACITY = -8     /* output buffer too small (required size is returned) */
+} start_status;
+
+typedef enum {
+    START_FP64 = 0,   /* march, exp and sums in FP64; Gamma written as double */
+    START_FP32C = 1   /* FP64 opening test (same lists), FP32 march with Kahan-compensated
+                         tau and Gamma sums; Gamma written as float */
+} start_precision;
+
+/* Cubic box [lo, lo+size]^3 holding sources, gas and targets. */
+typedef struct {
+    double lo[3];
+    double size;              /* > 0 */
+    double length_unit_cm;    /* cm per length unit, > 0 */
+} start_box;
+
+typedef struct start_ctx start_ctx;
+typedef struct start_tree start_tree;
+typedef struct start_grid start_grid;
+
+/* Context on `device`.  hip_stream: a hipStream_t to run on, or NULL for a
+ * stream of its own.  hbm_budget_bytes: cap on the device memory the library
+ * allocates through this context (0 = no cap); allocations beyond it fail
+ * with START_EBUDGET. */
+start_status start_ctx_create(int device, void *hip_stream, size_t hbm_budget_bytes, start_ctx **out);
+void start_ctx_destroy(start_ctx *ctx);
+/* Message of the last failing call on ctx; valid until the next call. */
+const char *start_last_error(const start_ctx *ctx);
+/* Waits for the context stream and reports device-side input errors. */
+start_status start_synchronize(start_ctx *ctx);
+/* Device memory currently held by trees, grids and scratch of ctx. */
+size_t start_bytes_in_use(const start_ctx *ctx);
+
+/* Octree over n_s sources (section 2.2.2, eqs. 14-15).  src_xyz [3][n_s],
+ * src_lum [n_s] photons per second, >= 0 and finite.  Synchronous: returns
+ * after validation (START_EOUTOFBOX / START_ENONFINITE / START_EINVAL).  The
+ * tree owns its device memory until start_tree_free. */
+start_status start_build_source_tree(start_ctx *ctx, const start_box *box, int64_t n_s, const double *src_xyz,
+                                     const double *src_lum, start_tree **out);
+start_status start_tree_free(start_ctx *ctx, start_tree *tree);
+
+/* Neutral-hydrogen grid: G = 2^grid_log2 cells per axis (1 <= grid_log2 <= 10;
+ * 0 picks G = 2^ceil(log2(n_gas^(1/3)))), value at each cell centre
+ *   n_c = sum_k nhi_k W(|x_c - r_k|, h_k) / sum_k W(|x_c - r_k|, h_k),
+ * W the cubic spline of section 2.1 with support 2h, 0 where no kernel
+ * reaches.  gas_xyz [3][n_gas], gas_h [n_gas] > 0, gas_nhi [n_gas] >= 0
+ * (cm^-3).  Synchronous, validates like the tree. */
+start_status start_build_gas_grid(start_ctx *ctx, const start_box *box, int64_t n_gas, const double *gas_xyz,
+                                  const double *gas_h, const double *gas_nhi, int grid_log2, start_grid **out);
+start_status start_grid_free(start_ctx *ctx, start_grid *grid);
+/* G of a grid (host). */
+int start_grid_size(const start_grid *grid);
+
+/* Gamma for n_t targets: tgt_xyz [3][n_t]; self_src [n_t] original source
+ * index of each target's own emission, -1 for none, or NULL; theta_crit >= 0
+ * (0 = every source individually); sigma_cm2 >= 0.  gamma_out [n_t], in the
+ * targets' input order, double for START_FP64 and float for START_FP32C,
+ * s^-1 per H I atom.  Tree and grid must have been built on the same box.
+ * Asynchronous; uses context scratch that is grown when needed (so the first
+ * call of a larger size allocates and synchronises). */
+start_status start_compute_rates(start_ctx *ctx, const start_tree *tree, const start_grid *grid, int64_t n_t,
+                                 const double *tgt_xyz, const int64_t *self_src, double theta_crit,
+                                 double sigma_cm2, start_precision prec, void *gamma_out);
+
+/* One independent rate problem for start_compute_rates_batched. */
+typedef struct {
+    const start_tree *tree;
+    const start_grid *grid;
+    int64_t n_t;
+    const double *tgt_xyz;
+    const int64_t *self_src;
+    double theta_crit;
+    double sigma_cm2;
+    start_precision prec;
+    void *gamma_out;
+} start_item;
+
+/* Several independent problems (each exactly as start_compute_rates would
+ * compute it) enqueued together on the context stream. */
+start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const start_item *items);
+
+/* Upper bound of the device bytes a tree, grid and rate call of these sizes
+ * hold at once (for admission by memory). */
+size_t start_estimate_bytes(int64_t n_t, int64_t n_s, int64_t n_gas, int grid_log2, start_precision prec);
+
+/* ---- parity and diagnostics (synchronous; buffers host or device) ---- */
+
+/* Tree in depth-first order.  *n_nodes (host) receives the node count; each
+ * array may be NULL.  keys_sorted [n_s] Morton keys in sorted order (bit
+ * 3b+2 = x bit b, 3b+1 = y, 3b = z, 21 bits per axis); perm [n_s] original
+ * index of each sorted source; node_geo [n][4] = (cx, cy, cz, level | kind<<8)
+ * with kind 0 = cell that splits, 1 = level-21 bucket, 2 = single source;
+ * node_link [n][4] = (index after the subtree, first sorted source, source
+ * count, original source index of a single source or -1); node_mom [n][4] =
+ * (centre of luminosity x, y, z; luminosity) in FP64. */
+start_status start_tree_export(start_ctx *ctx, const start_tree *tree, int64_t *n_nodes, uint64_t *keys_sorted,
+                               uint32_t *perm, int32_t *node_geo, int32_t *node_link, double *node_mom);
+
+/* Interaction lists of the walk, per target in input order.  offsets [n_t+1]
+ * (host or device) receives the prefix of the list lengths; entries
+ * [capacity] (host or device) receives, per target in depth-first order, the
+ * node index of each cell used whole, or -(original source index)-1 of each
+ * source used individually.  Returns START_ECAPACITY, with offsets filled,
+ * when offsets[n_t] > capacity. */
+start_status start_interaction_lists(start_ctx *ctx, const start_tree *tree, int64_t n_t, const double *tgt_xyz,
+                                     const int64_t *self_src, double theta_crit, int64_t *offsets,
+                                     int64_t *entries, int64_t capacity);
+
+/* Grid values [G^3] (host or device), index (ix*G + iy)*G + iz, FP64. */
+start_status start_grid_export(start_ctx *ctx, const start_grid *grid, double *values);
+
+/* Per-target work counters [n_t][4] (host or device) of the rate walk:
+ * opening tests, entries used, grid cells crossed, entries skipped at zero
+ * distance. */
+start_status start_rate_counters(start_ctx *ctx, const start_tree *tree, const start_grid *grid, int64_t n_t,
+                                 const double *tgt_xyz, const int64_t *self_src, double theta_crit,
+                                 start_precision prec, int64_t *counters);
+
+/* Kernel timing of the rate walk (the dominant kernel): while enabled, every
+ * start_compute_rates records HIP events on the context stream around its
+ * walk kernel.  start_profile_read waits for the stream, returns the number
+ * of timed launches with the total and largest duration in milliseconds
+ * (host pointers, each may be NULL) and clears the record. */
+start_status start_profile_enable(start_ctx *ctx, int enable);
+start_status start_profile_read(start_ctx *ctx, int64_t *launches, double *total_ms, double *max_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,491 @@
+// C-ABI entry points of libstart (declared in include/start.h).
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+namespace start {
+
+start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *xyz, const double *lum, Tree *t);
+start_status build_grid(Ctx *c, const start_box &box, int64_t n, const double *xyz, const double *h,
+                        const double *nhi, int grid_log2, Grid *g);
+void make_fp32_tree(Tree *t, hipStream_t s);
+size_t target_scratch_bytes(int64_t n);
+void prepare_targets(Ctx *c, const start_box &box, int64_t n_t, const double *tgt_xyz, const int64_t *self_src,
+                     int64_t n_src, void *scratch, hipStream_t s);
+void launch_rates(const Tree *t, const Grid *g, int64_t n_t, void *scratch, const int64_t *self_src,
+                  double theta, double sigma, int prec, void *gamma, hipStream_t s);
+void launch_counts(const Tree *t, int64_t n_t, void *scratch, const int64_t *self_src, double theta,
+                   int64_t *counts, hipStream_t s);
+void launch_lists(const Tree *t, int64_t n_t, void *scratch, const int64_t *self_src, double theta,
+                  const int64_t *offsets, int64_t *entries, hipStream_t s);
+void launch_stats(const Tree *t, const Grid *g, int64_t n_t, void *scratch, const int64_t *self_src,
+                  double theta, int prec, int64_t *stats, hipStream_t s);
+
+hipError_t dmalloc(Ctx *c, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (c->budget && c->in_use + bytes > c->budget) return hipErrorOutOfMemory;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) c->in_use += bytes;
+    return e;
+}
+
+void dfree(Ctx *c, void *p, size_t bytes)
+{
+    if (!p) return;
+    if (bytes == 0) bytes = 256;
+    hipFree(p);
+    c->in_use -= bytes < c->in_use ? bytes : c->in_use;
+}
+
+}  // namespace start
+
+struct start_ctx {
+    start::Ctx c;
+};
+struct start_tree {
+    start::Tree t;
+};
+struct start_grid {
+    start::Grid g;
+};
+
+using namespace start;
+
+namespace {
+
+start_status fail(start_ctx *ctx, start_status st, const char *msg)
+{
+    if (ctx) ctx->c.err = msg;
+    return st;
+}
+
+start_status check_box(start_ctx *ctx, const start_box *box)
+{
+    if (!box) return fail(ctx, START_EINVAL, "box is NULL");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(box->lo[k])) return fail(ctx, START_ENONFINITE, "box corner is not finite");
+    if (!std::isfinite(box->size) || !std::isfinite(box->length_unit_cm))
+        return fail(ctx, START_ENONFINITE, "box size or unit is not finite");
+    if (!(box->size > 0.0) || !(box->length_unit_cm > 0.0))
+        return fail(ctx, START_EINVAL, "box size and length unit must be > 0");
+    return START_OK;
+}
+
+bool same_box(const start_box &a, const start_box &b)
+{
+    return a.lo[0] == b.lo[0] && a.lo[1] == b.lo[1] && a.lo[2] == b.lo[2] && a.size == b.size &&
+           a.length_unit_cm == b.length_unit_cm;
+}
+
+start_status ensure_scratch(start_ctx *ctx, size_t bytes)
+{
+    Ctx &c = ctx->c;
+    if (c.scratch_bytes >= bytes) return START_OK;
+    hipStreamSynchronize(c.stream);
+    dfree(&c, c.scratch, c.scratch_bytes);
+    c.scratch = nullptr;
+    c.scratch_bytes = 0;
+    size_t want = bytes + bytes / 4;
+    hipError_t e = dmalloc(&c, &c.scratch, want);
+    if (e != hipSuccess) {
+        if (c.budget && c.in_use + want > c.budget) return fail(ctx, START_EBUDGET, "HBM budget exceeded");
+        return fail(ctx, START_ENOMEM, "device allocation failed");
+    }
+    c.scratch_bytes = want;
+    return START_OK;
+}
+
+start_status check_rate_args(start_ctx *ctx, const start_tree *tree, const start_grid *grid, int64_t n_t,
+                             const double *tgt, double theta, double sigma, int prec, bool need_grid)
+{
+    if (!ctx) return START_EINVAL;
+    if (!tree) return fail(ctx, START_EINVAL, "tree is NULL");
+    if (need_grid && !grid) return fail(ctx, START_EINVAL, "grid is NULL");
+    if (n_t < 0) return fail(ctx, START_EINVAL, "n_t < 0");
+    if (n_t > 0 && !tgt) return fail(ctx, START_EINVAL, "target positions are NULL");
+    if (n_t > ((int64_t)1 << 31) - 1) return fail(ctx, START_EINVAL, "n_t too large");
+    if (!std::isfinite(theta) || !std::isfinite(sigma)) return fail(ctx, START_ENONFINITE, "theta or sigma not finite");
+    if (theta < 0.0 || sigma < 0.0) return fail(ctx, START_EINVAL, "theta and sigma must be >= 0");
+    if (prec != START_FP64 && prec != START_FP32C) return fail(ctx, START_EINVAL, "unknown precision");
+    if (need_grid && !same_box(tree->t.box, grid->g.box))
+        return fail(ctx, START_EINVAL, "tree and grid were built on different boxes");
+    return START_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+start_status start_ctx_create(int device, void *hip_stream, size_t hbm_budget_bytes, start_ctx **out)
+{
+    if (!out) return START_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return START_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return START_EHIP;
+    start_ctx *ctx = new (std::nothrow) start_ctx;
+    if (!ctx) return START_ENOMEM;
+    ctx->c.device = device;
+    ctx->c.budget = hbm_budget_bytes;
+    if (hip_stream) {
+        ctx->c.stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->c.stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return START_EHIP;
+        }
+        ctx->c.own_stream = true;
+    }
+    if (hipMalloc((void **)&ctx->c.d_flags, 256) != hipSuccess) {
+        if (ctx->c.own_stream) hipStreamDestroy(ctx->c.stream);
+        delete ctx;
+        return START_ENOMEM;
+    }
+    hipMemset(ctx->c.d_flags, 0, 256);
+    *out = ctx;
+    return START_OK;
+}
+
+void start_ctx_destroy(start_ctx *ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->c.device);
+    hipStreamSynchronize(ctx->c.stream);
+    dfree(&ctx->c, ctx->c.scratch, ctx->c.scratch_bytes);
+    for (hipEvent_t ev : ctx->c.ev_pool) hipEventDestroy(ev);
+    hipFree(ctx->c.d_flags);
+    if (ctx->c.own_stream) hipStreamDestroy(ctx->c.stream);
+    delete ctx;
+}
+
+const char *start_last_error(const start_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "no context"; }
+
+size_t start_bytes_in_use(const start_ctx *ctx) { return ctx ? ctx->c.in_use : 0; }
+
+start_status start_synchronize(start_ctx *ctx)
+{
+    if (!ctx) return START_EINVAL;
+    hipSetDevice(ctx->c.device);
+    hipError_t e = hipStreamSynchronize(ctx->c.stream);
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    unsigned flags = 0;
+    e = hipMemcpy(&flags, ctx->c.d_flags, sizeof(unsigned), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    if (!flags) return START_OK;
+    hipMemset(ctx->c.d_flags, 0, sizeof(unsigned));
+    if (flags & kFlagNonFinite) return fail(ctx, START_ENONFINITE, "non-finite target position");
+    if (flags & kFlagOutOfBox) return fail(ctx, START_EOUTOFBOX, "target outside the box");
+    return fail(ctx, START_EINVAL, "self_src index out of range");
+}
+
+start_status start_build_source_tree(start_ctx *ctx, const start_box *box, int64_t n_s, const double *src_xyz,
+                                     const double *src_lum, start_tree **out)
+{
+    if (!ctx || !out) return START_EINVAL;
+    *out = nullptr;
+    start_status st = check_box(ctx, box);
+    if (st) return st;
+    if (n_s < 0) return fail(ctx, START_EINVAL, "n_s < 0");
+    if (n_s > ((int64_t)1 << 30)) return fail(ctx, START_EINVAL, "n_s too large");
+    if (n_s > 0 && (!src_xyz || !src_lum)) return fail(ctx, START_EINVAL, "source arrays are NULL");
+    hipSetDevice(ctx->c.device);
+    // the flags word is shared with asynchronous rate calls: report theirs first
+    st = start_synchronize(ctx);
+    if (st) return st;
+    start_tree *t = new (std::nothrow) start_tree;
+    if (!t) return START_ENOMEM;
+    st = build_tree(&ctx->c, *box, n_s, src_xyz, src_lum, &t->t);
+    if (st == START_ENOMEM && ctx->c.budget) st = START_EBUDGET;
+    if (st) {
+        if (ctx->c.err.empty()) ctx->c.err = "tree build failed";
+        delete t;
+        return st;
+    }
+    make_fp32_tree(&t->t, ctx->c.stream);
+    hipError_t e = hipStreamSynchronize(ctx->c.stream);
+    if (e != hipSuccess) {
+        start_tree_free(ctx, t);
+        return fail(ctx, START_EHIP, hipGetErrorString(e));
+    }
+    *out = t;
+    return START_OK;
+}
+
+start_status start_tree_free(start_ctx *ctx, start_tree *tree)
+{
+    if (!ctx) return START_EINVAL;
+    if (!tree) return START_OK;
+    hipSetDevice(ctx->c.device);
+    hipStreamSynchronize(ctx->c.stream);
+    // all persistent arrays live in one allocation starting at keys
+    dfree(&ctx->c, tree->t.keys, tree->t.bytes);
+    delete tree;
+    return START_OK;
+}
+
+start_status start_build_gas_grid(start_ctx *ctx, const start_box *box, int64_t n_gas, const double *gas_xyz,
+                                  const double *gas_h, const double *gas_nhi, int grid_log2, start_grid **out)
+{
+    if (!ctx || !out) return START_EINVAL;
+    *out = nullptr;
+    start_status st = check_box(ctx, box);
+    if (st) return st;
+    if (n_gas < 0) return fail(ctx, START_EINVAL, "n_gas < 0");
+    if (n_gas > ((int64_t)1 << 31) - 1) return fail(ctx, START_EINVAL, "n_gas too large");
+    if (n_gas > 0 && (!gas_xyz || !gas_h || !gas_nhi)) return fail(ctx, START_EINVAL, "gas arrays are NULL");
+    if (grid_log2 == 0) {
+        grid_log2 = 1;
+        while (grid_log2 < 10 && (double)(1 << grid_log2) < std::cbrt((double)n_gas) - 1e-9) ++grid_log2;
+    }
+    if (grid_log2 < 1 || grid_log2 > 10) return fail(ctx, START_EINVAL, "grid_log2 must be in [1, 10]");
+    hipSetDevice(ctx->c.device);
+    st = start_synchronize(ctx);
+    if (st) return st;
+    start_grid *g = new (std::nothrow) start_grid;
+    if (!g) return START_ENOMEM;
+    st = build_grid(&ctx->c, *box, n_gas, gas_xyz, gas_h, gas_nhi, grid_log2, &g->g);
+    if (st == START_ENOMEM && ctx->c.budget) st = START_EBUDGET;
+    if (st) {
+        if (ctx->c.err.empty()) ctx->c.err = "grid build failed";
+        delete g;
+        return st;
+    }
+    *out = g;
+    return START_OK;
+}
+
+start_status start_grid_free(start_ctx *ctx, start_grid *grid)
+{
+    if (!ctx) return START_EINVAL;
+    if (!grid) return START_OK;
+    hipSetDevice(ctx->c.device);
+    hipStreamSynchronize(ctx->c.stream);
+    dfree(&ctx->c, grid->g.val, grid->g.bytes);
+    delete grid;
+    return START_OK;
+}
+
+int start_grid_size(const start_grid *grid) { return grid ? grid->g.G : 0; }
+
+start_status start_compute_rates(start_ctx *ctx, const start_tree *tree, const start_grid *grid, int64_t n_t,
+                                 const double *tgt_xyz, const int64_t *self_src, double theta_crit,
+                                 double sigma_cm2, start_precision prec, void *gamma_out)
+{
+    start_status st = check_rate_args(ctx, tree, grid, n_t, tgt_xyz, theta_crit, sigma_cm2, prec, true);
+    if (st) return st;
+    if (n_t == 0) return START_OK;
+    if (!gamma_out) return fail(ctx, START_EINVAL, "gamma_out is NULL");
+    hipSetDevice(ctx->c.device);
+    st = ensure_scratch(ctx, target_scratch_bytes(n_t));
+    if (st) return st;
+    hipStream_t s = ctx->c.stream;
+    prepare_targets(&ctx->c, tree->t.box, n_t, tgt_xyz, self_src, tree->t.n_src, ctx->c.scratch, s);
+    hipEvent_t ev1 = nullptr;
+    if (ctx->c.profile) {
+        Ctx &c = ctx->c;
+        if (c.ev_used + 2 > c.ev_pool.size()) {
+            hipEvent_t a = nullptr, b = nullptr;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+                return fail(ctx, START_EHIP, "hipEventCreate failed");
+            c.ev_pool.push_back(a);
+            c.ev_pool.push_back(b);
+        }
+        hipEventRecord(c.ev_pool[c.ev_used], s);
+        ev1 = c.ev_pool[c.ev_used + 1];
+        c.ev_used += 2;
+    }
+    launch_rates(&tree->t, &grid->g, n_t, ctx->c.scratch, self_src, theta_crit, sigma_cm2, prec, gamma_out, s);
+    if (ev1) hipEventRecord(ev1, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    return START_OK;
+}
+
+start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const start_item *items)
+{
+    if (!ctx) return START_EINVAL;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, START_EINVAL, "bad item array");
+    for (int i = 0; i < n_items; ++i) {
+        const start_item &it = items[i];
+        start_status st = check_rate_args(ctx, it.tree, it.grid, it.n_t, it.tgt_xyz, it.theta_crit, it.sigma_cm2,
+                                          it.prec, true);
+        if (st) return st;
+        if (it.n_t > 0 && !it.gamma_out) return fail(ctx, START_EINVAL, "gamma_out is NULL");
+    }
+    for (int i = 0; i < n_items; ++i) {
+        const start_item &it = items[i];
+        start_status st = start_compute_rates(ctx, it.tree, it.grid, it.n_t, it.tgt_xyz, it.self_src, it.theta_crit,
+                                              it.sigma_cm2, it.prec, it.gamma_out);
+        if (st) return st;
+    }
+    return START_OK;
+}
+
+size_t start_estimate_bytes(int64_t n_t, int64_t n_s, int64_t n_gas, int grid_log2, start_precision prec)
+{
+    (void)prec;
+    if (n_t < 0 || n_s < 0 || n_gas < 0 || grid_log2 < 0 || grid_log2 > 10) return 0;
+    const size_t G3 = (size_t)1 << (3 * grid_log2);
+    // tree: persistent (keys, perm, sources, 2 n_s nodes) + build temporaries
+    const size_t tree = (size_t)n_s * (8 + 4 + 32 + 16) + (size_t)2 * n_s * (16 + 16 + 32 + 16) +
+                        radix_temp_bytes(2 * n_s) + (size_t)n_s * 48 + (size_t)2 * n_s * 44 + 65536;
+    const size_t grid = G3 * 12 + (size_t)n_gas * 56 + radix_temp_bytes(n_gas) + G3 * 4 + 65536;
+    const size_t rates = (target_scratch_bytes(n_t) * 5) / 4 + 65536;
+    return tree + grid + rates;
+}
+
+start_status start_tree_export(start_ctx *ctx, const start_tree *tree, int64_t *n_nodes, uint64_t *keys_sorted,
+                               uint32_t *perm, int32_t *node_geo, int32_t *node_link, double *node_mom)
+{
+    if (!ctx || !tree) return START_EINVAL;
+    hipSetDevice(ctx->c.device);
+    hipStreamSynchronize(ctx->c.stream);
+    const Tree &t = tree->t;
+    if (n_nodes) *n_nodes = t.n_nodes;
+    const size_t m = (size_t)t.n_nodes, n = (size_t)t.n_src;
+    hipError_t e = hipSuccess;
+    if (keys_sorted && n) e = hipMemcpy(keys_sorted, t.keys, n * sizeof(uint64_t), hipMemcpyDefault);
+    if (e == hipSuccess && perm && n) e = hipMemcpy(perm, t.perm, n * sizeof(unsigned), hipMemcpyDefault);
+    if (e == hipSuccess && node_geo && m) e = hipMemcpy(node_geo, t.geo, m * sizeof(int4), hipMemcpyDefault);
+    if (e == hipSuccess && node_mom && m) e = hipMemcpy(node_mom, t.mom, m * sizeof(double4), hipMemcpyDefault);
+    if (e == hipSuccess && node_link && m) {
+        std::vector<int> a(m), b(m), c(m), d(m);
+        std::vector<int32_t> link(4 * m);
+        e = hipMemcpy(a.data(), t.skip, m * sizeof(int), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(b.data(), t.first, m * sizeof(int), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(c.data(), t.count, m * sizeof(int), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(d.data(), t.ref, m * sizeof(int), hipMemcpyDeviceToHost);
+        for (size_t i = 0; i < m; ++i) {
+            link[4 * i] = a[i];
+            link[4 * i + 1] = b[i];
+            link[4 * i + 2] = c[i];
+            link[4 * i + 3] = d[i];
+        }
+        if (e == hipSuccess) e = hipMemcpy(node_link, link.data(), 4 * m * sizeof(int32_t), hipMemcpyDefault);
+    }
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    return START_OK;
+}
+
+start_status start_interaction_lists(start_ctx *ctx, const start_tree *tree, int64_t n_t, const double *tgt_xyz,
+                                     const int64_t *self_src, double theta_crit, int64_t *offsets,
+                                     int64_t *entries, int64_t capacity)
+{
+    start_status st = check_rate_args(ctx, tree, nullptr, n_t, tgt_xyz, theta_crit, 0.0, START_FP64, false);
+    if (st) return st;
+    if (!offsets) return fail(ctx, START_EINVAL, "offsets is NULL");
+    hipSetDevice(ctx->c.device);
+    std::vector<int64_t> off((size_t)n_t + 1, 0);
+    if (n_t == 0) {
+        hipError_t e = hipMemcpy(offsets, off.data(), sizeof(int64_t), hipMemcpyDefault);
+        return e == hipSuccess ? START_OK : fail(ctx, START_EHIP, hipGetErrorString(e));
+    }
+    st = ensure_scratch(ctx, target_scratch_bytes(n_t));
+    if (st) return st;
+    hipStream_t s = ctx->c.stream;
+    int64_t *d_counts = nullptr;
+    if (dmalloc(&ctx->c, (void **)&d_counts, (size_t)(n_t + 1) * sizeof(int64_t)) != hipSuccess)
+        return fail(ctx, START_ENOMEM, "device allocation failed");
+    prepare_targets(&ctx->c, tree->t.box, n_t, tgt_xyz, self_src, tree->t.n_src, ctx->c.scratch, s);
+    launch_counts(&tree->t, n_t, ctx->c.scratch, self_src, theta_crit, d_counts, s);
+    st = start_synchronize(ctx);
+    if (st) {
+        dfree(&ctx->c, d_counts, (size_t)(n_t + 1) * sizeof(int64_t));
+        return st;
+    }
+    hipMemcpy(off.data() + 1, d_counts, (size_t)n_t * sizeof(int64_t), hipMemcpyDeviceToHost);
+    for (int64_t i = 0; i < n_t; ++i) off[i + 1] += off[i];
+    hipError_t e = hipMemcpy(offsets, off.data(), (size_t)(n_t + 1) * sizeof(int64_t), hipMemcpyDefault);
+    if (e != hipSuccess || off[n_t] > capacity || !entries) {
+        dfree(&ctx->c, d_counts, (size_t)(n_t + 1) * sizeof(int64_t));
+        if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+        return fail(ctx, START_ECAPACITY, "entries capacity too small");
+    }
+    // offsets to the device, then the lists straight into a device staging buffer
+    hipMemcpy(d_counts, off.data(), (size_t)(n_t + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    int64_t *d_ent = nullptr;
+    const size_t ent_bytes = (size_t)(off[n_t] > 0 ? off[n_t] : 1) * sizeof(int64_t);
+    if (dmalloc(&ctx->c, (void **)&d_ent, ent_bytes) != hipSuccess) {
+        dfree(&ctx->c, d_counts, (size_t)(n_t + 1) * sizeof(int64_t));
+        return fail(ctx, START_ENOMEM, "device allocation failed");
+    }
+    launch_lists(&tree->t, n_t, ctx->c.scratch, self_src, theta_crit, d_counts, d_ent, s);
+    e = hipStreamSynchronize(s);
+    if (e == hipSuccess && off[n_t] > 0)
+        e = hipMemcpy(entries, d_ent, (size_t)off[n_t] * sizeof(int64_t), hipMemcpyDefault);
+    dfree(&ctx->c, d_ent, ent_bytes);
+    dfree(&ctx->c, d_counts, (size_t)(n_t + 1) * sizeof(int64_t));
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    return START_OK;
+}
+
+start_status start_grid_export(start_ctx *ctx, const start_grid *grid, double *values)
+{
+    if (!ctx || !grid || !values) return START_EINVAL;
+    hipSetDevice(ctx->c.device);
+    hipStreamSynchronize(ctx->c.stream);
+    const size_t n = (size_t)grid->g.G * grid->g.G * grid->g.G;
+    hipError_t e = hipMemcpy(values, grid->g.val, n * sizeof(double), hipMemcpyDefault);
+    return e == hipSuccess ? START_OK : fail(ctx, START_EHIP, hipGetErrorString(e));
+}
+
+start_status start_rate_counters(start_ctx *ctx, const start_tree *tree, const start_grid *grid, int64_t n_t,
+                                 const double *tgt_xyz, const int64_t *self_src, double theta_crit,
+                                 start_precision prec, int64_t *counters)
+{
+    start_status st = check_rate_args(ctx, tree, grid, n_t, tgt_xyz, theta_crit, 0.0, prec, true);
+    if (st) return st;
+    if (n_t == 0) return START_OK;
+    if (!counters) return fail(ctx, START_EINVAL, "counters is NULL");
+    hipSetDevice(ctx->c.device);
+    st = ensure_scratch(ctx, target_scratch_bytes(n_t));
+    if (st) return st;
+    hipStream_t s = ctx->c.stream;
+    int64_t *d_stats = nullptr;
+    const size_t bytes = (size_t)n_t * 4 * sizeof(int64_t);
+    if (dmalloc(&ctx->c, (void **)&d_stats, bytes) != hipSuccess) return fail(ctx, START_ENOMEM, "allocation failed");
+    prepare_targets(&ctx->c, tree->t.box, n_t, tgt_xyz, self_src, tree->t.n_src, ctx->c.scratch, s);
+    launch_stats(&tree->t, &grid->g, n_t, ctx->c.scratch, self_src, theta_crit, prec, d_stats, s);
+    st = start_synchronize(ctx);
+    hipError_t e = hipSuccess;
+    if (!st) e = hipMemcpy(counters, d_stats, bytes, hipMemcpyDefault);
+    dfree(&ctx->c, d_stats, bytes);
+    if (st) return st;
+    return e == hipSuccess ? START_OK : fail(ctx, START_EHIP, hipGetErrorString(e));
+}
+
+start_status start_profile_enable(start_ctx *ctx, int enable)
+{
+    if (!ctx) return START_EINVAL;
+    ctx->c.profile = enable != 0;
+    return START_OK;
+}
+
+start_status start_profile_read(start_ctx *ctx, int64_t *launches, double *total_ms, double *max_ms)
+{
+    if (!ctx) return START_EINVAL;
+    Ctx &c = ctx->c;
+    hipSetDevice(c.device);
+    hipError_t e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    double tot = 0.0, mx = 0.0;
+    for (size_t i = 0; i + 1 < c.ev_used; i += 2) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, c.ev_pool[i], c.ev_pool[i + 1]);
+        if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+        tot += ms;
+        mx = ms > mx ? ms : mx;
+    }
+    if (launches) *launches = (int64_t)(c.ev_used / 2);
+    if (total_ms) *total_ms = tot;
+    if (max_ms) *max_ms = mx;
+    c.ev_used = 0;
+    return START_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal declarations of libstart (HIP, gfx950).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/start.h"
+
+namespace start {
+
+constexpr int kMaxLevel = 21;            // 63-bit Morton keys: 21 levels below the root
+constexpr int kKindInternal = 0;         // cell that splits into >= 2 sub-cubes
+constexpr int kKindBucket = 1;           // level-21 cell with >= 2 coincident sources
+constexpr int kKindLeaf = 2;             // single source
+
+// Error flags raised by validation kernels (bit set in a device word).
+constexpr unsigned kFlagNonFinite = 1u;
+constexpr unsigned kFlagOutOfBox = 2u;
+constexpr unsigned kFlagNegative = 4u;
+constexpr unsigned kFlagBadSelf = 8u;
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;        // 0 = unlimited
+    size_t in_use = 0;
+    unsigned *d_flags = nullptr;   // sticky validation flags (device)
+    std::string err;
+    // scratch reused by compute_rates (grown on demand)
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    // walk-kernel timing (start_profile_enable)
+    bool profile = false;
+    std::vector<hipEvent_t> ev_pool;   // pairs (start, stop)
+    size_t ev_used = 0;
+};
+
+// Device-resident octree in depth-first (Morton) order.  Arrays of n_nodes.
+struct Tree {
+    start_box box;
+    int64_t n_src = 0;
+    int64_t n_nodes = 0;
+    int4 *geo = nullptr;       // (cx, cy, cz, level | kind << 8)
+    int *skip = nullptr;       // index of the first node after the subtree
+    int *first = nullptr;      // range of the cell in sorted source order
+    int *count = nullptr;
+    int *ref = nullptr;        // leaf: original source index
+    double4 *mom = nullptr;    // (centre of luminosity x, y, z; luminosity)
+    float4 *momf = nullptr;    // FP32 copy: centre in grid units, L / lum_ref
+    double lum_ref = 1.0;      // scale of momf.w and srcf.w
+    uint64_t *keys = nullptr;  // sorted source keys
+    unsigned *perm = nullptr;  // sorted position -> original source index
+    double4 *src = nullptr;    // sorted sources (x, y, z, L)
+    float4 *srcf = nullptr;    // FP32 copy for buckets (grid units, L / lum_ref)
+    int grid_log2_f = -1;      // grid resolution momf/srcf were scaled for
+    size_t bytes = 0;
+    Ctx *ctx = nullptr;
+};
+
+struct Grid {
+    start_box box;
+    int grid_log2 = 0;
+    int G = 1;
+    double *val = nullptr;     // G^3 values, linear (ix*G + iy)*G + iz
+    float *valf = nullptr;     // FP32 copy
+    size_t bytes = 0;
+};
+
+// ---- memory helpers (count against the context budget) ----
+hipError_t dmalloc(Ctx *c, void **p, size_t bytes);
+void dfree(Ctx *c, void *p, size_t bytes);
+
+// ---- primitives (sort.hip) ----
+// Exclusive scan of n unsigned ints in place; returns total through *d_total
+// when non-null (device pointer).  temp must hold scan_temp_bytes(n).
+size_t scan_temp_bytes(int64_t n);
+void exclusive_scan_u32(unsigned *d_data, int64_t n, void *temp, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
+// keys.  Buffers are ping-ponged; the result ends in keys/vals.
+size_t radix_temp_bytes(int64_t n);
+void radix_sort_pairs(uint64_t *keys, unsigned *vals, int64_t n, int bits, void *temp,
+                      hipStream_t s);
+
+// ---- Morton keys (tree.hip) ----
+void launch_keys(const start_box &box, int64_t n, const double *xyz, const double *lum,
+                 uint64_t *keys, unsigned *idx, unsigned *flags, hipStream_t s);
+
+}  // namespace start
