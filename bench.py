@@ -226,7 +226,7 @@ def main():
     ach = alg[prec] / (kern[prec]["avg_ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(args.workload, prec, sha),
-                "kernel": "walk_kernel<FP32C> (tree walk + ray march + Gamma)",
+                "kernel": "rates_kernel<FP32C> (tree walk + ray march + Gamma)",
                 "algorithmic_bytes_per_launch": alg[prec], "kernel_avg_ms": round(kern[prec]["avg_ms"], 4)}
     ach64 = alg["fp64"] / (kern["fp64"]["avg_ms"] * 1e-3) / 1e9
 

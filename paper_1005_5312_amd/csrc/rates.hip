@@ -23,6 +23,7 @@
 #include "internal.h"
 
 #include <cstring>
+#include <type_traits>
 
 namespace start {
 
@@ -96,242 +97,139 @@ __device__ inline bool accept(const int4 g, const double u[3], double theta2)
 
 __device__ inline int clampi(int v, int G) { return v < 0 ? 0 : (v >= G ? G - 1 : v); }
 
-// Exact column of the piecewise-constant field from a to b (FP64 grid units),
-// stepping cell to cell; returns sum n_c dt with t in [0, 1].
-__device__ inline double column_fp64(const double *grid, int G, const double A[3], const double B[3],
-                                     int &ncell)
+// Orders LDS traffic between the lanes of one wavefront (no block barrier:
+// the waves of a block are independent).
+__device__ inline void wave_sync()
 {
-    int cell[3], step[3];
-    double tn[3], dt[3];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint64_t uniform64(uint64_t v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline int lanes_below(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// ---------------------------------------------------------------------------
+// Ray march through the piecewise-constant grid, from the target (t = 0) to
+// the source (t = 1).  The target is given as its cell (bi, linear index)
+// and the fraction fb inside it, so the crossings next to the target -- where
+// a dense target cell makes errors count -- are resolved to the precision of
+// fb.  The parameter of the next plane on each axis is recomputed from the
+// plane index as t = o * inv + nfb (o = plane offset from the target cell,
+// nfb = -fb * inv), never accumulated.  The cell index moves by the linear
+// stride of the axis crossed.  Returns sum n_c * dt (t in [0, 1]).
+// ---------------------------------------------------------------------------
+template <typename T, bool STATS>
+__device__ inline T march(const T *__restrict__ grid, int G, int ncell_m1, const int bi[3], int idx0,
+                          const T fb[3], const T D[3], int &ncell)
+{
+    const int stride[3] = {G * G, G, 1};
+    T inv[3], nfb[3], o[3], os[3], tn[3];
+    int ds[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double D = B[k] - A[k];
-        cell[k] = clampi((int)floor(A[k]), G);
-        if (D > 0.0) {
-            const double inv = 1.0 / D;
-            step[k] = 1;
-            tn[k] = ((double)(cell[k] + 1) - A[k]) * inv;
-            dt[k] = inv;
-        } else if (D < 0.0) {
-            const double inv = 1.0 / D;
-            step[k] = -1;
-            tn[k] = ((double)cell[k] - A[k]) * inv;
-            dt[k] = -inv;
+        if (D[k] > T(0)) {
+            inv[k] = T(1) / D[k];
+            o[k] = T(1);
+            os[k] = T(1);
+            ds[k] = stride[k];
+            nfb[k] = -fb[k] * inv[k];
+        } else if (D[k] < T(0)) {
+            inv[k] = T(1) / D[k];
+            o[k] = T(0);
+            os[k] = T(-1);
+            ds[k] = -stride[k];
+            nfb[k] = -fb[k] * inv[k];
         } else {
-            step[k] = 0;
-            tn[k] = 2.0;
-            dt[k] = 0.0;
+            inv[k] = T(0);
+            o[k] = T(0);
+            os[k] = T(0);
+            ds[k] = 0;
+            nfb[k] = T(2);   // never crossed
         }
+        tn[k] = fma(o[k], inv[k], nfb[k]);
     }
-    double t = 0.0, sum = 0.0;
+    (void)bi;
+    int idx = idx0;
+    T t = T(0), sum = T(0), comp = T(0);
+    T v = grid[idx];
     const int max_steps = 3 * G + 3;
     for (int it = 0; it < max_steps; ++it) {
-        double tm = fmin(fmin(tn[0], tn[1]), tn[2]);
-        const bool last = !(tm < 1.0);
-        if (last) tm = 1.0;
-        const double len = tm - t;
-        if (len > 0.0) {
-            sum += grid[((int64_t)cell[0] * G + cell[1]) * G + cell[2]] * len;
-            ++ncell;
+        const T m = fmin(fmin(tn[0], tn[1]), tn[2]);
+        const T e = fmin(m, T(1));
+        const bool bx = tn[0] == m;
+        const bool by = !bx && tn[1] == m;
+        const bool bz = !bx && !by;
+        int nidx = idx + (bx ? ds[0] : (by ? ds[1] : ds[2]));
+        nidx = nidx < 0 ? 0 : (nidx > ncell_m1 ? ncell_m1 : nidx);
+        const T vn = grid[nidx];            // next cell, loaded one step ahead
+        const T len = e - t;
+        if (sizeof(T) == 4) {
+            // Kahan-compensated FP32 sum
+            const T y = fma(v, len, -comp);
+            const T s2 = sum + y;
+            comp = (s2 - sum) - y;
+            sum = s2;
+        } else {
+            sum = fma(v, len, sum);
         }
-        if (last) break;
-        t = tm;
-        int a = (tn[0] <= tn[1] && tn[0] <= tn[2]) ? 0 : (tn[1] <= tn[2] ? 1 : 2);
-        cell[a] = clampi(cell[a] + step[a], G);
-        tn[a] += dt[a];
+        if (STATS) ncell += len > T(0) ? 1 : 0;
+        if (!(m < T(1))) break;
+        t = m;
+        idx = nidx;
+        v = vn;
+        o[0] += bx ? os[0] : T(0);
+        o[1] += by ? os[1] : T(0);
+        o[2] += bz ? os[2] : T(0);
+        tn[0] = fma(o[0], inv[0], nfb[0]);
+        tn[1] = fma(o[1], inv[1], nfb[1]);
+        tn[2] = fma(o[2], inv[2], nfb[2]);
     }
     return sum;
 }
 
-struct Acc64 {
-    double g = 0.0;
-};
-
-// FP64 contribution of a (virtual) source at physical position s with
-// luminosity L to the target at x.
-__device__ inline void contribute_fp64(const Params &P, const double x[3], const double B[3], double sx,
-                                       double sy, double sz, double L, Acc64 &acc, int64_t *st)
-{
-    const double dx = x[0] - sx, dy = x[1] - sy, dz = x[2] - sz;
-    const double dist = sqrt(dx * dx + dy * dy + dz * dz);
-    if (dist == 0.0) {
-        if (st) st[3]++;
-        return;
-    }
-    const double A[3] = {(sx - P.lo[0]) * P.gs, (sy - P.lo[1]) * P.gs, (sz - P.lo[2]) * P.gs};
-    int nc = 0;
-    const double col = column_fp64(P.grid, P.G, A, B, nc) * dist;
-    if (st) st[2] += nc;
-    const double tau = P.sigma * col * P.unit_cm;
-    const double dcm = dist * P.unit_cm;
-    acc.g += L * exp(-tau) / (dcm * dcm);
-}
-
-// FP32: the ray is marched from the target (origin, t = 0) to the source
-// (t = 1), so the crossings nearest the target -- where the target's own cell
-// may be dense -- carry the smallest absolute error.  Crossing parameters come
-// from the plane index each time, never by accumulation.
-struct Acc32 {
-    float g = 0.f, gc = 0.f;   // Kahan sum of L' e^-tau / d^2
-};
-
-__device__ inline void contribute_fp32(const Params &P, const int bi[3], const float fb[3], float4 s,
-                                       Acc32 &acc, int64_t *st)
-{
-    const float Gf = (float)P.G;
-    int ai[3];
-    float D[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const float* sp = &s.x;
-        const float A = sp[k] * Gf;                 // exact: G is a power of two
-        const float fl = floorf(A);
-        ai[k] = (int)fl;
-        const float fa = A - fl;                     // exact
-        D[k] = (float)(ai[k] - bi[k]) + (fa - fb[k]);
-    }
-    const float d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
-    if (d2 == 0.f) {
-        if (st) st[3]++;
-        return;
-    }
-    int cell[3], step[3], plane[3];
-    float inv[3], tn[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        cell[k] = clampi(bi[k], P.G);
-        if (D[k] > 0.f) {
-            step[k] = 1;
-            plane[k] = bi[k] + 1;
-            inv[k] = 1.0f / D[k];
-            tn[k] = ((float)(plane[k] - bi[k]) - fb[k]) * inv[k];
-        } else if (D[k] < 0.f) {
-            step[k] = -1;
-            plane[k] = bi[k];
-            inv[k] = 1.0f / D[k];
-            tn[k] = ((float)(plane[k] - bi[k]) - fb[k]) * inv[k];
-        } else {
-            step[k] = 0;
-            plane[k] = 0;
-            inv[k] = 0.f;
-            tn[k] = 2.f;
-        }
-    }
-    float t = 0.f, sum = 0.f, comp = 0.f;
-    const int max_steps = 3 * P.G + 3;
-    int nc = 0;
-    for (int it = 0; it < max_steps; ++it) {
-        float tm = fminf(fminf(tn[0], tn[1]), tn[2]);
-        const bool last = !(tm < 1.f);
-        if (last) tm = 1.f;
-        const float len = tm - t;
-        if (len > 0.f) {
-            const float v = P.gridf[((int64_t)cell[0] * P.G + cell[1]) * P.G + cell[2]];
-            const float y = fmaf(v, len, -comp);
-            const float tt = sum + y;
-            comp = (tt - sum) - y;
-            sum = tt;
-            ++nc;
-        }
-        if (last) break;
-        t = tm;
-        const int a = (tn[0] <= tn[1] && tn[0] <= tn[2]) ? 0 : (tn[1] <= tn[2] ? 1 : 2);
-        cell[a] = clampi(cell[a] + step[a], P.G);
-        plane[a] += step[a];
-        tn[a] = ((float)(plane[a] - bi[a]) - fb[a]) * inv[a];
-    }
-    if (st) st[2] += nc;
-    const float dist = sqrtf(d2);                    // grid units
-    const float tau = (float)(P.sigma * P.cell_cm) * (sum * dist);
-    const float term = s.w * expf(-tau) / d2;
-    const float y = term - acc.gc;
-    const float tt = acc.g + y;
-    acc.gc = (tt - acc.g) - y;
-    acc.g = tt;
-}
-
-template <int PREC, int MODE>
-__global__ void __launch_bounds__(kThreads) walk_kernel(Params P)
+// ---------------------------------------------------------------------------
+// Walk used by the list export (entries only, no march).
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ void __launch_bounds__(kThreads) list_kernel(Params P)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t it = tile * kWave + lane;
     const bool valid = it < P.n_t;
-    if (tile * kWave >= P.n_t) return;   // whole wave past the end
-
-    double x[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0};
-    int bi[3] = {0, 0, 0};
-    float fb[3] = {0.f, 0.f, 0.f};
+    if (tile * kWave >= P.n_t) return;
+    double u[3] = {0.0, 0.0, 0.0};
     unsigned orig = 0;
     int64_t self = -1;
     if (valid) {
         const double4 p = P.tgt[it];
-        x[0] = p.x;
-        x[1] = p.y;
-        x[2] = p.z;
+        const double x[3] = {p.x, p.y, p.z};
         orig = P.tgt_orig[it];
         if (P.self_src) self = P.self_src[orig];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const double v = (x[k] - P.lo[k]) * P.inv_size;
             u[k] = v > 1.0 ? 1.0 : (v < 0.0 ? 0.0 : v);
-            B[k] = (x[k] - P.lo[k]) * P.gs;
-            // cell of the target clamped to the grid (a target on the top
-            // face sits in the last cell at fraction 1)
-            bi[k] = clampi((int)floor(B[k]), P.G);
-            fb[k] = (float)(B[k] - (double)bi[k]);
         }
     }
-    Acc64 a64;
-    Acc32 a32;
-    int64_t stv[4] = {0, 0, 0, 0};
-    int64_t *st = MODE == kStats ? stv : nullptr;
     int64_t n_entries = 0;
-    int64_t out_base = 0;
-    if (MODE == kList && valid) out_base = P.offsets[orig];
-
-    auto use = [&](int64_t code, double4 m64, float4 m32) {
-        // one interaction-list entry: code >= 0 node index, < 0 -(source)-1
-        if (MODE == kCount) {
-            ++n_entries;
-        } else if (MODE == kList) {
-            P.entries[out_base + n_entries] = code;
-            ++n_entries;
-        } else {
-            if (st) st[1]++;
-            if (PREC == START_FP64)
-                contribute_fp64(P, x, B, m64.x, m64.y, m64.z, m64.w, a64, st);
-            else
-                contribute_fp32(P, bi, fb, m32, a32, st);
-        }
+    const int64_t out_base = (MODE == kList && valid) ? P.offsets[orig] : 0;
+    auto emit = [&](int64_t code, double L) {
+        if (!(L > 0.0)) return;
+        if (MODE == kList) P.entries[out_base + n_entries] = code;
+        ++n_entries;
     };
-
-    // Entry filter: sources and cells of zero luminosity contribute nothing
-    // and are left out.  The FP32 rate path reads only the FP32 copy.
-    constexpr bool kFp32Rates = PREC == START_FP32C && MODE == kRates;
-    const double4 z64 = make_double4(0.0, 0.0, 0.0, 0.0);
-    const float4 z32 = make_float4(0.f, 0.f, 0.f, 0.f);
-    auto use_node = [&](int64_t code, int nd) {
-        if (kFp32Rates) {
-            const float4 mf = P.momf[nd];
-            if (mf.w > 0.f) use(code, z64, mf);
-        } else {
-            const double4 m = P.mom[nd];
-            if (m.w > 0.0) use(code, m, PREC == START_FP32C ? P.momf[nd] : z32);
-        }
-    };
-    auto use_src = [&](int64_t code, int q) {
-        if (kFp32Rates) {
-            const float4 mf = P.srcf[q];
-            if (mf.w > 0.f) use(code, z64, mf);
-        } else {
-            const double4 m = P.src[q];
-            if (m.w > 0.0) use(code, m, PREC == START_FP32C ? P.srcf[q] : z32);
-        }
-    };
-
-    int resume = 0;
-    int node = 0;
+    int resume = 0, node = 0;
     const int n_nodes = (int)P.n_nodes;
     while (node < n_nodes) {
         node = __builtin_amdgcn_readfirstlane(node);
@@ -339,30 +237,230 @@ __global__ void __launch_bounds__(kThreads) walk_kernel(Params P)
         const int kind = g.w >> 8;
         const bool active = valid && node >= resume;
         if (kind == kKindLeaf) {
-            if (active) {
-                const int j = P.ref[node];
-                if ((int64_t)j != self) use_node(-(int64_t)j - 1, node);
-            }
+            if (active && (int64_t)P.ref[node] != self) emit(-(int64_t)P.ref[node] - 1, P.mom[node].w);
             node += 1;
             continue;
         }
         const int sk = P.skip[node];
-        bool acc = false;
-        if (active) {
-            if (st) st[0]++;
-            acc = accept(g, u, P.theta2);
-        }
+        const bool acc = active && accept(g, u, P.theta2);
         if (acc) {
-            use_node(node, node);
+            emit(node, P.mom[node].w);
             resume = sk;
         }
         const bool open = active && !acc;
         if (kind == kKindBucket) {
-            if (open) {
+            if (open)
+                for (int q = P.first[node]; q < P.first[node] + P.count[node]; ++q)
+                    if ((int64_t)P.perm[q] != self) emit(-(int64_t)P.perm[q] - 1, P.src[q].w);
+            node += 1;
+            continue;
+        }
+        node = __any(open) ? node + 1 : sk;
+    }
+    if (valid) {
+        if (MODE == kCount) P.counts[orig] = n_entries;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rate kernel.  The wave walks as above, but an entry taken by a lane is not
+// marched at once: (entry, lane) items go to a per-wave ring in LDS in node
+// order, and as soon as 64 items are pending every lane marches one of them
+// -- whichever target it belongs to.  Items of one node share the source and
+// sit side by side, so a batch is 1-3 bundles of nearly parallel rays.  Each
+// node's items are recorded as (first slot, lane mask); after a batch every
+// lane picks its own terms out of the ring through these records, in node
+// order, and adds them to its Kahan (FP32) or plain (FP64) sum.  Results are
+// deterministic and every target sums its terms in depth-first order.
+// ---------------------------------------------------------------------------
+constexpr int kRing = 128;   // items; a node adds <= 64 and a batch drains 64
+
+template <typename T>
+struct WaveLds {
+    int code[kRing];          // node index, or -(sorted source index)-1
+    unsigned char lane[kRing];
+    T term[kRing];
+    int ncell[kRing];         // grid cells crossed (counter mode)
+    int rec_start[kRing];     // per node: first slot (absolute) of its items
+    uint64_t rec_mask[kRing]; // per node: lanes that took it
+    int4 tcell[kWave];        // target cell (bi0, bi1, bi2, linear index)
+    T tfrac[kWave][3];        // target fraction inside its cell
+};
+
+template <int PREC, bool STATS>
+__global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
+{
+    using T = typename std::conditional<PREC == START_FP64, double, float>::type;
+    __shared__ WaveLds<T> lds_all[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x >> 6;
+    WaveLds<T> &L = lds_all[wv];
+    // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+    // run of Morton-ordered tiles so that its L2 sees neighbouring targets
+    const int64_t nb = gridDim.x;
+    const int64_t per_xcd = nb / 8;
+    int64_t blk = blockIdx.x;
+    if (per_xcd > 0 && blk < per_xcd * 8) blk = (blk & 7) * per_xcd + (blk >> 3);
+    const int64_t tile = blk * kWavesPerBlock + wv;
+    const int64_t it = tile * kWave + lane;
+    const bool valid = it < P.n_t;
+    if (tile * kWave >= P.n_t) return;
+
+    const int G = P.G;
+    const int ncell_m1 = G * G * G - 1;
+    double u[3] = {0.0, 0.0, 0.0};
+    unsigned orig = 0;
+    int64_t self = -1;
+    {
+        int bi[3] = {0, 0, 0};
+        T fb[3] = {T(0), T(0), T(0)};
+        if (valid) {
+            const double4 p = P.tgt[it];
+            const double x[3] = {p.x, p.y, p.z};
+            orig = P.tgt_orig[it];
+            if (P.self_src) self = P.self_src[orig];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double v = (x[k] - P.lo[k]) * P.inv_size;
+                u[k] = v > 1.0 ? 1.0 : (v < 0.0 ? 0.0 : v);
+                const double B = (x[k] - P.lo[k]) * P.gs;
+                // a target on the top face sits in the last cell at fraction 1
+                bi[k] = clampi((int)floor(B), G);
+                fb[k] = (T)(B - (double)bi[k]);
+            }
+        }
+        L.tcell[lane] = make_int4(bi[0], bi[1], bi[2], (bi[0] * G + bi[1]) * G + bi[2]);
+        L.tfrac[lane][0] = fb[0];
+        L.tfrac[lane][1] = fb[1];
+        L.tfrac[lane][2] = fb[2];
+    }
+
+    T acc = T(0), accc = T(0);
+    int64_t st_test = 0, st_entries = 0, st_cells = 0, st_zero = 0;
+    int head = 0, tail = 0, rhead = 0, rtail = 0;   // wave-uniform ring counters
+    const T Gf = (T)G;
+    const T tau_scale = (T)(P.sigma * P.cell_cm);
+
+    // March the next (up to) 64 pending items and hand the terms back.
+    auto drain = [&]() {
+        const int nb_items = (tail - head) < kWave ? (tail - head) : kWave;
+        const int slot = (head + lane) & (kRing - 1);
+        T term = T(0);
+        int nc = 0;
+        if (lane < nb_items) {
+            const int code = L.code[slot];
+            const int tl = L.lane[slot];
+            const int4 tc = L.tcell[tl];
+            const T fb[3] = {L.tfrac[tl][0], L.tfrac[tl][1], L.tfrac[tl][2]};
+            const int bi[3] = {tc.x, tc.y, tc.z};
+            T D[3], w;
+            if (PREC == START_FP64) {
+                const double4 m = code >= 0 ? P.mom[code] : P.src[-code - 1];
+                const double A[3] = {(m.x - P.lo[0]) * P.gs, (m.y - P.lo[1]) * P.gs, (m.z - P.lo[2]) * P.gs};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) D[k] = (T)(A[k] - ((double)bi[k] + (double)fb[k]));
+                w = (T)m.w;
+            } else {
+                const float4 m = code >= 0 ? P.momf[code] : P.srcf[-code - 1];
+                const float a[3] = {m.x, m.y, m.z};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const float A = a[k] * (float)Gf;    // exact: G is a power of two
+                    const float fl = floorf(A);
+                    D[k] = (T)((float)((int)fl - bi[k]) + ((A - fl) - (float)fb[k]));
+                }
+                w = (T)m.w;
+            }
+            const T d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+            if (d2 > T(0)) {
+                const T col = march<T, STATS>(PREC == START_FP64 ? (const T *)P.grid : (const T *)P.gridf, G,
+                                              ncell_m1, bi, tc.w, fb, D, nc);
+                const T dist = sqrt(d2);                       // grid units
+                const T tau = tau_scale * (col * dist);
+                term = w * exp(-tau) / d2;
+            } else {
+                nc = -1;                                       // zero distance: skipped
+            }
+        }
+        L.term[slot] = term;
+        if (STATS) L.ncell[slot] = nc;
+        wave_sync();
+        const int end = head + nb_items;
+        while (rhead < rtail) {
+            const int rs = __builtin_amdgcn_readfirstlane(L.rec_start[rhead & (kRing - 1)]);
+            if (rs >= end) break;
+            const uint64_t m = uniform64(L.rec_mask[rhead & (kRing - 1)]);
+            if ((m >> lane) & 1ull) {
+                const int s = rs + lanes_below(m);
+                if (s >= head && s < end) {
+                    const T y = L.term[s & (kRing - 1)] - accc;
+                    const T t2 = acc + y;
+                    if (sizeof(T) == 4) accc = (t2 - acc) - y;
+                    acc = t2;
+                    if (STATS) {
+                        const int c = L.ncell[s & (kRing - 1)];
+                        if (c < 0) st_zero++;
+                        else st_cells += c;
+                    }
+                }
+            }
+            if (rs + __popcll(m) <= end) ++rhead;
+            else break;
+        }
+        head = end;
+        wave_sync();
+    };
+
+    // Queue the entry `code` for the lanes with want == true.
+    auto push = [&](bool want, int code) {
+        const uint64_t m = __ballot(want);
+        if (m == 0) return;
+        if (want) {
+            const int s = (tail + lanes_below(m)) & (kRing - 1);
+            L.code[s] = code;
+            L.lane[s] = (unsigned char)lane;
+            if (STATS) st_entries++;
+        }
+        if (lane == 0) {
+            L.rec_start[rtail & (kRing - 1)] = tail;
+            L.rec_mask[rtail & (kRing - 1)] = m;
+        }
+        ++rtail;
+        tail += __popcll(m);
+        wave_sync();
+        if (tail - head >= kWave) drain();
+    };
+
+    const bool fp32 = PREC == START_FP32C;
+    int resume = 0, node = 0;
+    const int n_nodes = (int)P.n_nodes;
+    while (node < n_nodes) {
+        node = __builtin_amdgcn_readfirstlane(node);
+        const int4 g = P.geo[node];
+        const int kind = g.w >> 8;
+        const bool active = valid && node >= resume;
+        if (kind == kKindLeaf) {
+            const float lw = fp32 ? P.momf[node].w : (float)(P.mom[node].w > 0.0);
+            push(active && (int64_t)P.ref[node] != self && lw > 0.f, node);
+            node += 1;
+            continue;
+        }
+        const int sk = P.skip[node];
+        bool acc_node = false;
+        if (active) {
+            if (STATS) st_test++;
+            acc_node = accept(g, u, P.theta2);
+        }
+        if (acc_node) resume = sk;
+        const float lw = fp32 ? P.momf[node].w : (float)(P.mom[node].w > 0.0);
+        push(acc_node && lw > 0.f, node);
+        const bool open = active && !acc_node;
+        if (kind == kKindBucket) {
+            if (__any(open)) {
                 const int f = P.first[node], cnt = P.count[node];
                 for (int q = f; q < f + cnt; ++q) {
-                    const int j = (int)P.perm[q];
-                    if ((int64_t)j != self) use_src(-(int64_t)j - 1, q);
+                    const float qw = fp32 ? P.srcf[q].w : (float)(P.src[q].w > 0.0);
+                    push(open && (int64_t)P.perm[q] != self && qw > 0.f, -q - 1);
                 }
             }
             node += 1;
@@ -370,23 +468,27 @@ __global__ void __launch_bounds__(kThreads) walk_kernel(Params P)
         }
         node = __any(open) ? node + 1 : sk;
     }
+    while (head < tail) drain();
 
     if (!valid) return;
-    if (MODE == kCount) {
-        P.counts[orig] = n_entries;
-    } else if (MODE == kStats) {
-        for (int k = 0; k < 4; ++k) P.stats[(int64_t)orig * 4 + k] = stv[k];
-    } else if (MODE == kRates) {
-        const double four_pi = 4.0 * M_PI;
-        if (PREC == START_FP64) {
-            static_cast<double *>(P.gamma)[orig] = P.sigma / four_pi * a64.g;
-        } else {
-            // L' = L / L_root and lengths in cells: restore units in FP64
-            const double L0 = P.n_nodes > 0 ? P.mom[0].w : 0.0;   // empty tree: no arrays
-            const double Lref = L0 > 0.0 ? L0 : 1.0;
-            const double sum = (double)a32.g - (double)a32.gc;
-            static_cast<float *>(P.gamma)[orig] = (float)(P.sigma / four_pi * sum * Lref / (P.cell_cm * P.cell_cm));
-        }
+    if (STATS) {
+        int64_t *o = P.stats + (int64_t)orig * 4;
+        o[0] = st_test;
+        o[1] = st_entries;
+        o[2] = st_cells;
+        o[3] = st_zero;
+        return;
+    }
+    const double four_pi = 4.0 * M_PI;
+    if (PREC == START_FP64) {
+        // terms are L / d^2 with d in cells: restore cm
+        static_cast<double *>(P.gamma)[orig] = P.sigma / four_pi * (double)acc / (P.cell_cm * P.cell_cm);
+    } else {
+        // L' = L / L_root and lengths in cells: restore units in FP64
+        const double L0 = P.n_nodes > 0 ? P.mom[0].w : 0.0;   // empty tree: no arrays
+        const double Lref = L0 > 0.0 ? L0 : 1.0;
+        const double sum = (double)acc - (double)accc;
+        static_cast<float *>(P.gamma)[orig] = (float)(P.sigma / four_pi * sum * Lref / (P.cell_cm * P.cell_cm));
     }
 }
 
@@ -527,7 +629,9 @@ static Params make_params(const Tree *t, const Grid *g, int64_t n_t, void *scrat
 static unsigned walk_blocks(int64_t n_t)
 {
     const int64_t tiles = (n_t + kWave - 1) / kWave;
-    return (unsigned)((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    int64_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks >= 64) blocks = (blocks + 7) / 8 * 8;   // whole rounds over the 8 XCDs
+    return (unsigned)blocks;
 }
 
 void launch_rates(const Tree *t, const Grid *g, int64_t n_t, void *scratch, const int64_t *self_src,
@@ -535,11 +639,10 @@ void launch_rates(const Tree *t, const Grid *g, int64_t n_t, void *scratch, cons
 {
     Params P = make_params(t, g, n_t, scratch, self_src, theta, sigma);
     P.gamma = gamma;
-    if (prec == START_FP64) {
-        walk_kernel<START_FP64, kRates><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
-    } else {
-        walk_kernel<START_FP32C, kRates><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
-    }
+    if (prec == START_FP64)
+        rates_kernel<START_FP64, false><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
+    else
+        rates_kernel<START_FP32C, false><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
 }
 
 void launch_counts(const Tree *t, int64_t n_t, void *scratch, const int64_t *self_src, double theta,
@@ -547,7 +650,7 @@ void launch_counts(const Tree *t, int64_t n_t, void *scratch, const int64_t *sel
 {
     Params P = make_params(t, nullptr, n_t, scratch, self_src, theta, 0.0);
     P.counts = counts;
-    walk_kernel<START_FP64, kCount><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
+    list_kernel<kCount><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
 }
 
 void launch_lists(const Tree *t, int64_t n_t, void *scratch, const int64_t *self_src, double theta,
@@ -556,7 +659,7 @@ void launch_lists(const Tree *t, int64_t n_t, void *scratch, const int64_t *self
     Params P = make_params(t, nullptr, n_t, scratch, self_src, theta, 0.0);
     P.offsets = offsets;
     P.entries = entries;
-    walk_kernel<START_FP64, kList><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
+    list_kernel<kList><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
 }
 
 void launch_stats(const Tree *t, const Grid *g, int64_t n_t, void *scratch, const int64_t *self_src,
@@ -565,9 +668,9 @@ void launch_stats(const Tree *t, const Grid *g, int64_t n_t, void *scratch, cons
     Params P = make_params(t, g, n_t, scratch, self_src, theta, 1.0);
     P.stats = stats;
     if (prec == START_FP64)
-        walk_kernel<START_FP64, kStats><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
+        rates_kernel<START_FP64, true><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
     else
-        walk_kernel<START_FP32C, kStats><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
+        rates_kernel<START_FP32C, true><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
 }
 
 }  // namespace start
