@@ -50,13 +50,12 @@ struct Tree {
     int *count = nullptr;
     int *ref = nullptr;        // leaf: original source index
     double4 *mom = nullptr;    // (centre of luminosity x, y, z; luminosity)
-    float4 *momf = nullptr;    // FP32 copy: centre in grid units, L / lum_ref
-    double lum_ref = 1.0;      // scale of momf.w and srcf.w
+    uint4 *momq = nullptr;     // FP32 path: centre as 32-bit fixed-point box
+                               // coordinates, L / L_root as float bits
     uint64_t *keys = nullptr;  // sorted source keys
     unsigned *perm = nullptr;  // sorted position -> original source index
     double4 *src = nullptr;    // sorted sources (x, y, z, L)
-    float4 *srcf = nullptr;    // FP32 copy for buckets (grid units, L / lum_ref)
-    int grid_log2_f = -1;      // grid resolution momf/srcf were scaled for
+    uint4 *srcq = nullptr;     // same for the sorted sources (bucket members)
     size_t bytes = 0;
     Ctx *ctx = nullptr;
 };

@@ -44,14 +44,16 @@ struct Params {
     const int *count;
     const int *ref;
     const double4 *mom;
-    const float4 *momf;
+    const uint4 *momq;
     const double4 *src;
-    const float4 *srcf;
+    const uint4 *srcq;
     const unsigned *perm;
     // grid
     const double *grid;
     const float *gridf;
     int G;
+    int grid_log2;
+    double frac_scale;  // 2^-(32 - grid_log2)
     double gs;          // G / size
     double lo[3];
     double inv_size;
@@ -121,78 +123,87 @@ __device__ inline int lanes_below(uint64_t m)
 // ---------------------------------------------------------------------------
 // Ray march through the piecewise-constant grid, from the target (t = 0) to
 // the source (t = 1).  The target is given as its cell (bi, linear index)
-// and the fraction fb inside it, so the crossings next to the target -- where
-// a dense target cell makes errors count -- are resolved to the precision of
-// fb.  The parameter of the next plane on each axis is recomputed from the
-// plane index as t = o * inv + nfb (o = plane offset from the target cell,
-// nfb = -fb * inv), never accumulated.  The cell index moves by the linear
-// stride of the axis crossed.  Returns sum n_c * dt (t in [0, 1]).
+// and its fraction fb inside the cell.  The geometry (direction D, plane
+// parameters) is FP64 in both precisions: an FP32 ray parameter resolves a
+// crossing only to ~6e-8 of the ray length (1e-5 cell over 128 cells), which
+// times the optical depth of a dense cell (~200 per cell for the 200x clumps)
+// is above the 2e-4 target.  The parameter of the next plane on each axis is
+// recomputed from the plane index as t = o * inv + nfb (o = plane offset from
+// the target cell, nfb = -fb * inv), never accumulated.  The cell index moves
+// by the linear stride of the axis crossed.  TV is the type of the grid values
+// and of the sum: FP32 with Kahan compensation, or FP64.  Returns sum n_c dt.
+//
+// The loop ends: each step moves one axis to its next plane, and o * inv then
+// grows by |inv| >= 1 / (2 G) (|D| is below 2G for points in the box), so tn
+// passes 1 after at most 2G + 2 steps per axis; a NaN parameter is never the
+// minimum (fmin) and an all-NaN state exits at once; max_steps also bounds it.
 // ---------------------------------------------------------------------------
-template <typename T, bool STATS>
-__device__ inline T march(const T *__restrict__ grid, int G, int ncell_m1, const int bi[3], int idx0,
-                          const T fb[3], const T D[3], int &ncell)
+template <typename TV, bool STATS>
+__device__ inline TV march(const TV *__restrict__ grid, int G, unsigned ncell_m1, unsigned idx0, const double fb[3],
+                           const double D[3], int &ncell)
 {
     const int stride[3] = {G * G, G, 1};
-    T inv[3], nfb[3], o[3], os[3], tn[3];
-    int ds[3];
+    double inv[3], nfb[3], tn[3];
+    int o[3], os[3], ds[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        if (D[k] > T(0)) {
-            inv[k] = T(1) / D[k];
-            o[k] = T(1);
-            os[k] = T(1);
+        if (D[k] > 0.0) {
+            inv[k] = 1.0 / D[k];
+            o[k] = 1;
+            os[k] = 1;
             ds[k] = stride[k];
             nfb[k] = -fb[k] * inv[k];
-        } else if (D[k] < T(0)) {
-            inv[k] = T(1) / D[k];
-            o[k] = T(0);
-            os[k] = T(-1);
+        } else if (D[k] < 0.0) {
+            inv[k] = 1.0 / D[k];
+            o[k] = 0;
+            os[k] = -1;
             ds[k] = -stride[k];
             nfb[k] = -fb[k] * inv[k];
         } else {
-            inv[k] = T(0);
-            o[k] = T(0);
-            os[k] = T(0);
+            inv[k] = 0.0;
+            o[k] = 0;
+            os[k] = 0;
             ds[k] = 0;
-            nfb[k] = T(2);   // never crossed
+            nfb[k] = 2.0;   // never crossed
         }
-        tn[k] = fma(o[k], inv[k], nfb[k]);
+        tn[k] = fma((double)o[k], inv[k], nfb[k]);
     }
-    (void)bi;
-    int idx = idx0;
-    T t = T(0), sum = T(0), comp = T(0);
-    T v = grid[idx];
+    unsigned idx = idx0;
+    double t = 0.0;
+    TV sum = TV(0), comp = TV(0);
+    const char *base = reinterpret_cast<const char *>(grid);
+    TV v = *reinterpret_cast<const TV *>(base + (size_t)idx * sizeof(TV));
     const int max_steps = 3 * G + 3;
     for (int it = 0; it < max_steps; ++it) {
-        const T m = fmin(fmin(tn[0], tn[1]), tn[2]);
-        const T e = fmin(m, T(1));
+        const double m = fmin(fmin(tn[0], tn[1]), tn[2]);
+        const double e = fmin(m, 1.0);
         const bool bx = tn[0] == m;
         const bool by = !bx && tn[1] == m;
         const bool bz = !bx && !by;
-        int nidx = idx + (bx ? ds[0] : (by ? ds[1] : ds[2]));
-        nidx = nidx < 0 ? 0 : (nidx > ncell_m1 ? ncell_m1 : nidx);
-        const T vn = grid[nidx];            // next cell, loaded one step ahead
-        const T len = e - t;
-        if (sizeof(T) == 4) {
+        unsigned nidx = idx + (unsigned)(bx ? ds[0] : (by ? ds[1] : ds[2]));
+        nidx = nidx > ncell_m1 ? ncell_m1 : nidx;   // also catches a step below 0
+        const TV vn = *reinterpret_cast<const TV *>(base + (size_t)nidx * sizeof(TV));
+        const TV len = (TV)(e - t);
+        if (sizeof(TV) == 4) {
             // Kahan-compensated FP32 sum
-            const T y = fma(v, len, -comp);
-            const T s2 = sum + y;
+            const TV y = fma(v, len, -comp);
+            const TV s2 = sum + y;
             comp = (s2 - sum) - y;
             sum = s2;
         } else {
             sum = fma(v, len, sum);
         }
-        if (STATS) ncell += len > T(0) ? 1 : 0;
-        if (!(m < T(1))) break;
+        if (STATS) ncell += len > TV(0) ? 1 : 0;
+        if (!(m < 1.0)) break;
         t = m;
         idx = nidx;
         v = vn;
-        o[0] += bx ? os[0] : T(0);
-        o[1] += by ? os[1] : T(0);
-        o[2] += bz ? os[2] : T(0);
-        tn[0] = fma(o[0], inv[0], nfb[0]);
-        tn[1] = fma(o[1], inv[1], nfb[1]);
-        tn[2] = fma(o[2], inv[2], nfb[2]);
+        o[0] += bx ? os[0] : 0;
+        o[1] += by ? os[1] : 0;
+        o[2] += bz ? os[2] : 0;
+        tn[0] = fma((double)o[0], inv[0], nfb[0]);
+        tn[1] = fma((double)o[1], inv[1], nfb[1]);
+        tn[2] = fma((double)o[2], inv[2], nfb[2]);
     }
     return sum;
 }
@@ -284,7 +295,7 @@ struct WaveLds {
     int rec_start[kRing];     // per node: first slot (absolute) of its items
     uint64_t rec_mask[kRing]; // per node: lanes that took it
     int4 tcell[kWave];        // target cell (bi0, bi1, bi2, linear index)
-    T tfrac[kWave][3];        // target fraction inside its cell
+    double tfrac[kWave][3];   // target fraction inside its cell
 };
 
 template <int PREC, bool STATS>
@@ -313,7 +324,7 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
     int64_t self = -1;
     {
         int bi[3] = {0, 0, 0};
-        T fb[3] = {T(0), T(0), T(0)};
+        double fb[3] = {0.0, 0.0, 0.0};
         if (valid) {
             const double4 p = P.tgt[it];
             const double x[3] = {p.x, p.y, p.z};
@@ -326,7 +337,7 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
                 const double B = (x[k] - P.lo[k]) * P.gs;
                 // a target on the top face sits in the last cell at fraction 1
                 bi[k] = clampi((int)floor(B), G);
-                fb[k] = (T)(B - (double)bi[k]);
+                fb[k] = B - (double)bi[k];
             }
         }
         L.tcell[lane] = make_int4(bi[0], bi[1], bi[2], (bi[0] * G + bi[1]) * G + bi[2]);
@@ -338,7 +349,6 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
     T acc = T(0), accc = T(0);
     int64_t st_test = 0, st_entries = 0, st_cells = 0, st_zero = 0;
     int head = 0, tail = 0, rhead = 0, rtail = 0;   // wave-uniform ring counters
-    const T Gf = (T)G;
     const T tau_scale = (T)(P.sigma * P.cell_cm);
 
     // March the next (up to) 64 pending items and hand the terms back.
@@ -351,33 +361,38 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
             const int code = L.code[slot];
             const int tl = L.lane[slot];
             const int4 tc = L.tcell[tl];
-            const T fb[3] = {L.tfrac[tl][0], L.tfrac[tl][1], L.tfrac[tl][2]};
+            const double fb[3] = {L.tfrac[tl][0], L.tfrac[tl][1], L.tfrac[tl][2]};
             const int bi[3] = {tc.x, tc.y, tc.z};
-            T D[3], w;
+            double D[3];
+            T w;
             if (PREC == START_FP64) {
                 const double4 m = code >= 0 ? P.mom[code] : P.src[-code - 1];
                 const double A[3] = {(m.x - P.lo[0]) * P.gs, (m.y - P.lo[1]) * P.gs, (m.z - P.lo[2]) * P.gs};
 #pragma unroll
-                for (int k = 0; k < 3; ++k) D[k] = (T)(A[k] - ((double)bi[k] + (double)fb[k]));
+                for (int k = 0; k < 3; ++k) D[k] = A[k] - ((double)bi[k] + fb[k]);
                 w = (T)m.w;
             } else {
-                const float4 m = code >= 0 ? P.momf[code] : P.srcf[-code - 1];
-                const float a[3] = {m.x, m.y, m.z};
+                // centre as 32-bit fixed point of the box: the top g bits are
+                // the cell, the rest the fraction inside it (exact in FP64)
+                const uint4 m = code >= 0 ? P.momq[code] : P.srcq[-code - 1];
+                const unsigned q[3] = {m.x, m.y, m.z};
+                const int sh = 32 - P.grid_log2;
+                const unsigned fmask = (1u << sh) - 1u;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    const float A = a[k] * (float)Gf;    // exact: G is a power of two
-                    const float fl = floorf(A);
-                    D[k] = (T)((float)((int)fl - bi[k]) + ((A - fl) - (float)fb[k]));
+                    const int ai = (int)(q[k] >> sh);
+                    const double fa = (double)(q[k] & fmask) * P.frac_scale;
+                    D[k] = (double)(ai - bi[k]) + (fa - fb[k]);
                 }
-                w = (T)m.w;
+                w = (T)__uint_as_float(m.w);
             }
-            const T d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
-            if (d2 > T(0)) {
+            const double d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+            if (d2 > 0.0) {
                 const T col = march<T, STATS>(PREC == START_FP64 ? (const T *)P.grid : (const T *)P.gridf, G,
-                                              ncell_m1, bi, tc.w, fb, D, nc);
-                const T dist = sqrt(d2);                       // grid units
+                                              (unsigned)ncell_m1, (unsigned)tc.w, fb, D, nc);
+                const T dist = (T)sqrt(d2);                    // grid units
                 const T tau = tau_scale * (col * dist);
-                term = w * exp(-tau) / d2;
+                term = w * exp(-tau) / (T)d2;
             } else {
                 nc = -1;                                       // zero distance: skipped
             }
@@ -440,7 +455,7 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
         const int kind = g.w >> 8;
         const bool active = valid && node >= resume;
         if (kind == kKindLeaf) {
-            const float lw = fp32 ? P.momf[node].w : (float)(P.mom[node].w > 0.0);
+            const float lw = fp32 ? __uint_as_float(P.momq[node].w) : (float)(P.mom[node].w > 0.0);
             push(active && (int64_t)P.ref[node] != self && lw > 0.f, node);
             node += 1;
             continue;
@@ -452,14 +467,14 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
             acc_node = accept(g, u, P.theta2);
         }
         if (acc_node) resume = sk;
-        const float lw = fp32 ? P.momf[node].w : (float)(P.mom[node].w > 0.0);
+        const float lw = fp32 ? __uint_as_float(P.momq[node].w) : (float)(P.mom[node].w > 0.0);
         push(acc_node && lw > 0.f, node);
         const bool open = active && !acc_node;
         if (kind == kKindBucket) {
             if (__any(open)) {
                 const int f = P.first[node], cnt = P.count[node];
                 for (int q = f; q < f + cnt; ++q) {
-                    const float qw = fp32 ? P.srcf[q].w : (float)(P.src[q].w > 0.0);
+                    const float qw = fp32 ? __uint_as_float(P.srcq[q].w) : (float)(P.src[q].w > 0.0);
                     push(open && (int64_t)P.perm[q] != self && qw > 0.f, -q - 1);
                 }
             }
@@ -510,28 +525,38 @@ __global__ void __launch_bounds__(kThreads) gather_targets(int64_t n, const unsi
     tgt[j] = make_double4(xyz[o], xyz[n + o], xyz[2 * n + o], 0.0);
 }
 
-// FP32 copies of the virtual sources: normalised centre in [0, 1] and the
-// luminosity relative to the root's (so every L' <= 1).
+// FP32-path copies of the virtual sources: the centre as 32-bit fixed-point
+// coordinates of the box (resolution 2^-32 of the side, so the source end of
+// every ray is placed to ~1e-8 cell in FP32 arithmetic) and the luminosity
+// relative to the root's (every L' <= 1).
+__device__ inline unsigned fixed32(double x, double lo, double inv)
+{
+    double u = (x - lo) * inv;
+    u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+    const double q = floor(u * 4294967296.0);
+    return q >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned)q;
+}
+
 __global__ void __launch_bounds__(kThreads) make_fp32_nodes(int64_t m, const double4 *mom, start_box box,
-                                                            double inv, float4 *momf)
+                                                            double inv, uint4 *momq)
 {
     const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (p >= m) return;
     const double Lref = mom[0].w > 0.0 ? mom[0].w : 1.0;
     const double4 v = mom[p];
-    momf[p] = make_float4((float)((v.x - box.lo[0]) * inv), (float)((v.y - box.lo[1]) * inv),
-                          (float)((v.z - box.lo[2]) * inv), (float)(v.w / Lref));
+    momq[p] = make_uint4(fixed32(v.x, box.lo[0], inv), fixed32(v.y, box.lo[1], inv), fixed32(v.z, box.lo[2], inv),
+                         __float_as_uint((float)(v.w / Lref)));
 }
 
 __global__ void __launch_bounds__(kThreads) make_fp32_src(int64_t n, const double4 *src, const double4 *mom,
-                                                          start_box box, double inv, float4 *srcf)
+                                                          start_box box, double inv, uint4 *srcq)
 {
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (j >= n) return;
     const double Lref = mom[0].w > 0.0 ? mom[0].w : 1.0;
     const double4 v = src[j];
-    srcf[j] = make_float4((float)((v.x - box.lo[0]) * inv), (float)((v.y - box.lo[1]) * inv),
-                          (float)((v.z - box.lo[2]) * inv), (float)(v.w / Lref));
+    srcq[j] = make_uint4(fixed32(v.x, box.lo[0], inv), fixed32(v.y, box.lo[1], inv), fixed32(v.z, box.lo[2], inv),
+                         __float_as_uint((float)(v.w / Lref)));
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
@@ -542,8 +567,8 @@ void make_fp32_tree(Tree *t, hipStream_t s)
 {
     if (t->n_nodes == 0) return;
     const double inv = 1.0 / t->box.size;
-    make_fp32_nodes<<<blocks_for(t->n_nodes), kThreads, 0, s>>>(t->n_nodes, t->mom, t->box, inv, t->momf);
-    make_fp32_src<<<blocks_for(t->n_src), kThreads, 0, s>>>(t->n_src, t->src, t->mom, t->box, inv, t->srcf);
+    make_fp32_nodes<<<blocks_for(t->n_nodes), kThreads, 0, s>>>(t->n_nodes, t->mom, t->box, inv, t->momq);
+    make_fp32_src<<<blocks_for(t->n_src), kThreads, 0, s>>>(t->n_src, t->src, t->mom, t->box, inv, t->srcq);
 }
 
 struct TargetScratch {
@@ -601,17 +626,20 @@ static Params make_params(const Tree *t, const Grid *g, int64_t n_t, void *scrat
     P.count = t->count;
     P.ref = t->ref;
     P.mom = t->mom;
-    P.momf = t->momf;
+    P.momq = t->momq;
     P.src = t->src;
-    P.srcf = t->srcf;
+    P.srcq = t->srcq;
     P.perm = t->perm;
     if (g) {
         P.grid = g->val;
         P.gridf = g->valf;
         P.G = g->G;
+        P.grid_log2 = g->grid_log2;
     } else {
         P.G = 1;
+        P.grid_log2 = 0;
     }
+    P.frac_scale = ldexp(1.0, -(32 - P.grid_log2));
     P.gs = (double)P.G / t->box.size;
     for (int k = 0; k < 3; ++k) P.lo[k] = t->box.lo[k];
     P.inv_size = 1.0 / t->box.size;

@@ -296,8 +296,8 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     const int64_t max_items = 2 * n;
     // persistent arrays
     size_t persist = al(n * sizeof(uint64_t)) + al(n * sizeof(unsigned)) + al(n * sizeof(double4)) +
-                     al(n * sizeof(float4)) + al(max_items * sizeof(int4)) + 4 * al(max_items * sizeof(int)) +
-                     al(max_items * sizeof(double4)) + al(max_items * sizeof(float4));
+                     al(n * sizeof(uint4)) + al(max_items * sizeof(int4)) + 4 * al(max_items * sizeof(int)) +
+                     al(max_items * sizeof(double4)) + al(max_items * sizeof(uint4));
     char *pm = nullptr;
     if (dmalloc(c, (void **)&pm, persist) != hipSuccess) return START_ENOMEM;
     t->bytes = persist;
@@ -306,14 +306,14 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     t->keys = (uint64_t *)take(n * sizeof(uint64_t));
     t->perm = (unsigned *)take(n * sizeof(unsigned));
     t->src = (double4 *)take(n * sizeof(double4));
-    t->srcf = (float4 *)take(n * sizeof(float4));
+    t->srcq = (uint4 *)take(n * sizeof(uint4));
     t->geo = (int4 *)take(max_items * sizeof(int4));
     t->skip = (int *)take(max_items * sizeof(int));
     t->first = (int *)take(max_items * sizeof(int));
     t->count = (int *)take(max_items * sizeof(int));
     t->ref = (int *)take(max_items * sizeof(int));
     t->mom = (double4 *)take(max_items * sizeof(double4));
-    t->momf = (float4 *)take(max_items * sizeof(float4));
+    t->momq = (uint4 *)take(max_items * sizeof(uint4));
 
     // temporaries
     size_t tmp_bytes = al(radix_temp_bytes(max_items)) + 6 * al(n * sizeof(int)) + 2 * al(n * sizeof(unsigned)) +

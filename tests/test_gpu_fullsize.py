@@ -1,0 +1,59 @@
+"""Full-size parity: the diffuse (2^20 emitters + star) and shadow (2^21
+emitters + star, 16 dense clumps) workloads, rate call exactly as bench.py
+launches it, checked on seeded samples of targets that the oracle computes
+one by one (with its own tree and grid)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests import gpu_common as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1005_5312_amd as S
+    c = S.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("name,sample", [("diffuse", 768), ("shadow", 512)])
+def test_fullsize_sampled(ctx, name, sample):
+    w = H.workload(name)
+    print(f"[case] full size {name}: {w.n_tgt} targets, {w.n_src} sources", flush=True)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    box = H.box_of(w)
+    tree = ctx.build_source_tree(box, d(w.src_xyz), d(w.src_lum))
+    grid = ctx.build_gas_grid(box, d(w.gas_xyz), d(w.gas_h), d(w.gas_nhi), w.grid_log2)
+    tgt, ss = d(w.tgt_xyz), d(w.self_src)
+    g32 = ctx.compute_rates(tree, grid, tgt, ss, 1.0, w.sigma, "fp32c").cpu().numpy()
+    g64 = ctx.compute_rates(tree, grid, tgt, ss, 1.0, w.sigma, "fp64").cpu().numpy()
+    ctx.synchronize()
+    assert np.all(np.isfinite(g32)) and np.all(np.isfinite(g64))
+    assert np.all(g32 >= 0) and np.all(g64 >= 0)
+    obox = H.obox_of(w)
+    ot = O.Tree(obox, w.src_xyz, w.src_lum)
+    og = O.grid(obox, w.gas_xyz, w.gas_h, w.gas_nhi, w.grid_log2)
+    # the sample: seeded uniform draws plus the targets inside dense clumps or
+    # deepest in the neutral shell, where FP32 errors would show first
+    idx = H.W.sample_indices(w.n_tgt, sample, seed=101)
+    dense = np.argsort(-w.gas_nhi)[: sample // 8]
+    idx = np.unique(np.concatenate([idx, dense]))
+    want = O.rates(ot, w.grid_log2, og, w.tgt_xyz[:, idx], w.self_src[idx], 1.0, w.sigma)
+    r64 = H.rel_errors(g64[idx], want)
+    r32 = H.rel_errors(g32[idx].astype(np.float64), want)
+    print(f"  fp64 max rel {r64[0]:.3e} (abs below floor {r64[1]:.1e}); "
+          f"fp32c max rel {r32[0]:.3e} (abs below floor {r32[1]:.1e}) over {r32[2]} targets", flush=True)
+    assert r64[0] <= H.TOL_FP64 and r64[1] <= H.ABS_FLOOR
+    assert r32[0] <= H.TOL_FP32C and r32[1] <= H.ABS_FLOOR
+    # the grid itself on sampled cells (brute force over all particles)
+    cells = H.W.sample_indices((1 << w.grid_log2) ** 3, 256, seed=5)
+    gw = O.grid_cells(obox, w.gas_xyz, w.gas_h, w.gas_nhi, w.grid_log2, cells)
+    gg = ctx.grid_export(grid).reshape(-1)[cells]
+    nz = gw != 0
+    assert np.array_equal(gg == 0, gw == 0)
+    assert np.max(np.abs(gg[nz] / gw[nz] - 1)) <= 1e-12
