@@ -65,7 +65,7 @@ def source_sha():
 def traffic_from_profiles(workload, prec, sha):
     """HBM bytes per walk launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"walk_{prec}_{workload}_pmc.txt")
+    path = os.path.join(ROOT, "profiles", f"rates_kernel_{prec}_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None
     vals = {}

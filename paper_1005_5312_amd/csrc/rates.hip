@@ -108,13 +108,6 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ inline uint64_t uniform64(uint64_t v)
-{
-    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
 __device__ inline int lanes_below(uint64_t m)
 {
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -133,56 +126,58 @@ __device__ inline int lanes_below(uint64_t m)
 // by the linear stride of the axis crossed.  TV is the type of the grid values
 // and of the sum: FP32 with Kahan compensation, or FP64.  Returns sum n_c dt.
 //
-// The loop ends: each step moves one axis to its next plane, and o * inv then
-// grows by |inv| >= 1 / (2 G) (|D| is below 2G for points in the box), so tn
-// passes 1 after at most 2G + 2 steps per axis; a NaN parameter is never the
-// minimum (fmin) and an all-NaN state exits at once; max_steps also bounds it.
+// The loop ends: each step moves one axis to its next plane, and its
+// parameter then grows by a_k >= 1 / (2 G) (|D| is below 2G for points in the
+// box), so it passes 1 after at most 2G + 2 steps per axis; a NaN parameter
+// never wins the comparisons and an all-NaN state exits at once; max_steps
+// bounds the loop in any case.
 // ---------------------------------------------------------------------------
 template <typename TV, bool STATS>
 __device__ inline TV march(const TV *__restrict__ grid, int G, unsigned ncell_m1, unsigned idx0, const double fb[3],
                            const double D[3], int &ncell)
 {
+    // Axis k crosses its planes at t = (p_k - fb_k) / D_k for D_k > 0 and
+    // t = -(p_k + fb_k) / D_k ... written for both signs as t = p_k a_k + c_k
+    // with a_k = |1 / D_k| and p_k = 1, 2, ... (D_k > 0) or 0, 1, ... (D_k < 0)
+    // counting the planes crossed so far.
     const int stride[3] = {G * G, G, 1};
-    double inv[3], nfb[3], tn[3];
-    int o[3], os[3], ds[3];
+    double a[3], c[3], p[3], tn[3];
+    int ds[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         if (D[k] > 0.0) {
-            inv[k] = 1.0 / D[k];
-            o[k] = 1;
-            os[k] = 1;
+            a[k] = 1.0 / D[k];
+            p[k] = 1.0;
+            c[k] = -fb[k] * a[k];
             ds[k] = stride[k];
-            nfb[k] = -fb[k] * inv[k];
         } else if (D[k] < 0.0) {
-            inv[k] = 1.0 / D[k];
-            o[k] = 0;
-            os[k] = -1;
+            a[k] = -1.0 / D[k];
+            p[k] = 0.0;
+            c[k] = fb[k] * a[k];
             ds[k] = -stride[k];
-            nfb[k] = -fb[k] * inv[k];
         } else {
-            inv[k] = 0.0;
-            o[k] = 0;
-            os[k] = 0;
+            a[k] = 0.0;
+            p[k] = 0.0;
+            c[k] = 2.0;   // never crossed
             ds[k] = 0;
-            nfb[k] = 2.0;   // never crossed
         }
-        tn[k] = fma((double)o[k], inv[k], nfb[k]);
+        tn[k] = fma(p[k], a[k], c[k]);
     }
     unsigned idx = idx0;
     double t = 0.0;
     TV sum = TV(0), comp = TV(0);
     const char *base = reinterpret_cast<const char *>(grid);
-    TV v = *reinterpret_cast<const TV *>(base + (size_t)idx * sizeof(TV));
     const int max_steps = 3 * G + 3;
     for (int it = 0; it < max_steps; ++it) {
-        const double m = fmin(fmin(tn[0], tn[1]), tn[2]);
-        const double e = fmin(m, 1.0);
-        const bool bx = tn[0] == m;
-        const bool by = !bx && tn[1] == m;
-        const bool bz = !bx && !by;
-        unsigned nidx = idx + (unsigned)(bx ? ds[0] : (by ? ds[1] : ds[2]));
-        nidx = nidx > ncell_m1 ? ncell_m1 : nidx;   // also catches a step below 0
-        const TV vn = *reinterpret_cast<const TV *>(base + (size_t)nidx * sizeof(TV));
+        const TV v = *reinterpret_cast<const TV *>(base + (size_t)idx * sizeof(TV));
+        // nearest plane: two compare-selects give both the minimum and the
+        // axis (a NaN parameter never wins; an all-NaN state exits below)
+        const bool c01 = tn[0] <= tn[1];
+        const double m01 = c01 ? tn[0] : tn[1];
+        const bool c2 = m01 <= tn[2];
+        const double m = c2 ? m01 : tn[2];
+        const bool more = m < 1.0;
+        const double e = more ? m : 1.0;
         const TV len = (TV)(e - t);
         if (sizeof(TV) == 4) {
             // Kahan-compensated FP32 sum
@@ -194,16 +189,22 @@ __device__ inline TV march(const TV *__restrict__ grid, int G, unsigned ncell_m1
             sum = fma(v, len, sum);
         }
         if (STATS) ncell += len > TV(0) ? 1 : 0;
-        if (!(m < 1.0)) break;
+        if (!more) break;
         t = m;
-        idx = nidx;
-        v = vn;
-        o[0] += bx ? os[0] : 0;
-        o[1] += by ? os[1] : 0;
-        o[2] += bz ? os[2] : 0;
-        tn[0] = fma((double)o[0], inv[0], nfb[0]);
-        tn[1] = fma((double)o[1], inv[1], nfb[1]);
-        tn[2] = fma((double)o[2], inv[2], nfb[2]);
+        if (c2 && c01) {
+            idx += (unsigned)ds[0];
+            p[0] += 1.0;
+            tn[0] = fma(p[0], a[0], c[0]);
+        } else if (c2) {
+            idx += (unsigned)ds[1];
+            p[1] += 1.0;
+            tn[1] = fma(p[1], a[1], c[1]);
+        } else {
+            idx += (unsigned)ds[2];
+            p[2] += 1.0;
+            tn[2] = fma(p[2], a[2], c[2]);
+        }
+        idx = idx > ncell_m1 ? ncell_m1 : idx;   // also catches a step below 0
     }
     return sum;
 }
@@ -278,34 +279,49 @@ __global__ void __launch_bounds__(kThreads) list_kernel(Params P)
 // marched at once: (entry, lane) items go to a per-wave ring in LDS in node
 // order, and as soon as 64 items are pending every lane marches one of them
 // -- whichever target it belongs to.  Items of one node share the source and
-// sit side by side, so a batch is 1-3 bundles of nearly parallel rays.  Each
-// node's items are recorded as (first slot, lane mask); after a batch every
-// lane picks its own terms out of the ring through these records, in node
-// order, and adds them to its Kahan (FP32) or plain (FP64) sum.  Results are
+// sit side by side, so a batch is 1-3 bundles of nearly parallel rays that
+// read the same grid lines (sorting a window by ray length instead balanced
+// the lanes better but lost this locality and ran 40% slower).  Each node's
+// items are recorded as (first slot, lane mask); after a batch every lane
+// picks its own terms out of the ring through these records, in node order,
+// and adds them to its Kahan (FP32) or plain (FP64) sum.  Results are
 // deterministic and every target sums its terms in depth-first order.
 // ---------------------------------------------------------------------------
 constexpr int kRing = 128;   // items; a node adds <= 64 and a batch drains 64
 
-template <typename T>
+// TF: the target's fraction inside its cell, FP64 for the FP64 path and
+// 32-bit fixed point (2^-32 cell) for the FP32 path, which halves that array.
+template <typename T, typename TF>
 struct WaveLds {
-    int code[kRing];          // node index, or -(sorted source index)-1
-    unsigned char lane[kRing];
+    uint64_t rec_mask[kRing];     // per node: lanes that took it
+    int code[kRing];              // node index, or -(sorted source index)-1
+    int rec_start[kRing];         // per node: first slot (absolute) of its items
     T term[kRing];
-    int ncell[kRing];         // grid cells crossed (counter mode)
-    int rec_start[kRing];     // per node: first slot (absolute) of its items
-    uint64_t rec_mask[kRing]; // per node: lanes that took it
-    int4 tcell[kWave];        // target cell (bi0, bi1, bi2, linear index)
-    double tfrac[kWave][3];   // target fraction inside its cell
+    unsigned tcell[kWave];        // target cell, linear index
+    TF tfrac[kWave][3];           // target fraction inside its cell
+    unsigned char lane[kRing];    // target lane of the item
 };
+
+__device__ inline double frac_of(double f) { return f; }
+__device__ inline double frac_of(unsigned f) { return (double)f * 0x1p-32; }
+__device__ inline void store_frac(double &d, double f) { d = f; }
+__device__ inline void store_frac(unsigned &d, double f)
+{
+    const double q = floor(f * 4294967296.0);
+    d = q >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned)q;
+}
 
 template <int PREC, bool STATS>
 __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
 {
     using T = typename std::conditional<PREC == START_FP64, double, float>::type;
-    __shared__ WaveLds<T> lds_all[kWavesPerBlock];
+    using TF = typename std::conditional<PREC == START_FP64, double, unsigned>::type;
+    __shared__ WaveLds<T, TF> lds_all[kWavesPerBlock];
+    __shared__ int ncell_all[STATS ? kWavesPerBlock : 1][STATS ? kRing : 1];   // counter mode only
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x >> 6;
-    WaveLds<T> &L = lds_all[wv];
+    WaveLds<T, TF> &L = lds_all[wv];
+    int *lds_ncell = ncell_all[STATS ? wv : 0];
     // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
     // run of Morton-ordered tiles so that its L2 sees neighbouring targets
     const int64_t nb = gridDim.x;
@@ -318,6 +334,7 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
     if (tile * kWave >= P.n_t) return;
 
     const int G = P.G;
+    const int gl = P.grid_log2;
     const int ncell_m1 = G * G * G - 1;
     double u[3] = {0.0, 0.0, 0.0};
     unsigned orig = 0;
@@ -340,16 +357,60 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
                 fb[k] = B - (double)bi[k];
             }
         }
-        L.tcell[lane] = make_int4(bi[0], bi[1], bi[2], (bi[0] * G + bi[1]) * G + bi[2]);
-        L.tfrac[lane][0] = fb[0];
-        L.tfrac[lane][1] = fb[1];
-        L.tfrac[lane][2] = fb[2];
+        L.tcell[lane] = (unsigned)((bi[0] * G + bi[1]) * G + bi[2]);
+        store_frac(L.tfrac[lane][0], fb[0]);
+        store_frac(L.tfrac[lane][1], fb[1]);
+        store_frac(L.tfrac[lane][2], fb[2]);
     }
 
     T acc = T(0), accc = T(0);
     int64_t st_test = 0, st_entries = 0, st_cells = 0, st_zero = 0;
     int head = 0, tail = 0, rhead = 0, rtail = 0;   // wave-uniform ring counters
     const T tau_scale = (T)(P.sigma * P.cell_cm);
+    const int sh = 32 - gl;
+
+    // March one item: the term L e^-tau / d^2 (d in cells) of ring slot `slot`.
+    auto march_item = [&](int slot, T &term, int &nc) {
+        const int code = L.code[slot];
+        const int tl = L.lane[slot];
+        const unsigned tcell = L.tcell[tl];
+        const double fb[3] = {frac_of(L.tfrac[tl][0]), frac_of(L.tfrac[tl][1]), frac_of(L.tfrac[tl][2])};
+        const int tb[3] = {(int)(tcell >> (2 * gl)), (int)((tcell >> gl) & (unsigned)(G - 1)),
+                           (int)(tcell & (unsigned)(G - 1))};
+        double D[3];
+        T w;
+        if (PREC == START_FP64) {
+            const double4 m = code >= 0 ? P.mom[code] : P.src[-code - 1];
+            const double A[3] = {(m.x - P.lo[0]) * P.gs, (m.y - P.lo[1]) * P.gs, (m.z - P.lo[2]) * P.gs};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) D[k] = A[k] - ((double)tb[k] + fb[k]);
+            w = (T)m.w;
+        } else {
+            // centre as 32-bit fixed point of the box: the top g bits are the
+            // cell, the rest the fraction inside it (exact in FP64)
+            const uint4 m = code >= 0 ? P.momq[code] : P.srcq[-code - 1];
+            const unsigned q[3] = {m.x, m.y, m.z};
+            const unsigned fmask = (1u << sh) - 1u;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int ai = (int)(q[k] >> sh);
+                const double fa = (double)(q[k] & fmask) * P.frac_scale;
+                D[k] = (double)(ai - tb[k]) + (fa - fb[k]);
+            }
+            w = (T)__uint_as_float(m.w);
+        }
+        const double d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+        if (d2 > 0.0) {
+            const T col = march<T, STATS>(PREC == START_FP64 ? (const T *)P.grid : (const T *)P.gridf, G,
+                                          (unsigned)ncell_m1, tcell, fb, D, nc);
+            const T dist = (T)sqrt(d2);                        // grid units
+            const T tau = tau_scale * (col * dist);
+            term = w * exp(-tau) / (T)d2;
+        } else {
+            term = T(0);
+            nc = -1;                                           // zero distance: skipped
+        }
+    };
 
     // March the next (up to) 64 pending items and hand the terms back.
     auto drain = [&]() {
@@ -357,54 +418,15 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
         const int slot = (head + lane) & (kRing - 1);
         T term = T(0);
         int nc = 0;
-        if (lane < nb_items) {
-            const int code = L.code[slot];
-            const int tl = L.lane[slot];
-            const int4 tc = L.tcell[tl];
-            const double fb[3] = {L.tfrac[tl][0], L.tfrac[tl][1], L.tfrac[tl][2]};
-            const int bi[3] = {tc.x, tc.y, tc.z};
-            double D[3];
-            T w;
-            if (PREC == START_FP64) {
-                const double4 m = code >= 0 ? P.mom[code] : P.src[-code - 1];
-                const double A[3] = {(m.x - P.lo[0]) * P.gs, (m.y - P.lo[1]) * P.gs, (m.z - P.lo[2]) * P.gs};
-#pragma unroll
-                for (int k = 0; k < 3; ++k) D[k] = A[k] - ((double)bi[k] + fb[k]);
-                w = (T)m.w;
-            } else {
-                // centre as 32-bit fixed point of the box: the top g bits are
-                // the cell, the rest the fraction inside it (exact in FP64)
-                const uint4 m = code >= 0 ? P.momq[code] : P.srcq[-code - 1];
-                const unsigned q[3] = {m.x, m.y, m.z};
-                const int sh = 32 - P.grid_log2;
-                const unsigned fmask = (1u << sh) - 1u;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const int ai = (int)(q[k] >> sh);
-                    const double fa = (double)(q[k] & fmask) * P.frac_scale;
-                    D[k] = (double)(ai - bi[k]) + (fa - fb[k]);
-                }
-                w = (T)__uint_as_float(m.w);
-            }
-            const double d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
-            if (d2 > 0.0) {
-                const T col = march<T, STATS>(PREC == START_FP64 ? (const T *)P.grid : (const T *)P.gridf, G,
-                                              (unsigned)ncell_m1, (unsigned)tc.w, fb, D, nc);
-                const T dist = (T)sqrt(d2);                    // grid units
-                const T tau = tau_scale * (col * dist);
-                term = w * exp(-tau) / (T)d2;
-            } else {
-                nc = -1;                                       // zero distance: skipped
-            }
-        }
+        if (lane < nb_items) march_item(slot, term, nc);
         L.term[slot] = term;
-        if (STATS) L.ncell[slot] = nc;
+        if (STATS) lds_ncell[slot] = nc;
         wave_sync();
         const int end = head + nb_items;
         while (rhead < rtail) {
             const int rs = __builtin_amdgcn_readfirstlane(L.rec_start[rhead & (kRing - 1)]);
             if (rs >= end) break;
-            const uint64_t m = uniform64(L.rec_mask[rhead & (kRing - 1)]);
+            const uint64_t m = L.rec_mask[rhead & (kRing - 1)];
             if ((m >> lane) & 1ull) {
                 const int s = rs + lanes_below(m);
                 if (s >= head && s < end) {
@@ -413,7 +435,7 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
                     if (sizeof(T) == 4) accc = (t2 - acc) - y;
                     acc = t2;
                     if (STATS) {
-                        const int c = L.ncell[s & (kRing - 1)];
+                        const int c = lds_ncell[s & (kRing - 1)];
                         if (c < 0) st_zero++;
                         else st_cells += c;
                     }
