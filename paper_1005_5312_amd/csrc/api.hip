@@ -12,17 +12,6 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
 start_status build_grid(Ctx *c, const start_box &box, int64_t n, const double *xyz, const double *h,
                         const double *nhi, int grid_log2, Grid *g);
 void make_fp32_tree(Tree *t, hipStream_t s);
-size_t target_scratch_bytes(int64_t n);
-void prepare_targets(Ctx *c, const start_box &box, int64_t n_t, const double *tgt_xyz, const int64_t *self_src,
-                     int64_t n_src, void *scratch, hipStream_t s);
-void launch_rates(const Tree *t, const Grid *g, int64_t n_t, void *scratch, const int64_t *self_src,
-                  double theta, double sigma, int prec, void *gamma, hipStream_t s);
-void launch_counts(const Tree *t, int64_t n_t, void *scratch, const int64_t *self_src, double theta,
-                   int64_t *counts, hipStream_t s);
-void launch_lists(const Tree *t, int64_t n_t, void *scratch, const int64_t *self_src, double theta,
-                  const int64_t *offsets, int64_t *entries, hipStream_t s);
-void launch_stats(const Tree *t, const Grid *g, int64_t n_t, void *scratch, const int64_t *self_src,
-                  double theta, int prec, int64_t *stats, hipStream_t s);
 
 hipError_t dmalloc(Ctx *c, void **p, size_t bytes)
 {
@@ -100,6 +89,68 @@ start_status ensure_scratch(start_ctx *ctx, size_t bytes)
     return START_OK;
 }
 
+start_status ensure_stage(start_ctx *ctx, size_t bytes)
+{
+    Ctx &c = ctx->c;
+    if (c.host_stage_bytes >= bytes) return START_OK;
+    hipEventSynchronize(c.stage_ev);
+    if (c.host_stage) hipHostFree(c.host_stage);
+    c.host_stage = nullptr;
+    c.host_stage_bytes = 0;
+    const size_t want = bytes + bytes / 2 + 4096;
+    if (hipHostMalloc(&c.host_stage, want, hipHostMallocDefault) != hipSuccess)
+        return fail(ctx, START_ENOMEM, "pinned host allocation failed");
+    c.host_stage_bytes = want;
+    return START_OK;
+}
+
+// Enqueues a batch of rate problems (mode 0 rates, 1 counters, 2 list
+// counts, 3 lists), growing scratch and staging when needed.
+start_status enqueue(start_ctx *ctx, const RateSpec *specs, int n, int mode)
+{
+    Ctx &c = ctx->c;
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) total += specs[i].n_t;
+    const int64_t tiles = batch_tiles(specs, n);
+    start_status st = ensure_scratch(ctx, batch_scratch_bytes(total, n, tiles));
+    if (st) return st;
+    st = ensure_stage(ctx, batch_stage_bytes(n, tiles));
+    if (st) return st;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (c.profile && mode == 0) {
+        if (c.ev_used + 2 > c.ev_pool.size()) {
+            hipEvent_t a = nullptr, b = nullptr;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+                return fail(ctx, START_EHIP, "hipEventCreate failed");
+            c.ev_pool.push_back(a);
+            c.ev_pool.push_back(b);
+        }
+        ev0 = c.ev_pool[c.ev_used];
+        ev1 = c.ev_pool[c.ev_used + 1];
+        c.ev_used += 2;
+    }
+    run_batch(&c, specs, n, mode, c.scratch, ev0, ev1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    return START_OK;
+}
+
+RateSpec spec_of(const start_tree *tree, const start_grid *grid, int64_t n_t, const double *tgt_xyz,
+                 const int64_t *self_src, double theta, double sigma, int prec)
+{
+    RateSpec r;
+    memset(&r, 0, sizeof(r));
+    r.tree = &tree->t;
+    r.grid = grid ? &grid->g : nullptr;
+    r.n_t = n_t;
+    r.tgt_xyz = tgt_xyz;
+    r.self_src = self_src;
+    r.theta = theta;
+    r.sigma = sigma;
+    r.prec = prec;
+    return r;
+}
+
 start_status check_rate_args(start_ctx *ctx, const start_tree *tree, const start_grid *grid, int64_t n_t,
                              const double *tgt, double theta, double sigma, int prec, bool need_grid)
 {
@@ -147,6 +198,12 @@ start_status start_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
         return START_ENOMEM;
     }
     hipMemset(ctx->c.d_flags, 0, 256);
+    if (hipEventCreateWithFlags(&ctx->c.stage_ev, hipEventDisableTiming) != hipSuccess) {
+        hipFree(ctx->c.d_flags);
+        if (ctx->c.own_stream) hipStreamDestroy(ctx->c.stream);
+        delete ctx;
+        return START_EHIP;
+    }
     *out = ctx;
     return START_OK;
 }
@@ -158,6 +215,8 @@ void start_ctx_destroy(start_ctx *ctx)
     hipStreamSynchronize(ctx->c.stream);
     dfree(&ctx->c, ctx->c.scratch, ctx->c.scratch_bytes);
     for (hipEvent_t ev : ctx->c.ev_pool) hipEventDestroy(ev);
+    if (ctx->c.stage_ev) hipEventDestroy(ctx->c.stage_ev);
+    if (ctx->c.host_stage) hipHostFree(ctx->c.host_stage);
     hipFree(ctx->c.d_flags);
     if (ctx->c.own_stream) hipStreamDestroy(ctx->c.stream);
     delete ctx;
@@ -281,29 +340,9 @@ start_status start_compute_rates(start_ctx *ctx, const start_tree *tree, const s
     if (n_t == 0) return START_OK;
     if (!gamma_out) return fail(ctx, START_EINVAL, "gamma_out is NULL");
     hipSetDevice(ctx->c.device);
-    st = ensure_scratch(ctx, target_scratch_bytes(n_t));
-    if (st) return st;
-    hipStream_t s = ctx->c.stream;
-    prepare_targets(&ctx->c, tree->t.box, n_t, tgt_xyz, self_src, tree->t.n_src, ctx->c.scratch, s);
-    hipEvent_t ev1 = nullptr;
-    if (ctx->c.profile) {
-        Ctx &c = ctx->c;
-        if (c.ev_used + 2 > c.ev_pool.size()) {
-            hipEvent_t a = nullptr, b = nullptr;
-            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
-                return fail(ctx, START_EHIP, "hipEventCreate failed");
-            c.ev_pool.push_back(a);
-            c.ev_pool.push_back(b);
-        }
-        hipEventRecord(c.ev_pool[c.ev_used], s);
-        ev1 = c.ev_pool[c.ev_used + 1];
-        c.ev_used += 2;
-    }
-    launch_rates(&tree->t, &grid->g, n_t, ctx->c.scratch, self_src, theta_crit, sigma_cm2, prec, gamma_out, s);
-    if (ev1) hipEventRecord(ev1, s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
-    return START_OK;
+    RateSpec r = spec_of(tree, grid, n_t, tgt_xyz, self_src, theta_crit, sigma_cm2, prec);
+    r.gamma = gamma_out;
+    return enqueue(ctx, &r, 1, 0);
 }
 
 start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const start_item *items)
@@ -317,13 +356,18 @@ start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const star
         if (st) return st;
         if (it.n_t > 0 && !it.gamma_out) return fail(ctx, START_EINVAL, "gamma_out is NULL");
     }
+    std::vector<RateSpec> specs;
+    specs.reserve((size_t)n_items);
     for (int i = 0; i < n_items; ++i) {
         const start_item &it = items[i];
-        start_status st = start_compute_rates(ctx, it.tree, it.grid, it.n_t, it.tgt_xyz, it.self_src, it.theta_crit,
-                                              it.sigma_cm2, it.prec, it.gamma_out);
-        if (st) return st;
+        if (it.n_t == 0) continue;
+        RateSpec r = spec_of(it.tree, it.grid, it.n_t, it.tgt_xyz, it.self_src, it.theta_crit, it.sigma_cm2, it.prec);
+        r.gamma = it.gamma_out;
+        specs.push_back(r);
     }
-    return START_OK;
+    if (specs.empty()) return START_OK;
+    hipSetDevice(ctx->c.device);
+    return enqueue(ctx, specs.data(), (int)specs.size(), 0);
 }
 
 size_t start_estimate_bytes(int64_t n_t, int64_t n_s, int64_t n_gas, int grid_log2, start_precision prec)
@@ -335,7 +379,7 @@ size_t start_estimate_bytes(int64_t n_t, int64_t n_s, int64_t n_gas, int grid_lo
     const size_t tree = (size_t)n_s * (8 + 4 + 32 + 16) + (size_t)2 * n_s * (16 + 16 + 32 + 16) +
                         radix_temp_bytes(2 * n_s) + (size_t)n_s * 48 + (size_t)2 * n_s * 44 + 65536;
     const size_t grid = G3 * 12 + (size_t)n_gas * 56 + radix_temp_bytes(n_gas) + G3 * 4 + 65536;
-    const size_t rates = (target_scratch_bytes(n_t) * 5) / 4 + 65536;
+    const size_t rates = (batch_scratch_bytes(n_t, 1, (n_t + 63) / 64) * 5) / 4 + 65536;
     return tree + grid + rates;
 }
 
@@ -385,15 +429,14 @@ start_status start_interaction_lists(start_ctx *ctx, const start_tree *tree, int
         hipError_t e = hipMemcpy(offsets, off.data(), sizeof(int64_t), hipMemcpyDefault);
         return e == hipSuccess ? START_OK : fail(ctx, START_EHIP, hipGetErrorString(e));
     }
-    st = ensure_scratch(ctx, target_scratch_bytes(n_t));
-    if (st) return st;
     hipStream_t s = ctx->c.stream;
     int64_t *d_counts = nullptr;
     if (dmalloc(&ctx->c, (void **)&d_counts, (size_t)(n_t + 1) * sizeof(int64_t)) != hipSuccess)
         return fail(ctx, START_ENOMEM, "device allocation failed");
-    prepare_targets(&ctx->c, tree->t.box, n_t, tgt_xyz, self_src, tree->t.n_src, ctx->c.scratch, s);
-    launch_counts(&tree->t, n_t, ctx->c.scratch, self_src, theta_crit, d_counts, s);
-    st = start_synchronize(ctx);
+    RateSpec r = spec_of(tree, nullptr, n_t, tgt_xyz, self_src, theta_crit, 0.0, START_FP64);
+    r.counts = d_counts;
+    st = enqueue(ctx, &r, 1, 2);
+    if (!st) st = start_synchronize(ctx);
     if (st) {
         dfree(&ctx->c, d_counts, (size_t)(n_t + 1) * sizeof(int64_t));
         return st;
@@ -414,12 +457,16 @@ start_status start_interaction_lists(start_ctx *ctx, const start_tree *tree, int
         dfree(&ctx->c, d_counts, (size_t)(n_t + 1) * sizeof(int64_t));
         return fail(ctx, START_ENOMEM, "device allocation failed");
     }
-    launch_lists(&tree->t, n_t, ctx->c.scratch, self_src, theta_crit, d_counts, d_ent, s);
+    r.counts = nullptr;
+    r.offsets = d_counts;
+    r.entries = d_ent;
+    st = enqueue(ctx, &r, 1, 3);
     e = hipStreamSynchronize(s);
-    if (e == hipSuccess && off[n_t] > 0)
+    if (!st && e == hipSuccess && off[n_t] > 0)
         e = hipMemcpy(entries, d_ent, (size_t)off[n_t] * sizeof(int64_t), hipMemcpyDefault);
     dfree(&ctx->c, d_ent, ent_bytes);
     dfree(&ctx->c, d_counts, (size_t)(n_t + 1) * sizeof(int64_t));
+    if (st) return st;
     if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
     return START_OK;
 }
@@ -443,15 +490,13 @@ start_status start_rate_counters(start_ctx *ctx, const start_tree *tree, const s
     if (n_t == 0) return START_OK;
     if (!counters) return fail(ctx, START_EINVAL, "counters is NULL");
     hipSetDevice(ctx->c.device);
-    st = ensure_scratch(ctx, target_scratch_bytes(n_t));
-    if (st) return st;
-    hipStream_t s = ctx->c.stream;
     int64_t *d_stats = nullptr;
     const size_t bytes = (size_t)n_t * 4 * sizeof(int64_t);
     if (dmalloc(&ctx->c, (void **)&d_stats, bytes) != hipSuccess) return fail(ctx, START_ENOMEM, "allocation failed");
-    prepare_targets(&ctx->c, tree->t.box, n_t, tgt_xyz, self_src, tree->t.n_src, ctx->c.scratch, s);
-    launch_stats(&tree->t, &grid->g, n_t, ctx->c.scratch, self_src, theta_crit, prec, d_stats, s);
-    st = start_synchronize(ctx);
+    RateSpec r = spec_of(tree, grid, n_t, tgt_xyz, self_src, theta_crit, 1.0, prec);
+    r.stats = d_stats;
+    st = enqueue(ctx, &r, 1, 1);
+    if (!st) st = start_synchronize(ctx);
     hipError_t e = hipSuccess;
     if (!st) e = hipMemcpy(counters, d_stats, bytes, hipMemcpyDefault);
     dfree(&ctx->c, d_stats, bytes);

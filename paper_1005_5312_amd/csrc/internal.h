@@ -33,6 +33,11 @@ struct Ctx {
     // scratch reused by compute_rates (grown on demand)
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    // pinned staging of batch tables (item descriptors, offsets, tiles) and
+    // the event after its last upload
+    void *host_stage = nullptr;
+    size_t host_stage_bytes = 0;
+    hipEvent_t stage_ev = nullptr;
     // walk-kernel timing (start_profile_enable)
     bool profile = false;
     std::vector<hipEvent_t> ev_pool;   // pairs (start, stop)
@@ -84,6 +89,28 @@ void exclusive_scan_u32(unsigned *d_data, int64_t n, void *temp, hipStream_t s);
 size_t radix_temp_bytes(int64_t n);
 void radix_sort_pairs(uint64_t *keys, unsigned *vals, int64_t n, int bits, void *temp,
                       hipStream_t s);
+
+// ---- rate batches (rates.hip) ----
+// One rate problem as given to the library.
+struct RateSpec {
+    const Tree *tree;
+    const Grid *grid;
+    int64_t n_t;
+    const double *tgt_xyz;
+    const int64_t *self_src;
+    double theta;
+    double sigma;
+    int prec;
+    void *gamma;               // rates
+    int64_t *stats;            // counters [n_t][4]
+    int64_t *counts;           // list counts [n_t]
+    const int64_t *offsets;    // list offsets [n_t + 1]
+    int64_t *entries;          // list entries
+};
+size_t batch_scratch_bytes(int64_t n_targets, int n_items, int64_t n_tiles);
+size_t batch_stage_bytes(int n_items, int64_t n_tiles);
+int64_t batch_tiles(const RateSpec *specs, int n);
+void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, void *scratch, hipEvent_t ev0, hipEvent_t ev1);
 
 // ---- Morton keys (tree.hip) ----
 void launch_keys(const start_box &box, int64_t n, const double *xyz, const double *lum,

@@ -35,9 +35,13 @@ constexpr int kWavesPerBlock = kThreads / kWave;
 
 enum Mode { kRates = 0, kCount = 1, kList = 2, kStats = 3 };
 
-struct Params {
+// One rate problem: a tree, a grid and a run of targets (the item's segment
+// of the batch's sorted target arrays).  Read by the kernels from a device
+// table, one entry per item of a batch.
+struct Item {
     // tree
     int64_t n_nodes;
+    int64_t n_src;
     const int4 *geo;
     const int *skip;
     const int *first;
@@ -56,23 +60,29 @@ struct Params {
     double frac_scale;  // 2^-(32 - grid_log2)
     double gs;          // G / size
     double lo[3];
+    double size;
     double inv_size;
     double unit_cm;
     double cell_cm;     // size / G * unit_cm
     double theta2;
     double sigma;
-    // targets (sorted)
+    // targets: caller's positions, and this item's run of the sorted arrays
     int64_t n_t;
+    const double *tgt_xyz;   // [3][n_t], caller order
     const double4 *tgt;      // sorted target positions
-    const unsigned *tgt_orig;
-    const int64_t *self_src; // original order, may be null
-    // outputs
-    void *gamma;             // original order
-    int64_t *counts;         // kCount: entries per target (original order)
-    const int64_t *offsets;  // kList
-    int64_t *entries;        // kList
-    int64_t *stats;          // kStats: [n_t][4]
+    const unsigned *tgt_orig;// caller index of each sorted target
+    const int64_t *self_src; // caller order, may be null
+    // outputs (caller order)
+    void *gamma;
+    int64_t *counts;         // list count mode: entries per target
+    const int64_t *offsets;  // list mode
+    int64_t *entries;        // list mode
+    int64_t *stats;          // counter mode: [n_t][4]
 };
+
+// A launch covers the tiles (runs of <= 64 targets of one item) of a batch,
+// one wave per tile; the item table and the tiles are kernel arguments of
+// their own (const, restrict) so their fields are read with scalar loads.
 
 // Eq. (12): l^2 <= theta^2 d^2 in normalised units, d the distance to the
 // closest point of the cube [c 2^-n, (c+1) 2^-n].  Written as the same FP64
@@ -213,13 +223,16 @@ __device__ inline TV march(const TV *__restrict__ grid, int G, unsigned ncell_m1
 // Walk used by the list export (entries only, no march).
 // ---------------------------------------------------------------------------
 template <int MODE>
-__global__ void __launch_bounds__(kThreads) list_kernel(Params P)
+__global__ void __launch_bounds__(kThreads) list_kernel(const Item *__restrict__ items, const int4 *__restrict__ tiles,
+                                                        int n_tiles)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int64_t it = tile * kWave + lane;
-    const bool valid = it < P.n_t;
-    if (tile * kWave >= P.n_t) return;
+    const int ti = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    if (ti >= n_tiles) return;
+    const int4 tile = tiles[ti];
+    const Item &P = items[__builtin_amdgcn_readfirstlane(tile.x)];
+    const int64_t it = (int64_t)tile.y + lane;
+    const bool valid = lane < tile.z;
     double u[3] = {0.0, 0.0, 0.0};
     unsigned orig = 0;
     int64_t self = -1;
@@ -311,34 +324,47 @@ __device__ inline void store_frac(unsigned &d, double f)
     d = q >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned)q;
 }
 
+template <int PREC, bool STATS, typename T, typename TF>
+__device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveLds<T, TF> &L, int *lds_ncell);
+
 template <int PREC, bool STATS>
-__global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
+__global__ void __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(PREC == START_FP64 ? 5 : 6))) rates_kernel(const Item *__restrict__ items,
+                                                         const int4 *__restrict__ tiles, int n_tiles)
 {
     using T = typename std::conditional<PREC == START_FP64, double, float>::type;
     using TF = typename std::conditional<PREC == START_FP64, double, unsigned>::type;
     __shared__ WaveLds<T, TF> lds_all[kWavesPerBlock];
     __shared__ int ncell_all[STATS ? kWavesPerBlock : 1][STATS ? kRing : 1];   // counter mode only
-    const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x >> 6;
-    WaveLds<T, TF> &L = lds_all[wv];
-    int *lds_ncell = ncell_all[STATS ? wv : 0];
-    // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
-    // run of Morton-ordered tiles so that its L2 sees neighbouring targets
-    const int64_t nb = gridDim.x;
-    const int64_t per_xcd = nb / 8;
-    int64_t blk = blockIdx.x;
+    // blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
+    // run of tiles (Morton-adjacent targets share nodes and grid lines in its L2)
+    const int nb = (int)gridDim.x;
+    const int per_xcd = nb / 8;
+    int blk = (int)blockIdx.x;
     if (per_xcd > 0 && blk < per_xcd * 8) blk = (blk & 7) * per_xcd + (blk >> 3);
-    const int64_t tile = blk * kWavesPerBlock + wv;
-    const int64_t it = tile * kWave + lane;
-    const bool valid = it < P.n_t;
-    if (tile * kWave >= P.n_t) return;
+    // wave-uniform: tile record and item table are read with scalar loads
+    const int ti = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + wv);
+    if (ti >= n_tiles) return;
+    const int4 tile = tiles[ti];
+    const int item = __builtin_amdgcn_readfirstlane(tile.x);
+    rates_tile<PREC, STATS, T, TF>(items[item], tile, lds_all[wv], ncell_all[STATS ? wv : 0]);
+}
+
+template <int PREC, bool STATS, typename T, typename TF>
+__device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveLds<T, TF> &L, int *lds_ncell)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t it = (int64_t)tile.y + lane;
+    const bool valid = lane < tile.z;
+    wave_sync();   // the previous tile's LDS reads are done
 
     const int G = P.G;
     const int gl = P.grid_log2;
     const int ncell_m1 = G * G * G - 1;
     double u[3] = {0.0, 0.0, 0.0};
     unsigned orig = 0;
-    int64_t self = -1;
+    int self = -1;   // source indices fit in 31 bits (n_s <= 2^30)
     {
         int bi[3] = {0, 0, 0};
         double fb[3] = {0.0, 0.0, 0.0};
@@ -346,7 +372,7 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
             const double4 p = P.tgt[it];
             const double x[3] = {p.x, p.y, p.z};
             orig = P.tgt_orig[it];
-            if (P.self_src) self = P.self_src[orig];
+            if (P.self_src) self = (int)P.self_src[orig];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double v = (x[k] - P.lo[k]) * P.inv_size;
@@ -478,7 +504,7 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
         const bool active = valid && node >= resume;
         if (kind == kKindLeaf) {
             const float lw = fp32 ? __uint_as_float(P.momq[node].w) : (float)(P.mom[node].w > 0.0);
-            push(active && (int64_t)P.ref[node] != self && lw > 0.f, node);
+            push(active && P.ref[node] != self && lw > 0.f, node);
             node += 1;
             continue;
         }
@@ -497,7 +523,7 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
                 const int f = P.first[node], cnt = P.count[node];
                 for (int q = f; q < f + cnt; ++q) {
                     const float qw = fp32 ? __uint_as_float(P.srcq[q].w) : (float)(P.src[q].w > 0.0);
-                    push(open && (int64_t)P.perm[q] != self && qw > 0.f, -q - 1);
+                    push(open && (int)P.perm[q] != self && qw > 0.f, -q - 1);
                 }
             }
             node += 1;
@@ -529,23 +555,80 @@ __global__ void __launch_bounds__(kThreads) rates_kernel(Params P)
     }
 }
 
-__global__ void __launch_bounds__(kThreads) check_self(int64_t n, const int64_t *self_src, int64_t n_src,
-                                                       unsigned *flags)
+// Batched target preparation: every target of every item gets the key
+// (item << 30 | 30-bit Morton key of its 1024^3 cell), so one radix sort
+// groups the targets by item and orders each item's targets along the Morton
+// curve (the order only affects speed: no target's result depends on its
+// neighbours).  Positions and self indices are validated on the way.
+__device__ inline unsigned spread10(unsigned v)
 {
-    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (j >= n) return;
-    const int64_t sv = self_src[j];
-    if (sv < -1 || sv >= n_src) atomicOr(flags, kFlagBadSelf);
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
 }
 
-__global__ void __launch_bounds__(kThreads) gather_targets(int64_t n, const unsigned *perm, const double *xyz,
-                                                           double4 *tgt)
+__device__ inline int item_of(int64_t g, int n_items, const int64_t *offsets)
 {
-    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (j >= n) return;
-    const unsigned o = perm[j];
-    tgt[j] = make_double4(xyz[o], xyz[n + o], xyz[2 * n + o], 0.0);
+    int lo = 0, hi = n_items - 1;   // last item with offsets[item] <= g
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offsets[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
+
+__global__ void __launch_bounds__(kThreads) batch_keys(int64_t n, int n_items, const int64_t *offsets,
+                                                       const Item *__restrict__ items, uint64_t *keys,
+                                                       unsigned *vals, unsigned *flags)
+{
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= n) return;
+    const int item = item_of(g, n_items, offsets);
+    const Item &I = items[item];
+    const int64_t j = g - offsets[item];
+    unsigned bad = 0, code = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double x = I.tgt_xyz[(int64_t)k * I.n_t + j];
+        double u = 0.0;
+        if (!isfinite(x)) {
+            bad |= kFlagNonFinite;
+        } else if (x < I.lo[k] || x > I.lo[k] + I.size) {
+            bad |= kFlagOutOfBox;
+        } else {
+            u = (x - I.lo[k]) * I.inv_size;
+            u = u > 1.0 ? 1.0 : u;
+        }
+        unsigned q = (unsigned)(u * 1024.0);
+        q = q > 1023u ? 1023u : q;
+        code |= spread10(q) << (2 - k);
+    }
+    if (I.self_src) {
+        const int64_t sv = I.self_src[j];
+        if (sv < -1 || sv >= I.n_src) bad |= kFlagBadSelf;
+    }
+    if (bad) atomicOr(flags, bad);
+    keys[g] = ((uint64_t)item << 30) | code;
+    vals[g] = (unsigned)g;
+}
+
+__global__ void __launch_bounds__(kThreads) batch_gather(int64_t n, const int64_t *offsets,
+                                                         const Item *__restrict__ items, const uint64_t *keys,
+                                                         const unsigned *vals, double4 *tgt, unsigned *tgt_orig)
+{
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n) return;
+    const int item = (int)(keys[k] >> 30);
+    const Item &I = items[item];
+    const int64_t j = (int64_t)vals[k] - offsets[item];
+    tgt[k] = make_double4(I.tgt_xyz[j], I.tgt_xyz[I.n_t + j], I.tgt_xyz[2 * I.n_t + j], 0.0);
+    tgt_orig[k] = (unsigned)j;
+}
+
 
 // FP32-path copies of the virtual sources: the centre as 32-bit fixed-point
 // coordinates of the box (resolution 2^-32 of the side, so the source end of
@@ -593,134 +676,188 @@ void make_fp32_tree(Tree *t, hipStream_t s)
     make_fp32_src<<<blocks_for(t->n_src), kThreads, 0, s>>>(t->n_src, t->src, t->mom, t->box, inv, t->srcq);
 }
 
-struct TargetScratch {
+// ------------------------------------------------------------------------
+// Batch launcher.  All items of a call share one sort of their targets and
+// one persistent launch per precision; a single start_compute_rates is a
+// batch of one item.
+// ------------------------------------------------------------------------
+namespace {
+
+struct BatchScratch {
     uint64_t *keys;
-    unsigned *idx;
+    unsigned *vals;
     double4 *tgt;
+    unsigned *tgt_orig;
+    Item *items;
+    int64_t *offsets;
+    int4 *tiles;
     void *radix_tmp;
 };
 
-size_t target_scratch_bytes(int64_t n)
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t stage_bytes(int n_items, int64_t n_tiles)
 {
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const int64_t nk = n > 1 ? n : 1;
-    return al(nk * sizeof(uint64_t)) + al(nk * sizeof(unsigned)) + al(nk * sizeof(double4)) +
-           al(radix_temp_bytes(nk)) + 256;
+    return al256((size_t)n_items * sizeof(Item)) + al256((size_t)(n_items + 1) * sizeof(int64_t)) +
+           al256((size_t)n_tiles * sizeof(int4));
 }
 
-static TargetScratch carve(void *base, int64_t n)
+BatchScratch carve_batch(void *base, int64_t n, int n_items, int64_t n_tiles)
 {
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const int64_t nk = n > 1 ? n : 1;
     char *q = (char *)base;
-    TargetScratch ts;
-    ts.keys = (uint64_t *)q;
-    q += al(nk * sizeof(uint64_t));
-    ts.idx = (unsigned *)q;
-    q += al(nk * sizeof(unsigned));
-    ts.tgt = (double4 *)q;
-    q += al(nk * sizeof(double4));
-    ts.radix_tmp = q;
-    return ts;
+    BatchScratch b;
+    b.items = (Item *)q;   // the staged block first: items, offsets, tiles
+    q += al256((size_t)n_items * sizeof(Item));
+    b.offsets = (int64_t *)q;
+    q += al256((size_t)(n_items + 1) * sizeof(int64_t));
+    b.tiles = (int4 *)q;
+    q += al256((size_t)n_tiles * sizeof(int4));
+    b.keys = (uint64_t *)q;
+    q += al256((size_t)nk * sizeof(uint64_t));
+    b.vals = (unsigned *)q;
+    q += al256((size_t)nk * sizeof(unsigned));
+    b.tgt = (double4 *)q;
+    q += al256((size_t)nk * sizeof(double4));
+    b.tgt_orig = (unsigned *)q;
+    q += al256((size_t)nk * sizeof(unsigned));
+    b.radix_tmp = q;
+    return b;
 }
 
-// Orders the targets by Morton key and gathers their positions (device).
-void prepare_targets(Ctx *c, const start_box &box, int64_t n_t, const double *tgt_xyz, const int64_t *self_src,
-                     int64_t n_src, void *scratch, hipStream_t s)
+template <int PREC, bool STATS>
+void launch_tiles(const Item *items, const int4 *tiles, int64_t n_tiles, hipStream_t s)
 {
-    TargetScratch ts = carve(scratch, n_t);
-    launch_keys(box, n_t, tgt_xyz, nullptr, ts.keys, ts.idx, c->d_flags, s);
-    if (self_src) check_self<<<blocks_for(n_t), kThreads, 0, s>>>(n_t, self_src, n_src, c->d_flags);
-    radix_sort_pairs(ts.keys, ts.idx, n_t, 63, ts.radix_tmp, s);
-    gather_targets<<<blocks_for(n_t), kThreads, 0, s>>>(n_t, ts.idx, tgt_xyz, ts.tgt);
-}
-
-static Params make_params(const Tree *t, const Grid *g, int64_t n_t, void *scratch, const int64_t *self_src,
-                          double theta, double sigma)
-{
-    TargetScratch ts = carve(scratch, n_t);
-    Params P;
-    memset(&P, 0, sizeof(P));
-    P.n_nodes = t->n_nodes;
-    P.geo = t->geo;
-    P.skip = t->skip;
-    P.first = t->first;
-    P.count = t->count;
-    P.ref = t->ref;
-    P.mom = t->mom;
-    P.momq = t->momq;
-    P.src = t->src;
-    P.srcq = t->srcq;
-    P.perm = t->perm;
-    if (g) {
-        P.grid = g->val;
-        P.gridf = g->valf;
-        P.G = g->G;
-        P.grid_log2 = g->grid_log2;
-    } else {
-        P.G = 1;
-        P.grid_log2 = 0;
-    }
-    P.frac_scale = ldexp(1.0, -(32 - P.grid_log2));
-    P.gs = (double)P.G / t->box.size;
-    for (int k = 0; k < 3; ++k) P.lo[k] = t->box.lo[k];
-    P.inv_size = 1.0 / t->box.size;
-    P.unit_cm = t->box.length_unit_cm;
-    P.cell_cm = t->box.size / P.G * t->box.length_unit_cm;
-    P.theta2 = theta * theta;
-    P.sigma = sigma;
-    P.n_t = n_t;
-    P.tgt = ts.tgt;
-    P.tgt_orig = ts.idx;
-    P.self_src = self_src;
-    return P;
-}
-
-static unsigned walk_blocks(int64_t n_t)
-{
-    const int64_t tiles = (n_t + kWave - 1) / kWave;
-    int64_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    int64_t blocks = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks >= 64) blocks = (blocks + 7) / 8 * 8;   // whole rounds over the 8 XCDs
-    return (unsigned)blocks;
+    rates_kernel<PREC, STATS><<<(unsigned)blocks, kThreads, 0, s>>>(items, tiles, (int)n_tiles);
 }
 
-void launch_rates(const Tree *t, const Grid *g, int64_t n_t, void *scratch, const int64_t *self_src,
-                  double theta, double sigma, int prec, void *gamma, hipStream_t s)
+}  // namespace
+
+size_t batch_stage_bytes(int n_items, int64_t n_tiles) { return stage_bytes(n_items, n_tiles); }
+
+size_t batch_scratch_bytes(int64_t n, int n_items, int64_t n_tiles)
 {
-    Params P = make_params(t, g, n_t, scratch, self_src, theta, sigma);
-    P.gamma = gamma;
-    if (prec == START_FP64)
-        rates_kernel<START_FP64, false><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
-    else
-        rates_kernel<START_FP32C, false><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
+    const int64_t nk = n > 1 ? n : 1;
+    return stage_bytes(n_items, n_tiles) + al256((size_t)nk * sizeof(uint64_t)) +
+           al256((size_t)nk * sizeof(unsigned)) + al256((size_t)nk * sizeof(double4)) +
+           al256((size_t)nk * sizeof(unsigned)) + al256(radix_temp_bytes(nk)) + 256;
 }
 
-void launch_counts(const Tree *t, int64_t n_t, void *scratch, const int64_t *self_src, double theta,
-                   int64_t *counts, hipStream_t s)
+int64_t batch_tiles(const RateSpec *specs, int n)
 {
-    Params P = make_params(t, nullptr, n_t, scratch, self_src, theta, 0.0);
-    P.counts = counts;
-    list_kernel<kCount><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
+    int64_t t = 0;
+    for (int i = 0; i < n; ++i) t += (specs[i].n_t + kWave - 1) / kWave;
+    return t;
 }
 
-void launch_lists(const Tree *t, int64_t n_t, void *scratch, const int64_t *self_src, double theta,
-                  const int64_t *offsets, int64_t *entries, hipStream_t s)
+// Enqueues a batch (the scratch and the pinned staging area must be large
+// enough: batch_scratch_bytes / stage_bytes).  mode: 0 rates, 1 counters,
+// 2 list counts, 3 lists.  ev0/ev1 (may be null) bracket the rate kernels.
+void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, void *scratch, hipEvent_t ev0, hipEvent_t ev1)
 {
-    Params P = make_params(t, nullptr, n_t, scratch, self_src, theta, 0.0);
-    P.offsets = offsets;
-    P.entries = entries;
-    list_kernel<kList><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
-}
+    hipStream_t s = c->stream;
+    int64_t N = 0;
+    for (int i = 0; i < n; ++i) N += specs[i].n_t;
+    const int64_t n_tiles = batch_tiles(specs, n);
+    BatchScratch bs = carve_batch(scratch, N, n, n_tiles);
 
-void launch_stats(const Tree *t, const Grid *g, int64_t n_t, void *scratch, const int64_t *self_src,
-                  double theta, int prec, int64_t *stats, hipStream_t s)
-{
-    Params P = make_params(t, g, n_t, scratch, self_src, theta, 1.0);
-    P.stats = stats;
-    if (prec == START_FP64)
-        rates_kernel<START_FP64, true><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
-    else
-        rates_kernel<START_FP32C, true><<<walk_blocks(n_t), kThreads, 0, s>>>(P);
+    // host side: item table, offsets, tiles (FP64 items' tiles first)
+    hipEventSynchronize(c->stage_ev);   // the previous upload has been read
+    char *h = (char *)c->host_stage;
+    Item *hi = (Item *)h;
+    int64_t *ho = (int64_t *)(h + al256((size_t)n * sizeof(Item)));
+    int4 *ht = (int4 *)(h + al256((size_t)n * sizeof(Item)) + al256((size_t)(n + 1) * sizeof(int64_t)));
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        const RateSpec &r = specs[i];
+        const Tree *t = r.tree;
+        const Grid *g = r.grid;
+        Item I;
+        memset(&I, 0, sizeof(I));
+        I.n_nodes = t->n_nodes;
+        I.n_src = t->n_src;
+        I.geo = t->geo;
+        I.skip = t->skip;
+        I.first = t->first;
+        I.count = t->count;
+        I.ref = t->ref;
+        I.mom = t->mom;
+        I.momq = t->momq;
+        I.src = t->src;
+        I.srcq = t->srcq;
+        I.perm = t->perm;
+        if (g) {
+            I.grid = g->val;
+            I.gridf = g->valf;
+            I.G = g->G;
+            I.grid_log2 = g->grid_log2;
+        } else {
+            I.G = 1;
+            I.grid_log2 = 0;
+        }
+        I.frac_scale = ldexp(1.0, -(32 - I.grid_log2));
+        I.gs = (double)I.G / t->box.size;
+        for (int k = 0; k < 3; ++k) I.lo[k] = t->box.lo[k];
+        I.size = t->box.size;
+        I.inv_size = 1.0 / t->box.size;
+        I.unit_cm = t->box.length_unit_cm;
+        I.cell_cm = t->box.size / I.G * t->box.length_unit_cm;
+        I.theta2 = r.theta * r.theta;
+        I.sigma = r.sigma;
+        I.n_t = r.n_t;
+        I.tgt_xyz = r.tgt_xyz;
+        I.tgt = bs.tgt + off;
+        I.tgt_orig = bs.tgt_orig + off;
+        I.self_src = r.self_src;
+        I.gamma = r.gamma;
+        I.counts = r.counts;
+        I.offsets = r.offsets;
+        I.entries = r.entries;
+        I.stats = r.stats;
+        hi[i] = I;
+        ho[i] = off;
+        off += r.n_t;
+    }
+    ho[n] = off;
+    int64_t t64 = 0;
+    for (int pass = 0; pass < 2; ++pass)   // FP64 items, then FP32C items
+        for (int i = 0; i < n; ++i) {
+            if ((specs[i].prec == START_FP64) != (pass == 0)) continue;
+            for (int64_t f = 0; f < specs[i].n_t; f += kWave)
+                ht[t64++] = make_int4(i, (int)f, (int)(specs[i].n_t - f < kWave ? specs[i].n_t - f : kWave), 0);
+        }
+    int64_t n64 = 0;
+    for (int i = 0; i < n; ++i)
+        if (specs[i].prec == START_FP64) n64 += (specs[i].n_t + kWave - 1) / kWave;
+    hipMemcpyAsync(bs.items, h, stage_bytes(n, n_tiles), hipMemcpyHostToDevice, s);
+    hipEventRecord(c->stage_ev, s);
+
+    if (N == 0) return;
+    const unsigned nb = (unsigned)((N + kThreads - 1) / kThreads);
+    batch_keys<<<nb, kThreads, 0, s>>>(N, n, bs.offsets, bs.items, bs.keys, bs.vals, c->d_flags);
+    int bits = 30;
+    while ((1 << (bits - 30)) < n) ++bits;
+    radix_sort_pairs(bs.keys, bs.vals, N, bits, bs.radix_tmp, s);
+    batch_gather<<<nb, kThreads, 0, s>>>(N, bs.offsets, bs.items, bs.keys, bs.vals, bs.tgt, bs.tgt_orig);
+
+    if (mode == 2 || mode == 3) {
+        const unsigned lb = (unsigned)((n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+        if (mode == 2) list_kernel<kCount><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
+        else list_kernel<kList><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
+        return;
+    }
+    if (ev0) hipEventRecord(ev0, s);
+    if (n64 > 0) {
+        if (mode == 1) launch_tiles<START_FP64, true>(bs.items, bs.tiles, n64, s);
+        else launch_tiles<START_FP64, false>(bs.items, bs.tiles, n64, s);
+    }
+    if (n_tiles - n64 > 0) {
+        if (mode == 1) launch_tiles<START_FP32C, true>(bs.items, bs.tiles + n64, n_tiles - n64, s);
+        else launch_tiles<START_FP32C, false>(bs.items, bs.tiles + n64, n_tiles - n64, s);
+    }
+    if (ev1) hipEventRecord(ev1, s);
 }
 
 }  // namespace start

@@ -364,3 +364,33 @@ def test_deterministic(ctx):
     b = ctx.compute_rates(tree, grid, dev(w.tgt_xyz), None, 1.0, w.sigma, "fp32c")
     ctx.synchronize()
     assert torch.equal(a, b)
+
+
+def test_batched_many_uneven_items_bitwise(ctx):
+    """One persistent launch over many uneven items (sizes, thetas, both
+    precisions, shared and separate trees) gives each item exactly what a
+    call of its own gives."""
+    rng = np.random.default_rng(3)
+    base = H.workload("small")
+    d = H.W.make_diffuse(seed=13, n_gas=5000)
+    t1, g1 = build(ctx, base)
+    t2, g2 = build(ctx, d)
+    items, singles = [], []
+    for k in range(23):
+        use_d = k % 3 == 0
+        w, t, g = (d, t2, g2) if use_d else (base, t1, g1)
+        n = int(rng.integers(1, 700))
+        idx = np.sort(rng.choice(w.n_tgt, size=n, replace=False))
+        tgt = dev(w.tgt_xyz[:, idx])
+        ss = dev(w.self_src[idx]) if use_d else None
+        theta = float(rng.choice([0.0, 0.4, 1.0, 1.3]))
+        prec = "fp64" if k % 2 else "fp32c"
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        out = torch.empty(n, dtype=dt, device="cuda")
+        items.append(dict(tree=t, grid=g, tgt_xyz=tgt, self_src=ss, theta=theta, sigma=w.sigma, prec=prec, out=out))
+        singles.append(ctx.compute_rates(t, g, tgt, ss, theta, w.sigma, prec).clone())
+    ctx.synchronize()
+    ctx.compute_rates_batched(items)
+    ctx.synchronize()
+    for it, ref in zip(items, singles):
+        assert torch.equal(it["out"], ref)
