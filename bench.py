@@ -106,6 +106,119 @@ def cpu_baseline(w, sample, seed=17):
             "rates_only_evals_per_s": len(idx) / (t3 - t2)}
 
 
+def make_scene_pool(n, seed, lo_log2=14, hi_log2=17):
+    """Scenes shaped like the served workload: N_p log-uniform, N_s in
+    {1, 64, N_p}, medium from one of the small / clumpy / diffuse generators."""
+    from paper_1005_5312_amd import serve
+    from paper_1005_5312_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    pool = []
+    for k in range(n):
+        n_p = int(round(2 ** rng.uniform(lo_log2, hi_log2)))
+        kind = ("small", "clumpy", "diffuse")[k % 3]
+        ns_kind = ("one", "64", "all")[(k // 3) % 3]
+        s = int(rng.integers(1 << 30))
+        if kind == "diffuse":
+            w = W.make_diffuse(seed=s, n_gas=n_p)
+            if ns_kind != "all":   # keep the star plus a few emitters
+                m = 1 if ns_kind == "one" else 64
+                keep = np.concatenate([rng.choice(n_p, size=m - 1, replace=False), [n_p]]) if m > 1 else [n_p]
+                w.src_xyz = np.ascontiguousarray(w.src_xyz[:, keep])
+                w.src_lum = np.ascontiguousarray(w.src_lum[keep])
+                w.self_src = None
+        else:
+            n_s = 1 if ns_kind == "one" else (64 if ns_kind == "64" else n_p)
+            w = (W.make_small if kind == "small" else W.make_clumpy)(seed=s, n_gas=n_p, n_src=n_s)
+        box_t = tuple(float(v) for v in w.box_lo)
+        from paper_1005_5312_amd import Box
+        pool.append((serve.Scene(("scene", k), Box(box_t, float(w.box_size), float(w.length_unit_cm)), w.src_xyz,
+                                 w.src_lum, w.gas_xyz, w.gas_h, w.gas_nhi, w.grid_log2), w))
+    return pool
+
+
+def serve_bench(lam, n_req, seed=5):
+    """Poisson arrivals at `lam` requests/s; each request asks for the rates of
+    every particle of a scene drawn from a resident pool."""
+    import threading
+    from paper_1005_5312_amd import serve
+    pool = make_scene_pool(6, seed)
+    ex = serve.GpuExecutor(0, n_slots=2)
+    srv = serve.Server(ex, hbm_budget=64 << 30, max_batch=32).start()
+    rng = np.random.default_rng(seed + 1)
+    # warm: build every scene once (resident afterwards)
+    for sc, w in pool:
+        srv.submit(serve.Request(sc, w.tgt_xyz, w.self_src, 1.0, w.sigma, "fp32c")).result()
+    srv.completed.clear()
+    gaps = rng.exponential(1.0 / lam, n_req)
+    picks = rng.integers(0, len(pool), n_req)
+    futs = []
+
+    def client():
+        t0 = time.perf_counter()
+        at = 0.0
+        for g, k in zip(gaps, picks):
+            at += g
+            d = t0 + at - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            sc, w = pool[k]
+            futs.append(srv.submit(serve.Request(sc, w.tgt_xyz, w.self_src, 1.0, w.sigma, "fp32c")))
+
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    for f in futs:
+        f.result(timeout=600)
+    srv.drain()
+    srv.stop()
+    st = srv.latency_stats()
+    st["arrival_rate_per_s"] = lam
+    st["scene_sizes"] = sorted(int(w.n_tgt) for _, w in pool)
+    return st
+
+
+def batch_bench(n_inst=256, n_p=1 << 14, seed=9, reps=3):
+    """n_inst instances of n_p targets in one batched call vs one call each."""
+    import torch
+    import paper_1005_5312_amd as S
+    pool = make_scene_pool(8, seed, lo_log2=14, hi_log2=14)
+    ctx = S.Context(0)
+    dev = torch.device("cuda", 0)
+    built = []
+    for sc, w in pool:
+        d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+        tree = ctx.build_source_tree(sc.box, d(w.src_xyz), d(w.src_lum))
+        grid = ctx.build_gas_grid(sc.box, d(w.gas_xyz), d(w.gas_h), d(w.gas_nhi), w.grid_log2)
+        built.append((tree, grid, d(w.tgt_xyz), None if w.self_src is None else d(w.self_src), w))
+    items = []
+    for k in range(n_inst):
+        tree, grid, tgt, ss, w = built[k % len(built)]
+        items.append(dict(tree=tree, grid=grid, tgt_xyz=tgt, self_src=ss, theta=1.0, sigma=w.sigma, prec="fp32c",
+                          out=torch.empty(w.n_tgt, dtype=torch.float32, device=dev)))
+    ctx.compute_rates_batched(items)
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.compute_rates_batched(items)
+    ctx.synchronize()
+    t_batched = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for it in items:
+            ctx.compute_rates_raw(it["tree"], it["grid"], it["tgt_xyz"], it["self_src"], 1.0, it["sigma"], "fp32c",
+                                  it["out"])
+    ctx.synchronize()
+    t_single = (time.perf_counter() - t0) / reps
+    n_total = sum(it["tgt_xyz"].shape[1] for it in items)
+    for tree, grid, *_ in built:
+        tree.free()
+        grid.free()
+    ctx.close()
+    return {"instances": n_inst, "targets_each": n_p, "batched_ms": t_batched * 1e3,
+            "one_call_each_ms": t_single * 1e3, "batched_evals_per_s": n_total / t_batched,
+            "one_call_each_evals_per_s": n_total / t_single}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +230,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rates-only", action="store_true",
                     help="time only the rate call (profiling runs)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving and batching measurements")
+    ap.add_argument("--serve-rates", default="10,100,1000", help="Poisson arrival rates swept (requests/s)")
+    ap.add_argument("--serve-requests", type=int, default=100, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -230,6 +346,15 @@ def main():
                 "algorithmic_bytes_per_launch": alg[prec], "kernel_avg_ms": round(kern[prec]["avg_ms"], 4)}
     ach64 = alg["fp64"] / (kern["fp64"]["avg_ms"] * 1e-3) / 1e9
 
+    serve_stats = batch_stats = None
+    if not args.no_serve and not args.rates_only:
+        log(f"[bench] batched launch: 256 instances of 2^14 targets")
+        batch_stats = batch_bench()
+        serve_stats = []
+        for lam in (float(v) for v in args.serve_rates.split(",") if v):
+            log(f"[bench] serving: Poisson arrivals at {lam}/s, {args.serve_requests} requests")
+            serve_stats.append(serve_bench(lam, args.serve_requests))
+
     cpu = None
     if not args.no_cpu_baseline and not args.rates_only:
         log(f"[bench] CPU baseline (oracle) on {args.cpu_sample} sampled targets")
@@ -261,6 +386,8 @@ def main():
                        "fp64_evals_per_s": rates["fp64"]["evals_per_s"],
                        "fp64_walk_kernel_ms": round(kern["fp64"]["avg_ms"], 4),
                        "fp64_roofline_frac": round(ach64 / HBM_PEAK_GBS, 4)},
+        "serve": serve_stats,
+        "batched": batch_stats,
         "work_per_target": {"opening_tests": float(c[:, 0].mean()), "entries": float(c[:, 1].mean()),
                             "grid_cells": float(c[:, 2].mean())},
         "source_sha": sha,

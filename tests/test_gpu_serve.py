@@ -1,0 +1,101 @@
+"""The rate server on the GPU: each request's result is the same alone and in
+the mix (bit for bit), and matches the oracle."""
+import threading
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests import gpu_common as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def make_scenes():
+    from paper_1005_5312_amd import serve
+    out = []
+    for key, w in (("small", H.W.make_small(seed=21)), ("diffuse", H.W.make_diffuse(seed=22, n_gas=1 << 13)),
+                   ("clumpy", H.W.make_clumpy(seed=23, n_gas=1 << 13, n_src=64))):
+        out.append((serve.Scene(key, H.box_of(w), w.src_xyz, w.src_lum, w.gas_xyz, w.gas_h, w.gas_nhi,
+                                w.grid_log2), w))
+    return out
+
+
+def make_requests(scenes, n, seed):
+    from paper_1005_5312_amd import serve
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(n):
+        sc, w = scenes[k % len(scenes)]
+        m = int(rng.integers(1, 1500))
+        idx = np.sort(rng.choice(w.n_tgt, size=m, replace=False))
+        ss = None if w.self_src is None else w.self_src[idx]
+        reqs.append(serve.Request(sc, np.ascontiguousarray(w.tgt_xyz[:, idx]), ss,
+                                  theta=float(rng.choice([0.5, 1.0])), sigma=w.sigma,
+                                  prec="fp64" if k % 3 == 0 else "fp32c"))
+    return reqs
+
+
+def test_alone_equals_mixed_and_oracle():
+    from paper_1005_5312_amd import serve
+    scenes = make_scenes()
+    ex = serve.GpuExecutor(0, n_slots=2)
+    # alone: one request at a time
+    alone = []
+    srv = serve.Server(ex, hbm_budget=8 << 30, max_batch=16).start()
+    for r in make_requests(scenes, 30, seed=1):
+        f = srv.submit(r)
+        alone.append(f.result(timeout=120))
+    srv.drain()
+    srv.stop()
+    # mixed: the same requests from two submitting threads at once
+    srv = serve.Server(ex, hbm_budget=8 << 30, max_batch=16).start()
+    reqs = make_requests(scenes, 30, seed=1)
+    futs = [None] * len(reqs)
+
+    def client(part):
+        for k in part:
+            futs[k] = srv.submit(reqs[k])
+
+    th = [threading.Thread(target=client, args=(range(i, len(reqs), 2),)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    mixed = [f.result(timeout=120) for f in futs]
+    srv.drain()
+    srv.stop()
+    for a, b in zip(alone, mixed):
+        assert a.dtype == b.dtype and np.array_equal(a, b)
+    stats = srv.latency_stats()
+    print(f"  mixed: {stats}")
+    assert stats["requests"] == 30
+    # a few against the oracle
+    for k in (0, 1, 5):
+        r = reqs[k]
+        w = dict((s.key, ww) for s, ww in scenes)[r.scene.key]
+        ob = H.obox_of(w)
+        want = O.rates(O.Tree(ob, w.src_xyz, w.src_lum), w.grid_log2,
+                       O.grid(ob, w.gas_xyz, w.gas_h, w.gas_nhi, w.grid_log2), r.tgt_xyz, r.self_src,
+                       r.theta, r.sigma)
+        rel, ab, _ = H.rel_errors(mixed[k].astype(np.float64), want)
+        assert rel <= (H.TOL_FP64 if r.prec == "fp64" else H.TOL_FP32C) and ab <= H.ABS_FLOOR
+
+
+def test_admission_under_a_small_budget():
+    """With room for about one scene and request at a time the server still
+    completes everything, in arrival order of admission."""
+    from paper_1005_5312_amd import serve
+    scenes = make_scenes()
+    ex = serve.GpuExecutor(0, n_slots=2)
+    need = max(ex.scene_bytes(s) for s, _ in scenes) + max(ex.request_bytes(r)
+                                                            for r in make_requests(scenes, 12, seed=4))
+    srv = serve.Server(ex, hbm_budget=int(need * 1.05), max_batch=4).start()
+    futs = [srv.submit(r) for r in make_requests(scenes, 12, seed=4)]
+    outs = [f.result(timeout=120) for f in futs]
+    srv.drain()
+    srv.stop()
+    assert all(o is not None and np.all(np.isfinite(o)) for o in outs)
+    assert srv.used <= srv.budget
