@@ -130,11 +130,10 @@ __device__ inline int lanes_below(uint64_t m)
 // parameters) is FP64 in both precisions: an FP32 ray parameter resolves a
 // crossing only to ~6e-8 of the ray length (1e-5 cell over 128 cells), which
 // times the optical depth of a dense cell (~200 per cell for the 200x clumps)
-// is above the 2e-4 target.  The parameter of the next plane on each axis is
-// recomputed from the plane index as t = o * inv + nfb (o = plane offset from
-// the target cell, nfb = -fb * inv), never accumulated.  The cell index moves
-// by the linear stride of the axis crossed.  TV is the type of the grid values
-// and of the sum: FP32 with Kahan compensation, or FP64.  Returns sum n_c dt.
+// is above the 2e-4 target.  The marching is from the target, so crossings
+// next to it come first and exactly.  The cell index moves by the linear
+// stride of the axis crossed.  TV is the type of the grid values and of the
+// sum: FP32 with Kahan compensation, or FP64.  Returns sum n_c dt.
 //
 // The loop ends: each step moves one axis to its next plane, and its
 // parameter then grows by a_k >= 1 / (2 G) (|D| is below 2G for points in the
@@ -142,36 +141,42 @@ __device__ inline int lanes_below(uint64_t m)
 // never wins the comparisons and an all-NaN state exits at once; max_steps
 // bounds the loop in any case.
 // ---------------------------------------------------------------------------
+// 1 / d for d > 0 to full FP64 precision: hardware reciprocal and two Newton
+// steps (the inputs are finite, normal magnitudes: ray components in cells).
+__device__ inline double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
 template <typename TV, bool STATS>
 __device__ inline TV march(const TV *__restrict__ grid, int G, unsigned ncell_m1, unsigned idx0, const double fb[3],
                            const double D[3], int &ncell)
 {
-    // Axis k crosses its planes at t = (p_k - fb_k) / D_k for D_k > 0 and
-    // t = -(p_k + fb_k) / D_k ... written for both signs as t = p_k a_k + c_k
-    // with a_k = |1 / D_k| and p_k = 1, 2, ... (D_k > 0) or 0, 1, ... (D_k < 0)
-    // counting the planes crossed so far.
+    // Axis k crosses its next plane at tn_k and every 1/|D_k| after it.  In
+    // FP64 stepping tn_k by a_k drifts by ~1 ulp per step: over the <= 3G
+    // steps of a ray that is ~1e-11 cell, far inside every tolerance.
     const int stride[3] = {G * G, G, 1};
-    double a[3], c[3], p[3], tn[3];
+    double a[3], tn[3];
     int ds[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         if (D[k] > 0.0) {
-            a[k] = 1.0 / D[k];
-            p[k] = 1.0;
-            c[k] = -fb[k] * a[k];
+            a[k] = recip(D[k]);
+            tn[k] = (1.0 - fb[k]) * a[k];
             ds[k] = stride[k];
         } else if (D[k] < 0.0) {
-            a[k] = -1.0 / D[k];
-            p[k] = 0.0;
-            c[k] = fb[k] * a[k];
+            a[k] = recip(-D[k]);
+            tn[k] = fb[k] * a[k];
             ds[k] = -stride[k];
         } else {
             a[k] = 0.0;
-            p[k] = 0.0;
-            c[k] = 2.0;   // never crossed
+            tn[k] = 2.0;   // never crossed
             ds[k] = 0;
         }
-        tn[k] = fma(p[k], a[k], c[k]);
     }
     unsigned idx = idx0;
     double t = 0.0;
@@ -203,16 +208,13 @@ __device__ inline TV march(const TV *__restrict__ grid, int G, unsigned ncell_m1
         t = m;
         if (c2 && c01) {
             idx += (unsigned)ds[0];
-            p[0] += 1.0;
-            tn[0] = fma(p[0], a[0], c[0]);
+            tn[0] += a[0];
         } else if (c2) {
             idx += (unsigned)ds[1];
-            p[1] += 1.0;
-            tn[1] = fma(p[1], a[1], c[1]);
+            tn[1] += a[1];
         } else {
             idx += (unsigned)ds[2];
-            p[2] += 1.0;
-            tn[2] = fma(p[2], a[2], c[2]);
+            tn[2] += a[2];
         }
         idx = idx > ncell_m1 ? ncell_m1 : idx;   // also catches a step below 0
     }
