@@ -141,6 +141,52 @@ start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const star
  * hold at once (for admission by memory). */
 size_t start_estimate_bytes(int64_t n_t, int64_t n_s, int64_t n_gas, int grid_log2, start_precision prec);
 
+/* ---- photoionisation equilibrium (pure hydrogen, static gas) ---- */
+
+/* Equilibrium neutral fraction of each particle for given rates: the
+ * ionisations per volume x n_H Gamma (Appendix A, eq. A2) balance the
+ * recombinations alpha (1 - x)^2 n_H^2 (n_e = n_p = (1 - x) n_H); alpha is the
+ * case-B coefficient under the on-the-spot approximation of section 2.1.  The
+ * root in [0, 1] is x = 2a / (2a + Gamma + sqrt(Gamma (Gamma + 4a))) with
+ * a = alpha n_H; a = Gamma = 0 gives x = 1.
+ *   n_h     [n] total hydrogen density, cm^-3, finite and >= 0
+ *   gamma   [n] rate per H I atom, s^-1: double (START_FP64) or float
+ *           (START_FP32C), finite and >= 0 (e.g. start_compute_rates output)
+ *   alpha   recombination coefficient, cm^3 s^-1, > 0
+ *   x_hi    [n] in: the previous neutral fraction; out: the new one
+ *   n_hi    [n] or NULL: receives x n_H (the n_HI of the next gas grid)
+ *   max_change  HOST pointer or NULL: receives max |x_new - x_old|; the call
+ *           then waits for the stream and reports bad device data itself
+ * Asynchronous when max_change is NULL; bad values in n_h, gamma or x_hi are
+ * then reported by the next start_synchronize (START_EINVAL). */
+start_status start_equilibrium_update(start_ctx *ctx, int64_t n, const double *n_h, const void *gamma,
+                                      start_precision gamma_prec, double alpha, double *x_hi, double *n_hi,
+                                      double *max_change);
+
+/* Photoionisation equilibrium of the gas around the fixed sources of `tree`,
+ * by fixed-point iteration: grid n_HI = x n_H (as start_build_gas_grid, on
+ * the tree's box), Gamma of every gas particle (as start_compute_rates with
+ * the particles as targets, no self term), then x from
+ * start_equilibrium_update; stop after the first iteration whose largest
+ * change of x is <= tol, or after max_iter.  From a neutral start the
+ * iterates decrease monotonically towards the equilibrium; for one source in
+ * uniform gas its ionised volume is the Stromgren sphere of eq. (17).
+ *   gas_xyz [3][n_gas], gas_h [n_gas] > 0, n_h [n_gas] >= 0 (cm^-3)
+ *   grid_log2 in [1, 10]; theta_crit, sigma_cm2 as start_compute_rates;
+ *   alpha > 0; prec: precision of the rate calls; max_iter >= 1; tol >= 0
+ *   x_hi [n_gas] in: initial neutral fraction in [0, 1]; out: the last iterate
+ *   gamma_out [n_gas] (double or float by prec): the rates the last iterate
+ *           was computed from
+ *   iterations, last_change (host, may be NULL): iterations run and the
+ *           largest change of the last one
+ * Synchronous (one stream synchronisation per iteration); allocates its
+ * grid, particle bins and one n_HI buffer for the duration of the call. */
+start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree, int64_t n_gas,
+                                          const double *gas_xyz, const double *gas_h, const double *n_h,
+                                          int grid_log2, double theta_crit, double sigma_cm2, double alpha,
+                                          start_precision prec, int max_iter, double tol, double *x_hi,
+                                          void *gamma_out, int *iterations, double *last_change);
+
 /* ---- parity and diagnostics (synchronous; buffers host or device) ---- */
 
 /* Tree in depth-first order.  *n_nodes (host) receives the node count; each

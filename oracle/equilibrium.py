@@ -1,0 +1,89 @@
+"""Photoionisation equilibrium on top of the rate checker.
+
+TEST INFRASTRUCTURE ONLY: the plain CPU FP64 definition that the HIP
+library's equilibrium update and equilibrium loop are compared against.  It
+shares no code with the HIP library; it calls only the checker in oracle.py.
+
+Physics (pure hydrogen, static gas, fixed temperature):
+
+* A particle with total hydrogen density n_H, neutral fraction x and
+  photoionisation rate per H I atom Gamma is in equilibrium when the
+  ionisations per unit volume, n_HI Gamma = x n_H Gamma (Appendix A, eq. A1
+  with eq. A2 for one frequency), balance the recombinations
+  alpha n_e n_p = alpha (1 - x)^2 n_H^2, with n_e = n_p = (1 - x) n_H.  Under
+  the on-the-spot approximation (section 2.1) alpha is the case-B
+  coefficient alpha_B.
+* The rates depend on x through the optical depths (n_HI = x n_H along every
+  ray), so the field is found by fixed-point iteration: n_HI -> gas grid ->
+  Gamma -> x -> n_HI ...  Starting from a neutral medium the iterates
+  decrease monotonically (more neutral gas means more absorption, smaller
+  Gamma and a larger equilibrium x), so the loop converges from above to the
+  equilibrium whose ionised volume the Stromgren radius of eq. (17)
+  describes.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import oracle as O
+
+
+def neutral_fraction(gamma, n_h, alpha):
+    """Equilibrium neutral fraction x in [0, 1] of  x Gamma = alpha n_H (1 - x)^2.
+
+    With a = alpha n_H the balance is the quadratic a x^2 - (2a + Gamma) x + a = 0.
+    Its two roots multiply to 1, so the one in [0, 1] is the reciprocal of the
+    larger root:  x = 2a / (2a + Gamma + sqrt(Gamma (Gamma + 4a))).
+    No ionisation and no recombination (a = Gamma = 0) leaves the gas neutral
+    (x = 1)."""
+    g = np.asarray(gamma, dtype=np.float64)
+    a = alpha * np.asarray(n_h, dtype=np.float64)
+    den = 2.0 * a + g + np.sqrt(g * (g + 4.0 * a))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        x = np.where(den > 0.0, 2.0 * a / den, 1.0)
+    return x
+
+
+def ionization_equilibrium(box, tree, gas_xyz, gas_h, n_h, x_init, grid_log2, theta, sigma, alpha,
+                           max_iter=100, tol=1e-4, history=False):
+    """Fixed-point iteration of the equilibrium field around the sources of
+    `tree`, with the gas particles as targets.
+
+    Each iteration grids n_HI = x n_H (section 2.1 kernel), evaluates Gamma for
+    every particle through the tree (eqs. 12-15, A2) and replaces x by
+    neutral_fraction(Gamma).  Stops after the first iteration whose largest
+    change |x_new - x| is <= tol, or after max_iter iterations.
+
+    Returns (x, gamma, iterations, last_change[, list of x after each
+    iteration]); gamma is the rate field the final x was computed from."""
+    x = np.array(x_init, dtype=np.float64, copy=True)
+    n_h = np.asarray(n_h, dtype=np.float64)
+    hist = []
+    change = np.inf
+    it = 0
+    gamma = None
+    while it < max_iter:
+        it += 1
+        g = O.grid(box, gas_xyz, gas_h, x * n_h, grid_log2)
+        gamma = O.rates(tree, grid_log2, g, gas_xyz, None, theta, sigma)
+        x_new = neutral_fraction(gamma, n_h, alpha)
+        change = float(np.max(np.abs(x_new - x))) if x.size else 0.0
+        x = x_new
+        if history:
+            hist.append(x.copy())
+        if change <= tol:
+            break
+    out = (x, gamma, it, change)
+    return out + (hist,) if history else out
+
+
+def ionised_volume_radius(x, volume_cm3):
+    """Radius (cm) of the sphere whose volume equals the ionised volume
+    sum_i (1 - x_i) V_i."""
+    v = float(np.sum((1.0 - np.asarray(x)) * np.asarray(volume_cm3)))
+    return (3.0 * v / (4.0 * np.pi)) ** (1.0 / 3.0)
+
+
+def photoionisations(x, gamma, n_h, volume_cm3):
+    """Photoionisations per second in the whole box, sum_i x_i n_H,i Gamma_i V_i."""
+    return float(np.sum(np.asarray(x) * np.asarray(n_h) * np.asarray(gamma) * np.asarray(volume_cm3)))

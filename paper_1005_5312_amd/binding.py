@@ -27,7 +27,8 @@ EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_s
            "start_bytes_in_use", "start_build_source_tree", "start_tree_free", "start_build_gas_grid",
            "start_grid_free", "start_grid_size", "start_compute_rates", "start_compute_rates_batched",
            "start_estimate_bytes", "start_tree_export", "start_interaction_lists", "start_grid_export",
-           "start_rate_counters", "start_profile_enable", "start_profile_read")
+           "start_rate_counters", "start_profile_enable", "start_profile_read", "start_equilibrium_update",
+           "start_ionization_equilibrium")
 
 
 class LibraryMissing(RuntimeError):
@@ -97,6 +98,9 @@ def lib():
         "start_rate_counters": ([P, P, P, i64, P, P, d, C.c_int, P], C.c_int),
         "start_profile_enable": ([P, C.c_int], C.c_int),
         "start_profile_read": ([P, P, P, P], C.c_int),
+        "start_equilibrium_update": ([P, i64, P, P, C.c_int, d, P, P, P], C.c_int),
+        "start_ionization_equilibrium": ([P, P, i64, P, P, P, C.c_int, d, d, d, C.c_int, C.c_int, d, P, P, P, P],
+                                         C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -307,6 +311,61 @@ class Context:
 
     def synchronize(self):
         self._check(lib().start_synchronize(self._h), "start_synchronize")
+
+    # --------------------------------------------------------- equilibrium --
+    def equilibrium_update(self, n_h, gamma, alpha: float, x_hi, n_hi=None, want_change: bool = True):
+        """x_hi (float64 device tensor, updated in place) <- equilibrium
+        neutral fraction for the rates gamma (float64 or float32); n_hi, if
+        given, <- x n_H.  Returns max |change| (waits for the stream) when
+        want_change, else None (asynchronous)."""
+        import torch
+        n = x_hi.numel()
+        nh = _vec(n_h, self.device)
+        if gamma.dtype == torch.float64:
+            p = FP64
+        elif gamma.dtype == torch.float32:
+            p = FP32C
+        else:
+            raise ValueError("gamma must be float64 or float32")
+        for t in (x_hi, n_hi):
+            if t is not None and (t.dtype != torch.float64 or t.numel() != n or not t.is_contiguous()
+                                  or t.device != torch.device(self.device)):
+                raise ValueError("x_hi and n_hi must be contiguous float64 tensors of n values on the device")
+        if nh.numel() != n or gamma.numel() != n or not gamma.is_contiguous():
+            raise ValueError("n_h and gamma must have one contiguous value per particle")
+        ch = C.c_double()
+        cur = self._enter(nh, gamma, x_hi, n_hi)
+        self._check(lib().start_equilibrium_update(self._h, n, _ptr(nh), _ptr(gamma), p, float(alpha), _ptr(x_hi),
+                                                   _ptr(n_hi), C.byref(ch) if want_change else None),
+                    "start_equilibrium_update")
+        self._leave(cur)
+        return ch.value if want_change else None
+
+    def ionization_equilibrium(self, tree: SourceTree, gas_xyz, gas_h, n_h, x_init, grid_log2: int,
+                               theta: float = 1.0, sigma: float = 6.3e-18, alpha: float = 2.6e-13,
+                               prec="fp64", max_iter: int = 100, tol: float = 1e-4):
+        """Fixed-point photoionisation equilibrium around the sources of
+        `tree` (see start_ionization_equilibrium).  Returns (x, gamma,
+        iterations, last_change); x float64, gamma float64 or float32."""
+        import torch
+        p = _prec(prec)
+        xyz = _xyz(gas_xyz, self.device)
+        n = xyz.shape[1]
+        h = _vec(gas_h, self.device)
+        nh = _vec(n_h, self.device)
+        x = _vec(x_init, self.device).clone()
+        if h.numel() != n or nh.numel() != n or x.numel() != n:
+            raise ValueError("gas_h, n_h and x_init need one value per particle")
+        gamma = torch.empty(n, dtype=torch.float64 if p == FP64 else torch.float32, device=self.device)
+        it, ch = C.c_int(), C.c_double()
+        cur = self._enter(xyz, h, nh, x, gamma)
+        self._check(lib().start_ionization_equilibrium(self._h, tree._h, n, _ptr(xyz), _ptr(h), _ptr(nh),
+                                                       int(grid_log2), float(theta), float(sigma), float(alpha), p,
+                                                       int(max_iter), float(tol), _ptr(x), _ptr(gamma),
+                                                       C.byref(it), C.byref(ch)),
+                    "start_ionization_equilibrium")
+        self._leave(cur)
+        return x, gamma, it.value, ch.value
 
     def profile(self, enable: bool = True):
         """Time every following walk kernel with HIP events on the context stream."""

@@ -237,6 +237,8 @@ start_status start_synchronize(start_ctx *ctx)
     if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
     if (!flags) return START_OK;
     hipMemset(ctx->c.d_flags, 0, sizeof(unsigned));
+    if (flags & kFlagEqInput)
+        return fail(ctx, START_EINVAL, "equilibrium input: n_H or Gamma negative or not finite, or x outside [0, 1]");
     if (flags & kFlagNonFinite) return fail(ctx, START_ENONFINITE, "non-finite target position");
     if (flags & kFlagOutOfBox) return fail(ctx, START_EOUTOFBOX, "target outside the box");
     return fail(ctx, START_EINVAL, "self_src index out of range");
@@ -368,6 +370,118 @@ start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const star
     if (specs.empty()) return START_OK;
     hipSetDevice(ctx->c.device);
     return enqueue(ctx, specs.data(), (int)specs.size(), 0);
+}
+
+start_status start_equilibrium_update(start_ctx *ctx, int64_t n, const double *n_h, const void *gamma,
+                                      start_precision gamma_prec, double alpha, double *x_hi, double *n_hi,
+                                      double *max_change)
+{
+    if (!ctx) return START_EINVAL;
+    if (n < 0) return fail(ctx, START_EINVAL, "n < 0");
+    if (n > ((int64_t)1 << 31) - 1) return fail(ctx, START_EINVAL, "n too large");
+    if (!std::isfinite(alpha)) return fail(ctx, START_ENONFINITE, "alpha not finite");
+    if (!(alpha > 0.0)) return fail(ctx, START_EINVAL, "alpha must be > 0");
+    if (gamma_prec != START_FP64 && gamma_prec != START_FP32C) return fail(ctx, START_EINVAL, "unknown precision");
+    if (n > 0 && (!n_h || !gamma || !x_hi)) return fail(ctx, START_EINVAL, "equilibrium arrays are NULL");
+    if (max_change) *max_change = 0.0;
+    if (n == 0) return START_OK;
+    hipSetDevice(ctx->c.device);
+    Ctx &c = ctx->c;
+    unsigned long long *word = nullptr;
+    if (max_change) {
+        start_status st = ensure_scratch(ctx, 256);
+        if (st) return st;
+        word = (unsigned long long *)c.scratch;
+        hipMemsetAsync(word, 0, sizeof(*word), c.stream);
+    }
+    launch_eq_update(&c, n, n_h, gamma, gamma_prec, alpha, x_hi, n_hi, word);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    if (!max_change) return START_OK;
+    unsigned long long bits = 0;
+    e = hipMemcpyAsync(&bits, word, sizeof(bits), hipMemcpyDeviceToHost, c.stream);
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    start_status st = start_synchronize(ctx);
+    if (st) return st;
+    std::memcpy(max_change, &bits, sizeof(double));
+    return START_OK;
+}
+
+start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree, int64_t n_gas,
+                                          const double *gas_xyz, const double *gas_h, const double *n_h,
+                                          int grid_log2, double theta_crit, double sigma_cm2, double alpha,
+                                          start_precision prec, int max_iter, double tol, double *x_hi,
+                                          void *gamma_out, int *iterations, double *last_change)
+{
+    if (iterations) *iterations = 0;
+    if (last_change) *last_change = 0.0;
+    if (!ctx) return START_EINVAL;
+    if (!tree) return fail(ctx, START_EINVAL, "tree is NULL");
+    if (n_gas < 0) return fail(ctx, START_EINVAL, "n_gas < 0");
+    if (n_gas > ((int64_t)1 << 31) - 1) return fail(ctx, START_EINVAL, "n_gas too large");
+    if (n_gas > 0 && (!gas_xyz || !gas_h || !n_h || !x_hi || !gamma_out))
+        return fail(ctx, START_EINVAL, "equilibrium arrays are NULL");
+    if (!std::isfinite(theta_crit) || !std::isfinite(sigma_cm2) || !std::isfinite(alpha) || !std::isfinite(tol))
+        return fail(ctx, START_ENONFINITE, "theta, sigma, alpha or tol not finite");
+    if (theta_crit < 0.0 || sigma_cm2 < 0.0 || !(alpha > 0.0) || tol < 0.0)
+        return fail(ctx, START_EINVAL, "theta, sigma and tol must be >= 0 and alpha > 0");
+    if (prec != START_FP64 && prec != START_FP32C) return fail(ctx, START_EINVAL, "unknown precision");
+    if (max_iter < 1) return fail(ctx, START_EINVAL, "max_iter must be >= 1");
+    if (grid_log2 < 1 || grid_log2 > 10) return fail(ctx, START_EINVAL, "grid_log2 must be in [1, 10]");
+    if (n_gas == 0) return START_OK;
+    hipSetDevice(ctx->c.device);
+    start_status st = start_synchronize(ctx);
+    if (st) return st;
+    Ctx &c = ctx->c;
+    const start_box box = tree->t.box;
+    double *nhi = nullptr;
+    const size_t nhi_bytes = (size_t)n_gas * sizeof(double) + 256;
+    if (dmalloc(&c, (void **)&nhi, nhi_bytes) != hipSuccess)
+        return fail(ctx, c.budget ? START_EBUDGET : START_ENOMEM, "equilibrium buffer allocation failed");
+    unsigned long long *word = (unsigned long long *)((char *)nhi + (size_t)n_gas * sizeof(double));
+    GasBins bins;
+    Grid grid;
+    bool have_grid = false, have_bins = false;
+    auto cleanup = [&](start_status code) {
+        hipStreamSynchronize(c.stream);
+        if (have_bins) free_bins(&c, &bins);
+        if (have_grid) dfree(&c, grid.val, grid.bytes);
+        dfree(&c, nhi, nhi_bytes);
+        return code;
+    };
+    launch_eq_prepare(&c, n_gas, n_h, x_hi, nhi);
+    st = start_synchronize(ctx);
+    if (st) return cleanup(st);
+    c.err.clear();
+    st = bin_gas(&c, box, n_gas, gas_xyz, gas_h, nhi, grid_log2, &bins);
+    if (st == START_ENOMEM && c.budget) st = START_EBUDGET;
+    if (st) return cleanup(st);
+    have_bins = true;
+    st = alloc_grid(&c, box, grid_log2, &grid);
+    if (st) return cleanup(fail(ctx, c.budget ? START_EBUDGET : START_ENOMEM, "grid allocation failed"));
+    have_grid = true;
+    start_grid gh;
+    gh.g = grid;
+    RateSpec r = spec_of(tree, &gh, n_gas, gas_xyz, nullptr, theta_crit, sigma_cm2, prec);
+    r.gamma = gamma_out;
+    for (int it = 1; it <= max_iter; ++it) {
+        fill_grid(&c, bins, it == 1 ? nullptr : nhi, &grid);
+        st = enqueue(ctx, &r, 1, 0);
+        if (st) return cleanup(st);
+        hipMemsetAsync(word, 0, sizeof(*word), c.stream);
+        launch_eq_update(&c, n_gas, n_h, gamma_out, prec, alpha, x_hi, nhi, word);
+        unsigned long long bits = 0;
+        hipError_t e = hipMemcpyAsync(&bits, word, sizeof(bits), hipMemcpyDeviceToHost, c.stream);
+        if (e != hipSuccess) return cleanup(fail(ctx, START_EHIP, hipGetErrorString(e)));
+        st = start_synchronize(ctx);
+        if (st) return cleanup(st);
+        double change;
+        std::memcpy(&change, &bits, sizeof(double));
+        if (iterations) *iterations = it;
+        if (last_change) *last_change = change;
+        if (change <= tol) break;
+    }
+    return cleanup(START_OK);
 }
 
 size_t start_estimate_bytes(int64_t n_t, int64_t n_s, int64_t n_gas, int grid_log2, start_precision prec)

@@ -65,6 +65,14 @@ __global__ void __launch_bounds__(kThreads) gather_particles(int64_t n, const un
     ns[k] = nhi[o];
 }
 
+__global__ void __launch_bounds__(kThreads) gather_values(int64_t n, const unsigned *perm, const double *nhi,
+                                                          double *ns)
+{
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n) return;
+    ns[k] = nhi[perm[k]];
+}
+
 // M4 cubic spline of section 2.1 with 3-D normalisation 1/(pi h^3).
 __device__ inline double kernel_w(double r, double h)
 {
@@ -122,11 +130,92 @@ __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double
 
 }  // namespace
 
-start_status build_grid(Ctx *c, const start_box &box, int64_t n, const double *xyz, const double *h,
-                        const double *nhi, int grid_log2, Grid *g)
+start_status bin_gas(Ctx *c, const start_box &box, int64_t n, const double *xyz, const double *h,
+                     const double *nhi, int grid_log2, GasBins *b)
 {
     hipStream_t s = c->stream;
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const int G = 1 << grid_log2;
+    const int64_t ncell = (int64_t)G * G * G;
+    *b = GasBins();
+    b->box = box;
+    b->n = n;
+    b->G = G;
+    b->delta = box.size / G;
+    if (n == 0) return START_OK;
+    const int64_t nk = n;
+    b->bytes = al(radix_temp_bytes(nk)) + al(nk * sizeof(uint64_t)) + al(nk * sizeof(unsigned)) +
+               al((ncell + 1) * sizeof(unsigned)) + al(scan_temp_bytes(ncell + 1)) + al(nk * sizeof(double4)) +
+               al(nk * sizeof(double)) + 256;
+    if (dmalloc(c, (void **)&b->mem, b->bytes) != hipSuccess) {
+        b->mem = nullptr;
+        return START_ENOMEM;
+    }
+    char *q = b->mem;
+    auto take = [&](size_t v) { char *r = q; q += al(v); return r; };
+    void *radix_tmp = take(radix_temp_bytes(nk));
+    uint64_t *keys = (uint64_t *)take(nk * sizeof(uint64_t));
+    b->idx = (unsigned *)take(nk * sizeof(unsigned));
+    b->start = (unsigned *)take((ncell + 1) * sizeof(unsigned));
+    void *scan_tmp = take(scan_temp_bytes(ncell + 1));
+    b->pos_h = (double4 *)take(nk * sizeof(double4));
+    b->ns = (double *)take(nk * sizeof(double));
+    unsigned long long *hmax = (unsigned long long *)take(256);
+
+    const double gs = (double)G / box.size;
+    unsigned *bflags = c->d_flags + 1;   // build validation word (not the rate calls' one)
+    hipMemsetAsync(bflags, 0, sizeof(unsigned), s);
+    hipMemsetAsync(hmax, 0, sizeof(unsigned long long), s);
+    grid_keys<<<blocks_for(n), kThreads, 0, s>>>(box, gs, G, n, xyz, h, nhi, keys, b->idx, bflags, hmax);
+    radix_sort_pairs(keys, b->idx, n, 3 * grid_log2, radix_tmp, s);
+    hipMemsetAsync(b->start, 0, (ncell + 1) * sizeof(unsigned), s);
+    cell_counts<<<blocks_for(n), kThreads, 0, s>>>(keys, n, b->start);
+    exclusive_scan_u32(b->start, ncell + 1, scan_tmp, s);
+    gather_particles<<<blocks_for(n), kThreads, 0, s>>>(n, b->idx, xyz, h, nhi, b->pos_h, b->ns);
+    unsigned flags = 0;
+    unsigned long long hbits = 0;
+    hipMemcpyAsync(&flags, bflags, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(&hbits, hmax, sizeof(hbits), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess || flags) {
+        free_bins(c, b);
+        if (e != hipSuccess) { c->err = hipGetErrorString(e); return START_EHIP; }
+        if (flags & kFlagNonFinite) { c->err = "non-finite gas position, h or n_HI"; return START_ENONFINITE; }
+        if (flags & kFlagOutOfBox) { c->err = "gas particle outside the box"; return START_EOUTOFBOX; }
+        c->err = "gas h <= 0 or n_HI < 0";
+        return START_EINVAL;
+    }
+    std::memcpy(&b->reach, &hbits, sizeof(double));
+    // a particle can reach a centre only from cells within ceil(reach/delta)
+    int R = (int)ceil(b->reach / b->delta);
+    b->R = R > G ? G : R;
+    return START_OK;
+}
+
+void free_bins(Ctx *c, GasBins *b)
+{
+    dfree(c, b->mem, b->bytes);
+    b->mem = nullptr;
+    b->bytes = 0;
+}
+
+void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g)
+{
+    hipStream_t s = c->stream;
+    const int64_t ncell = (int64_t)g->G * g->G * g->G;
+    if (b.n == 0) {
+        hipMemsetAsync(g->val, 0, ncell * sizeof(double), s);
+        hipMemsetAsync(g->valf, 0, ncell * sizeof(float), s);
+        return;
+    }
+    if (nhi) gather_values<<<blocks_for(b.n), kThreads, 0, s>>>(b.n, b.idx, nhi, b.ns);
+    shepard_gather<<<blocks_for(ncell), kThreads, 0, s>>>(b.box, b.delta, b.G, b.R, b.reach, b.start, b.pos_h,
+                                                           b.ns, g->val, g->valf);
+}
+
+start_status alloc_grid(Ctx *c, const start_box &box, int grid_log2, Grid *g)
+{
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     g->box = box;
     g->grid_log2 = grid_log2;
     const int G = 1 << grid_log2;
@@ -138,69 +227,26 @@ start_status build_grid(Ctx *c, const start_box &box, int64_t n, const double *x
     g->bytes = persist;
     g->val = (double *)pm;
     g->valf = (float *)(pm + al(ncell * sizeof(double)));
-    if (n == 0) {
-        hipMemsetAsync(g->val, 0, ncell * sizeof(double), s);
-        hipMemsetAsync(g->valf, 0, ncell * sizeof(float), s);
-        hipError_t e = hipStreamSynchronize(s);
-        return e == hipSuccess ? START_OK : START_EHIP;
-    }
-    const int64_t nk = n > 1 ? n : 1;
-    size_t tmp_bytes = al(radix_temp_bytes(nk)) + al(nk * sizeof(uint64_t)) + al(nk * sizeof(unsigned)) +
-                       al((ncell + 1) * sizeof(unsigned)) + al(scan_temp_bytes(ncell + 1)) +
-                       al(nk * sizeof(double4)) + al(nk * sizeof(double)) + 256;
-    char *tm = nullptr;
-    if (dmalloc(c, (void **)&tm, tmp_bytes) != hipSuccess) {
-        dfree(c, pm, persist);
-        return START_ENOMEM;
-    }
-    char *q = tm;
-    auto take = [&](size_t b) { char *r = q; q += al(b); return r; };
-    void *radix_tmp = take(radix_temp_bytes(nk));
-    uint64_t *keys = (uint64_t *)take(nk * sizeof(uint64_t));
-    unsigned *idx = (unsigned *)take(nk * sizeof(unsigned));
-    unsigned *startv = (unsigned *)take((ncell + 1) * sizeof(unsigned));
-    void *scan_tmp = take(scan_temp_bytes(ncell + 1));
-    double4 *pos_h = (double4 *)take(nk * sizeof(double4));
-    double *ns = (double *)take(nk * sizeof(double));
-    unsigned long long *hmax = (unsigned long long *)take(256);
+    return START_OK;
+}
 
-    const double gs = (double)G / box.size;
-    unsigned *bflags = c->d_flags + 1;   // build validation word (not the rate calls' one)
-    hipMemsetAsync(bflags, 0, sizeof(unsigned), s);
-    hipMemsetAsync(hmax, 0, sizeof(unsigned long long), s);
-    grid_keys<<<blocks_for(n), kThreads, 0, s>>>(box, gs, G, n, xyz, h, nhi, keys, idx, bflags, hmax);
-    radix_sort_pairs(keys, idx, n, 3 * grid_log2, radix_tmp, s);
-    hipMemsetAsync(startv, 0, (ncell + 1) * sizeof(unsigned), s);
-    cell_counts<<<blocks_for(n), kThreads, 0, s>>>(keys, n, startv);
-    exclusive_scan_u32(startv, ncell + 1, scan_tmp, s);
-    gather_particles<<<blocks_for(n), kThreads, 0, s>>>(n, idx, xyz, h, nhi, pos_h, ns);
-    unsigned flags = 0;
-    unsigned long long hbits = 0;
-    hipMemcpyAsync(&flags, bflags, sizeof(unsigned), hipMemcpyDeviceToHost, s);
-    hipMemcpyAsync(&hbits, hmax, sizeof(hbits), hipMemcpyDeviceToHost, s);
-    hipError_t e = hipStreamSynchronize(s);
-    if (e != hipSuccess || flags) {
-        dfree(c, tm, tmp_bytes);
-        dfree(c, pm, persist);
-        if (e != hipSuccess) { c->err = hipGetErrorString(e); return START_EHIP; }
-        if (flags & kFlagNonFinite) { c->err = "non-finite gas position, h or n_HI"; return START_ENONFINITE; }
-        if (flags & kFlagOutOfBox) { c->err = "gas particle outside the box"; return START_EOUTOFBOX; }
-        c->err = "gas h <= 0 or n_HI < 0";
-        return START_EINVAL;
+start_status build_grid(Ctx *c, const start_box &box, int64_t n, const double *xyz, const double *h,
+                        const double *nhi, int grid_log2, Grid *g)
+{
+    start_status st = alloc_grid(c, box, grid_log2, g);
+    if (st) return st;
+    GasBins b;
+    st = bin_gas(c, box, n, xyz, h, nhi, grid_log2, &b);
+    if (st) {
+        dfree(c, g->val, g->bytes);
+        return st;
     }
-    double reach;
-    std::memcpy(&reach, &hbits, sizeof(reach));
-    const double delta = box.size / G;
-    // a particle can reach a centre only from cells within ceil(reach/delta)
-    int R = (int)ceil(reach / delta);
-    if (R > G) R = G;
-    shepard_gather<<<blocks_for(ncell), kThreads, 0, s>>>(box, delta, G, R, reach, startv, pos_h, ns, g->val,
-                                                           g->valf);
-    e = hipStreamSynchronize(s);
-    dfree(c, tm, tmp_bytes);
+    fill_grid(c, b, nullptr, g);   // the binning already gathered n_HI
+    hipError_t e = hipStreamSynchronize(c->stream);
+    free_bins(c, &b);
     if (e != hipSuccess) {
         c->err = hipGetErrorString(e);
-        dfree(c, pm, persist);
+        dfree(c, g->val, g->bytes);
         return START_EHIP;
     }
     return START_OK;

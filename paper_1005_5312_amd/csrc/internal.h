@@ -21,6 +21,7 @@ constexpr unsigned kFlagNonFinite = 1u;
 constexpr unsigned kFlagOutOfBox = 2u;
 constexpr unsigned kFlagNegative = 4u;
 constexpr unsigned kFlagBadSelf = 8u;
+constexpr unsigned kFlagEqInput = 16u;    // equilibrium: n_H, Gamma or x out of range
 
 struct Ctx {
     int device = 0;
@@ -74,6 +75,33 @@ struct Grid {
     size_t bytes = 0;
 };
 
+// Gas particles counting-sorted into the cells of a G^3 grid, kept so that
+// the grid can be refilled for new n_HI values at the same positions.
+struct GasBins {
+    start_box box;
+    int64_t n = 0;
+    int G = 1;
+    int R = 0;                 // gather radius in cells
+    double reach = 0.0;        // largest kernel support 2h
+    double delta = 0.0;        // cell side
+    char *mem = nullptr;
+    size_t bytes = 0;
+    unsigned *idx = nullptr;   // binned order -> particle index
+    unsigned *start = nullptr; // first binned particle of each cell [G^3 + 1]
+    double4 *pos_h = nullptr;  // binned (x, y, z, h)
+    double *ns = nullptr;      // binned n_HI
+};
+
+// ---- gas grid (grid.hip) ----
+start_status alloc_grid(Ctx *c, const start_box &box, int grid_log2, Grid *g);
+// Validates and bins the particles (synchronises); n_HI is gathered too.
+start_status bin_gas(Ctx *c, const start_box &box, int64_t n, const double *xyz, const double *h,
+                     const double *nhi, int grid_log2, GasBins *b);
+void free_bins(Ctx *c, GasBins *b);
+// Enqueues the grid values from the binned particles; nhi (particle order,
+// not validated) replaces the binned n_HI first when non-null.
+void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g);
+
 // ---- memory helpers (count against the context budget) ----
 hipError_t dmalloc(Ctx *c, void **p, size_t bytes);
 void dfree(Ctx *c, void *p, size_t bytes);
@@ -111,6 +139,16 @@ size_t batch_scratch_bytes(int64_t n_targets, int n_items, int64_t n_tiles);
 size_t batch_stage_bytes(int n_items, int64_t n_tiles);
 int64_t batch_tiles(const RateSpec *specs, int n);
 void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, void *scratch, hipEvent_t ev0, hipEvent_t ev1);
+
+// ---- photoionisation equilibrium (equilibrium.hip) ----
+// x <- equilibrium neutral fraction for gamma (double or float by
+// gamma_prec); nhi (may be null) <- x n_H; max |change| folded into
+// *max_change (bits of a non-negative double; may be null).  Bad inputs set
+// kFlagEqInput in the context's flags word.
+void launch_eq_update(Ctx *c, int64_t n, const double *n_h, const void *gamma, int gamma_prec, double alpha,
+                      double *x, double *nhi, unsigned long long *max_change);
+// nhi <- x n_H after checking n_H >= 0 and x in [0, 1].
+void launch_eq_prepare(Ctx *c, int64_t n, const double *n_h, const double *x, double *nhi);
 
 // ---- Morton keys (tree.hip) ----
 void launch_keys(const start_box &box, int64_t n, const double *xyz, const double *lum,

@@ -21,6 +21,11 @@ from the paper is available):
 * ``shadow``    2^21 particles as ``diffuse`` plus 16 dense neutral clumps of
   200x overdensity and radius 0.05 box in one hemisphere around the star
   (the shadowing setting of Test 6, section 4.2.3).
+
+Equilibrium problems (``make_stromgren``) add the total hydrogen density of
+each particle and an initial neutral fraction: one 5e48 photons/s source at
+the centre of a 13.2 kpc box of uniform gas with n_H = 1e-3 cm^-3, the
+setting of Test 4 (section 4.2.1), whose Stromgren radius is 5.4 kpc (eq. 17).
 """
 from __future__ import annotations
 
@@ -166,6 +171,43 @@ def make_shadow(seed: int = 4, n_gas: int = 1 << 21, n_clumps: int = 16,
     self_src = np.arange(n_gas, dtype=np.int64)
     return Workload("shadow", np.zeros(3), L, KPC_CM, gas, smoothing_lengths(gas), nhi,
                     src, src_lum, gas, self_src, (1.0,), auto_grid_log2(n_gas))
+
+
+@dataclasses.dataclass
+class Equilibrium:
+    """A medium to bring into photoionisation equilibrium around fixed sources.
+
+    ``work`` holds the positions, smoothing lengths, sources and grid size
+    (its ``gas_nhi`` is the initial n_HI = x_init * n_h); ``n_h`` is the total
+    hydrogen density of each particle (cm^-3), ``x_init`` the initial neutral
+    fraction and ``volume_cm3`` the volume each particle stands for."""
+    work: Workload
+    n_h: np.ndarray
+    x_init: np.ndarray
+    volume_cm3: np.ndarray
+    alpha_b: float = ALPHA_B
+
+    def stromgren_radius_cm(self, n_h: float) -> float:
+        """R_s = (3 N / (4 pi n_H^2 alpha_B))^(1/3) of eq. (17) for the total
+        photon rate of all sources."""
+        q = float(self.work.src_lum.sum())
+        return (3.0 * q / (4.0 * math.pi * n_h * n_h * self.alpha_b)) ** (1.0 / 3.0)
+
+
+def make_stromgren(seed: int = 5, n_gas: int = 1 << 15, box_kpc: float = 13.2, lum: float = 5e48,
+                   n_h: float = 1e-3, x_ion0: float = 1.2e-3, grid_log2: int | None = None) -> Equilibrium:
+    """Test 4 (section 4.2.1): one source at the box centre in uniform static gas."""
+    rng = np.random.default_rng(seed)
+    L = box_kpc
+    gas = _uniform_positions(rng, n_gas, L)
+    c = np.full((3, 1), 0.5 * L)
+    nh = np.full(n_gas, n_h)
+    x0 = np.full(n_gas, 1.0 - x_ion0)
+    vol = np.full(n_gas, (L * KPC_CM) ** 3 / n_gas)
+    g = auto_grid_log2(n_gas) if grid_log2 is None else grid_log2
+    w = Workload("stromgren", np.zeros(3), L, KPC_CM, gas, smoothing_lengths(gas), x0 * nh,
+                 np.ascontiguousarray(c), np.array([lum]), gas, None, (1.0,), g)
+    return Equilibrium(w, nh, x0, vol)
 
 
 MAKERS = {"small": make_small, "clumpy": make_clumpy, "diffuse": make_diffuse,

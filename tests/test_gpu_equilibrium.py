@@ -1,0 +1,161 @@
+"""GPU equilibrium update and equilibrium loop (through the C-ABI) against
+the CPU checker in oracle/equilibrium.py."""
+import numpy as np
+import pytest
+
+from oracle import equilibrium as E
+from oracle import oracle as O
+from tests import gpu_common as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ALPHA = H.W.ALPHA_B
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1005_5312_amd import binding
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def update_inputs(n, seed, f32):
+    rng = np.random.default_rng(seed)
+    g = 10.0 ** rng.uniform(-24, -6, n)
+    g[rng.random(n) < 0.05] = 0.0
+    if f32:
+        g = g.astype(np.float32)
+    nh = 10.0 ** rng.uniform(-7, 3, n)
+    nh[rng.random(n) < 0.02] = 0.0
+    x0 = rng.random(n)
+    return g, nh, x0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("n", [1, 255, 100_003])
+def test_update_matches_oracle(ctx, prec, n):
+    g, nh, x0 = update_inputs(n, seed=11 + n, f32=(prec == "fp32c"))
+    dev = ctx.device
+    x = torch.from_numpy(x0.copy()).to(dev)
+    nhi = torch.empty(n, dtype=torch.float64, device=dev)
+    ch = ctx.equilibrium_update(torch.from_numpy(nh).to(dev), torch.from_numpy(g).to(dev), ALPHA, x, nhi)
+    got = x.cpu().numpy()
+    want = E.neutral_fraction(g.astype(np.float64), nh, ALPHA)
+    # same closed form in FP64 on both sides: a few ulp at most
+    assert np.all(np.abs(got - want) <= 4.5e-16 * np.abs(want)), np.max(np.abs(got - want) / np.maximum(want, 1e-300))
+    assert np.array_equal(nhi.cpu().numpy(), got * nh)
+    assert ch == np.max(np.abs(got - x0))
+
+
+def test_update_without_change_is_asynchronous(ctx):
+    g, nh, x0 = update_inputs(4096, seed=5, f32=False)
+    dev = ctx.device
+    x = torch.from_numpy(x0.copy()).to(dev)
+    assert ctx.equilibrium_update(torch.from_numpy(nh).to(dev), torch.from_numpy(g).to(dev), ALPHA, x,
+                                  want_change=False) is None
+    ctx.synchronize()
+    assert np.allclose(x.cpu().numpy(), E.neutral_fraction(g, nh, ALPHA), rtol=4.5e-16, atol=0)
+
+
+def test_update_input_errors(ctx):
+    from paper_1005_5312_amd import binding
+    dev = ctx.device
+    n = 1000
+    g, nh, x0 = update_inputs(n, seed=6, f32=False)
+    for bad_g, bad_nh in ((g, -nh), (np.where(np.arange(n) == 7, np.nan, g), nh), (-g, nh)):
+        x = torch.from_numpy(x0.copy()).to(dev)
+        with pytest.raises(binding.StartError) as ei:
+            ctx.equilibrium_update(torch.from_numpy(bad_nh).to(dev), torch.from_numpy(bad_g).to(dev), ALPHA, x)
+        assert ei.value.code == binding.EINVAL
+    ctx.synchronize()   # the error was reported once and cleared
+    with pytest.raises(binding.StartError):
+        ctx.equilibrium_update(torch.from_numpy(nh).to(dev), torch.from_numpy(g).to(dev), 0.0,
+                               torch.from_numpy(x0.copy()).to(dev))
+    # n = 0 is a no-op
+    e = torch.empty(0, dtype=torch.float64, device=dev)
+    assert ctx.equilibrium_update(e, e, ALPHA, e) == 0.0
+
+
+def loop_case(name):
+    if name == "stromgren":
+        e = H.W.make_stromgren(seed=5, n_gas=1 << 15, grid_log2=5)
+        return e.work, e.n_h, e.x_init, 1.0
+    w = H.W.make_small(seed=9, n_gas=4096, n_src=16)
+    return w, np.full(w.n_gas, 1e-3), np.ones(w.n_gas), 0.5
+
+
+def gpu_loop(ctx, w, nh, x0, theta, prec, max_iter, tol):
+    from paper_1005_5312_amd import binding
+    dev = ctx.device
+    tree = ctx.build_source_tree(H.box_of(w), torch.from_numpy(w.src_xyz).to(dev),
+                                 torch.from_numpy(w.src_lum).to(dev))
+    x, gam, it, ch = ctx.ionization_equilibrium(tree, w.gas_xyz, w.gas_h, nh, x0, w.grid_log2, theta=theta,
+                                                sigma=w.sigma, alpha=ALPHA, prec=prec, max_iter=max_iter, tol=tol)
+    assert isinstance(tree, binding.SourceTree)
+    return x.cpu().numpy(), gam.cpu().numpy().astype(np.float64), it, ch
+
+
+# Parity of whole loops: both sides start from the same neutral field and run
+# the same number of iterations, and are held to the tolerance of one rate
+# call.  For x the bound follows from the closed form: |d ln x / d ln Gamma|
+# = (1 - x) / (1 + x) <= 1, so a relative rate error e moves x by at most
+# x e <= e.  (Feeding x back into the optical depths could in principle
+# amplify errors from one iteration to the next; the printed errors show it
+# does not at these sizes.)
+LOOP_TOL = {"fp64": dict(gamma=H.TOL_FP64, x=H.TOL_FP64), "fp32c": dict(gamma=H.TOL_FP32C, x=H.TOL_FP32C)}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("name", ["stromgren", "small"])
+def test_loop_matches_oracle(ctx, name, prec):
+    w, nh, x0, theta = loop_case(name)
+    iters = 25 if name == "stromgren" else 10
+    x, gam, it, ch = gpu_loop(ctx, w, nh, x0, theta, prec, iters, 0.0)
+    box = H.obox_of(w)
+    tree = O.Tree(box, w.src_xyz, w.src_lum)
+    xo, go, ito, cho = E.ionization_equilibrium(box, tree, w.gas_xyz, w.gas_h, nh, x0, w.grid_log2, theta,
+                                                w.sigma, ALPHA, max_iter=iters, tol=0.0)
+    assert it == ito == iters
+    rel, ab, nbig = H.rel_errors(gam, go)
+    dx = float(np.max(np.abs(x - xo)))
+    print(f"  {name} {prec}: gamma rel {rel:.2e} (abs below floor {ab:.1e}), max |dx| {dx:.2e}, "
+          f"last change gpu {ch:.3e} oracle {cho:.3e}")
+    assert rel <= LOOP_TOL[prec]["gamma"] and ab <= H.ABS_FLOOR
+    assert dx <= LOOP_TOL[prec]["x"]
+
+
+def test_loop_converges_like_oracle(ctx):
+    w, nh, x0, theta = loop_case("stromgren")
+    x, gam, it, ch = gpu_loop(ctx, w, nh, x0, theta, "fp64", 300, 1e-3)
+    box = H.obox_of(w)
+    tree = O.Tree(box, w.src_xyz, w.src_lum)
+    xo, go, ito, cho = E.ionization_equilibrium(box, tree, w.gas_xyz, w.gas_h, nh, x0, w.grid_log2, theta,
+                                                w.sigma, ALPHA, max_iter=300, tol=1e-3)
+    print(f"  converged after {it} (oracle {ito}) iterations")
+    assert it == ito and ch <= 1e-3
+    assert float(np.max(np.abs(x - xo))) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_stromgren_sphere_full_size(ctx, prec):
+    """Test 4 at 2^21 particles on a 128^3 grid: properties that hold at any
+    size (the checker cannot run this many iterations here): a converged
+    field, the 5.4 kpc radius of eq. (17) within 5%, photon balance within
+    10%, ionised inside and neutral outside."""
+    import time
+    e = H.W.make_stromgren(seed=5, n_gas=1 << 21, grid_log2=7)
+    w = e.work
+    t0 = time.perf_counter()
+    x, gam, it, ch = gpu_loop(ctx, w, e.n_h, e.x_init, 1.0, prec, 200, 1e-4)
+    dt = time.perf_counter() - t0
+    r_eq = E.ionised_volume_radius(x, e.volume_cm3) / H.KPC
+    ph = E.photoionisations(x, gam, e.n_h, e.volume_cm3) / w.src_lum.sum()
+    print(f"  {prec}: {it} iterations in {dt:.2f} s, R_eq {r_eq:.3f} kpc, photons {ph:.4f}")
+    assert ch <= 1e-4 and it < 200
+    assert abs(r_eq / 5.4 - 1.0) <= 0.05
+    assert abs(ph - 1.0) <= 0.10
+    r = np.sqrt(((w.gas_xyz - 0.5 * w.box_size) ** 2).sum(axis=0))
+    assert np.mean(x[r < 3.0]) < 0.02 and np.mean(x[r > 6.2]) > 0.99
