@@ -219,6 +219,48 @@ def batch_bench(n_inst=256, n_p=1 << 14, seed=9, reps=3):
             "one_call_each_evals_per_s": n_total / t_single}
 
 
+def equilibrium_bench(n_gas=1 << 21, grid_log2=7, tol=1e-4, max_iter=200):
+    """Photoionisation equilibrium around one source (Test 4 setting) by the
+    library's fixed-point loop, in both precisions: iterations, time, and the
+    ionised radius against the Stromgren radius of eq. (17)."""
+    import torch
+    import paper_1005_5312_amd as S
+    from paper_1005_5312_amd import workloads as W
+    e = W.make_stromgren(n_gas=n_gas, grid_log2=grid_log2)
+    w = e.work
+    ctx = S.Context(0)
+    dev = torch.device("cuda", 0)
+    box = S.Box(tuple(float(v) for v in w.box_lo), float(w.box_size), float(w.length_unit_cm))
+    tree = ctx.build_source_tree(box, torch.from_numpy(w.src_xyz).to(dev), torch.from_numpy(w.src_lum).to(dev))
+    xyz = torch.from_numpy(w.gas_xyz).to(dev)
+    h = torch.from_numpy(w.gas_h).to(dev)
+    nh = torch.from_numpy(e.n_h).to(dev)
+    x0 = torch.from_numpy(e.x_init).to(dev)
+    out = {"workload": f"Test 4: one 5e48 photons/s source at the centre of a {w.box_size} kpc box, "
+                       f"uniform n_H = 1e-3, {n_gas} particles, G = {1 << grid_log2}",
+           "stromgren_radius_kpc": e.stromgren_radius_cm(1e-3) / W.KPC_CM}
+    for prec in ("fp32c", "fp64"):
+        ctx.ionization_equilibrium(tree, xyz, h, nh, x0, grid_log2, 1.0, w.sigma, e.alpha_b, prec, 2, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, gam, it, ch = ctx.ionization_equilibrium(tree, xyz, h, nh, x0, grid_log2, 1.0, w.sigma, e.alpha_b, prec,
+                                                    max_iter, tol)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        xn, gn = x.cpu().numpy(), gam.cpu().numpy().astype(np.float64)
+        # radius of the sphere with the ionised volume sum (1 - x) V, and the
+        # photoionisations per second sum x n_H Gamma V over the source rate
+        r_ion = (3.0 * float(np.sum((1.0 - xn) * e.volume_cm3)) / (4.0 * np.pi)) ** (1.0 / 3.0)
+        ph = float(np.sum(xn * e.n_h * gn * e.volume_cm3)) / float(w.src_lum.sum())
+        out[prec] = {"iterations": it, "last_change": ch, "ms_total": dt * 1e3, "ms_per_iteration": dt * 1e3 / it,
+                     "particle_updates_per_s": n_gas * it / dt, "ionised_radius_kpc": r_ion / W.KPC_CM,
+                     "photoionisations_over_source_rate": ph}
+        log(f"[bench] equilibrium {prec}: {it} iterations, {dt * 1e3:.1f} ms")
+    tree.free()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +275,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving and batching measurements")
     ap.add_argument("--serve-rates", default="10,100,1000", help="Poisson arrival rates swept (requests/s)")
     ap.add_argument("--serve-requests", type=int, default=100, help="requests per arrival rate")
+    ap.add_argument("--no-equilibrium", action="store_true", help="skip the equilibrium-loop measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -355,6 +398,11 @@ def main():
             log(f"[bench] serving: Poisson arrivals at {lam}/s, {args.serve_requests} requests")
             serve_stats.append(serve_bench(lam, args.serve_requests))
 
+    eq_stats = None
+    if not args.no_equilibrium and not args.rates_only:
+        log("[bench] photoionisation equilibrium (Test 4 setting)")
+        eq_stats = equilibrium_bench()
+
     cpu = None
     if not args.no_cpu_baseline and not args.rates_only:
         log(f"[bench] CPU baseline (oracle) on {args.cpu_sample} sampled targets")
@@ -388,6 +436,7 @@ def main():
                        "fp64_roofline_frac": round(ach64 / HBM_PEAK_GBS, 4)},
         "serve": serve_stats,
         "batched": batch_stats,
+        "equilibrium": eq_stats,
         "work_per_target": {"opening_tests": float(c[:, 0].mean()), "entries": float(c[:, 1].mean()),
                             "grid_cells": float(c[:, 2].mean())},
         "source_sha": sha,
