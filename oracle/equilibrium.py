@@ -87,3 +87,39 @@ def ionised_volume_radius(x, volume_cm3):
 def photoionisations(x, gamma, n_h, volume_cm3):
     """Photoionisations per second in the whole box, sum_i x_i n_H,i Gamma_i V_i."""
     return float(np.sum(np.asarray(x) * np.asarray(n_h) * np.asarray(gamma) * np.asarray(volume_cm3)))
+
+
+# ---------------------------------------------------------------------------
+# Transfer of recombination photons (section 4.1)
+# ---------------------------------------------------------------------------
+
+def recombination_emission(n_h, x, volume_cm3, alpha_1):
+    """Recombination photons per second emitted by each particle, eq. (19):
+    alpha_1 n_e n_p V with n_e = n_p = (1 - x) n_H and alpha_1 = alpha_A -
+    alpha_B the coefficient of recombinations to the ground state."""
+    ne = (1.0 - np.asarray(x, dtype=np.float64)) * np.asarray(n_h, dtype=np.float64)
+    return alpha_1 * ne * ne * np.asarray(volume_cm3, dtype=np.float64)
+
+
+def self_optical_depth(n_h, x, volume_cm3, sigma):
+    """Optical depth from the edge to the centre of a particle, eq. (28):
+    sigma n_HI (3 V / (4 pi))^(1/3)."""
+    nhi = np.asarray(x, dtype=np.float64) * np.asarray(n_h, dtype=np.float64)
+    return sigma * nhi * np.cbrt(3.0 * np.asarray(volume_cm3, dtype=np.float64) / (4.0 * np.pi))
+
+
+def k_self(n_h, x, volume_cm3, sigma, alpha_1):
+    """Ionisations per unit volume and time by a particle's own recombination
+    photons, eq. (30) for one frequency (from eqs. 27-29 with a flat source
+    function): alpha_1 n_e n_p (1 - exp(-tau)), with
+    1 - exp(-tau) evaluated as -expm1(-tau) (no cancellation at small tau)."""
+    ne = (1.0 - np.asarray(x, dtype=np.float64)) * np.asarray(n_h, dtype=np.float64)
+    tau = self_optical_depth(n_h, x, volume_cm3, sigma)
+    return alpha_1 * ne * ne * (-np.expm1(-tau))
+
+
+def k_ion_total(gamma_other, n_h, x, k_self_values):
+    """Eq. (25): k_ion = k_self + k_other, with k_other = n_HI Gamma (eq. 26,
+    Gamma the rate per H I atom from every other emitter, eq. A2)."""
+    return np.asarray(x, dtype=np.float64) * np.asarray(n_h, dtype=np.float64) * \
+        np.asarray(gamma_other, dtype=np.float64) + np.asarray(k_self_values, dtype=np.float64)

@@ -109,3 +109,83 @@ def test_iterates_fall_monotonically_small():
     assert np.all(hist[0] <= x0)
     for k in range(len(hist) - 1):
         assert np.all(hist[k + 1] <= hist[k] + 1e-15)
+
+
+# --- recombination photons: eq. (19), eqs. (27)-(30), eq. (25) -------------
+
+def test_k_self_closed_form_equals_the_transfer_integral():
+    """Eq. (27) with the constant one-frequency source function of eq. (29),
+    S / (h nu) = alpha_1 n_e n_p / (4 pi n_HI sigma), integrated numerically
+    over tau' in [0, tau], equals the closed form of eq. (30)."""
+    from scipy.integrate import quad
+    alpha_1, sigma = 1.58e-13, 6.3e-18
+    for n_h, x, vol in ((1e-3, 0.5, 1e60), (1.0, 0.01, 3e55), (1e-2, 0.9, 7.2e60), (1e-3, 1e-3, 1e58)):
+        ne = (1 - x) * n_h
+        nhi = x * n_h
+        tau = E.self_optical_depth(n_h, x, vol, sigma)
+        s_over_hnu = alpha_1 * ne * ne / (4 * math.pi * nhi * sigma)
+        val, _ = quad(lambda tp: s_over_hnu * sigma * math.exp(-tau + tp), 0.0, tau, epsabs=0, epsrel=1e-13)
+        want = 4 * math.pi * nhi * val
+        got = float(E.k_self(n_h, x, vol, sigma, alpha_1))
+        assert abs(got - want) <= 1e-11 * want, (got, want)
+
+
+def test_k_self_limits_and_self_depth():
+    alpha_1, sigma = 1.58e-13, 6.3e-18
+    # V of a sphere of radius R: tau = sigma n_HI R exactly
+    R = 2.5e20
+    vol = 4.0 / 3.0 * math.pi * R ** 3
+    assert abs(float(E.self_optical_depth(1e-3, 0.4, vol, sigma)) / (sigma * 4e-4 * R) - 1) <= 1e-15
+    # very opaque: every recombination photon is absorbed in place, k_self =
+    # alpha_1 n_e n_p (the limit stated after eq. 30)
+    k = float(E.k_self(10.0, 0.5, vol, sigma, alpha_1))
+    assert k == alpha_1 * 25.0
+    # optically thin: k_self = alpha_1 n_e n_p tau to first order
+    k = float(E.k_self(1e-9, 0.5, vol, sigma, alpha_1))
+    tau = sigma * 0.5e-9 * R
+    assert abs(k / (alpha_1 * (0.5e-9) ** 2 * tau) - 1) <= 1e-6
+    # no neutral gas: nothing to absorb; fully neutral: nothing to emit
+    assert float(E.k_self(1e-3, 0.0, vol, sigma, alpha_1)) == 0.0
+    assert float(E.k_self(1e-3, 1.0, vol, sigma, alpha_1)) == 0.0
+
+
+def test_emission_and_total_rate():
+    alpha_1 = 1.58e-13
+    n = 1000
+    rng = np.random.default_rng(3)
+    x = rng.random(n)
+    nh = 10.0 ** rng.uniform(-4, 0, n)
+    vol = 10.0 ** rng.uniform(55, 62, n)
+    em = E.recombination_emission(nh, x, vol, alpha_1)
+    assert np.allclose(em, alpha_1 * ((1 - x) * nh) ** 2 * vol, rtol=1e-15, atol=0)
+    g = 10.0 ** rng.uniform(-20, -10, n)
+    ks = E.k_self(nh, x, vol, 6.3e-18, alpha_1)
+    kt = E.k_ion_total(g, nh, x, ks)
+    assert np.allclose(kt, x * nh * g + ks, rtol=1e-15, atol=0)
+
+
+def test_opaque_medium_total_rate_is_alpha_1_ne_np():
+    """The statement after eq. (30): in a medium opaque everywhere, k_self +
+    k_other = alpha_1 n_e n_p, i.e. the net recombination coefficient is
+    alpha_B.  Uniform gas of 4096 particles in a 1 kpc box at n_H = 1, x = 0.5
+    (tau from edge to centre of a particle ~380): k_other from every other
+    particle's emission through the tree is negligible, except between the
+    few random pairs much closer than the mean spacing."""
+    w = W.make_small(seed=4, n_gas=4096, n_src=1)
+    L = 1.0
+    gas = w.gas_xyz / w.box_size * L
+    from paper_1005_5312_amd.workloads import smoothing_lengths
+    h = smoothing_lengths(gas)
+    box = O.make_box(np.zeros(3), L, W.KPC_CM)
+    nh = np.full(w.n_gas, 1.0)
+    x = np.full(w.n_gas, 0.5)
+    vol = np.full(w.n_gas, (L * W.KPC_CM) ** 3 / w.n_gas)
+    alpha_1, sigma = 1.58e-13, 6.3e-18
+    lum = E.recombination_emission(nh, x, vol, alpha_1)
+    tree = O.Tree(box, gas, lum)
+    g = O.grid(box, gas, h, x * nh, 4)
+    gam = O.rates(tree, 4, g, gas, np.arange(w.n_gas), 1.0, sigma)
+    kt = E.k_ion_total(gam, nh, x, E.k_self(nh, x, vol, sigma, alpha_1))
+    r = kt / (alpha_1 * 0.25) - 1.0
+    assert np.all(r >= -1e-15) and np.all(r <= 0.01)
+    assert np.mean(np.abs(r) <= 1e-12) >= 0.99
