@@ -187,6 +187,33 @@ start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree
                                           start_precision prec, int max_iter, double tol, double *x_hi,
                                           void *gamma_out, int *iterations, double *last_change);
 
+/* ---- transfer of recombination photons (section 4.1) ---- */
+
+/* Per particle, with n_e = n_p = (1 - x) n_H:
+ *   lum_out    [n] or NULL: recombination photons per second to the ground
+ *              state, alpha_1 n_e n_p V (eq. 19; alpha_1 = alpha_A - alpha_B),
+ *              the luminosity of the particle as an emitter (source tree)
+ *   k_self_out [n] or NULL: ionisations per cm^3 per s by the particle's own
+ *              photons, alpha_1 n_e n_p (1 - exp(-tau)) (eq. 30), with
+ *              tau = sigma n_HI (3 V / (4 pi))^(1/3) from its edge to its
+ *              centre (eq. 28)
+ * n_h [n] >= 0 (cm^-3), x_hi [n] neutral fraction in [0, 1], volume_cm3 [n]
+ * >= 0; sigma_cm2, alpha_1 >= 0.  Asynchronous; bad values in the arrays are
+ * reported by the next start_synchronize (START_EINVAL). */
+start_status start_recombination_emission(start_ctx *ctx, int64_t n, const double *n_h, const double *x_hi,
+                                          const double *volume_cm3, double sigma_cm2, double alpha_1,
+                                          double *lum_out, double *k_self_out);
+
+/* Total photoionisations per cm^3 per s of each particle, eq. (25):
+ * k_ion = k_other + k_self with k_other = x n_H Gamma (eq. 26), Gamma [n] the
+ * rate per H I atom from every other emitter (start_compute_rates with
+ * self_src set; double for START_FP64, float for START_FP32C); k_self [n] or
+ * NULL (= 0).  k_ion_out [n] double.  Asynchronous; bad values are reported
+ * by the next start_synchronize (START_EINVAL). */
+start_status start_total_ionization(start_ctx *ctx, int64_t n, const double *n_h, const double *x_hi,
+                                    const void *gamma, start_precision gamma_prec, const double *k_self,
+                                    double *k_ion_out);
+
 /* ---- parity and diagnostics (synchronous; buffers host or device) ---- */
 
 /* Tree in depth-first order.  *n_nodes (host) receives the node count; each

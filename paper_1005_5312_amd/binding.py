@@ -28,7 +28,7 @@ EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_s
            "start_grid_free", "start_grid_size", "start_compute_rates", "start_compute_rates_batched",
            "start_estimate_bytes", "start_tree_export", "start_interaction_lists", "start_grid_export",
            "start_rate_counters", "start_profile_enable", "start_profile_read", "start_equilibrium_update",
-           "start_ionization_equilibrium")
+           "start_ionization_equilibrium", "start_recombination_emission", "start_total_ionization")
 
 
 class LibraryMissing(RuntimeError):
@@ -101,6 +101,8 @@ def lib():
         "start_equilibrium_update": ([P, i64, P, P, C.c_int, d, P, P, P], C.c_int),
         "start_ionization_equilibrium": ([P, P, i64, P, P, P, C.c_int, d, d, d, C.c_int, C.c_int, d, P, P, P, P],
                                          C.c_int),
+        "start_recombination_emission": ([P, i64, P, P, P, d, d, P, P], C.c_int),
+        "start_total_ionization": ([P, i64, P, P, P, C.c_int, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -340,6 +342,45 @@ class Context:
                     "start_equilibrium_update")
         self._leave(cur)
         return ch.value if want_change else None
+
+    def recombination_emission(self, n_h, x_hi, volume_cm3, sigma: float = 6.3e-18, alpha_1: float = 1.58e-13,
+                               want_lum: bool = True, want_k_self: bool = True):
+        """(emitter luminosity alpha_1 n_e n_p V, k_self) per particle as
+        float64 device tensors (None where not asked for).  Asynchronous."""
+        import torch
+        nh, x, v = (_vec(t, self.device) for t in (n_h, x_hi, volume_cm3))
+        n = nh.numel()
+        if x.numel() != n or v.numel() != n:
+            raise ValueError("n_h, x_hi and volume_cm3 need one value per particle")
+        lum = torch.empty(n, dtype=torch.float64, device=self.device) if want_lum else None
+        ks = torch.empty(n, dtype=torch.float64, device=self.device) if want_k_self else None
+        cur = self._enter(nh, x, v, lum, ks)
+        self._check(lib().start_recombination_emission(self._h, n, _ptr(nh), _ptr(x), _ptr(v), float(sigma),
+                                                       float(alpha_1), _ptr(lum), _ptr(ks)),
+                    "start_recombination_emission")
+        self._leave(cur)
+        return lum, ks
+
+    def total_ionization(self, n_h, x_hi, gamma, k_self=None):
+        """k_ion = x n_H gamma + k_self (float64 device tensor).  Asynchronous."""
+        import torch
+        nh, x = _vec(n_h, self.device), _vec(x_hi, self.device)
+        n = nh.numel()
+        if gamma.dtype == torch.float64:
+            p = FP64
+        elif gamma.dtype == torch.float32:
+            p = FP32C
+        else:
+            raise ValueError("gamma must be float64 or float32")
+        ks = None if k_self is None else _vec(k_self, self.device)
+        if x.numel() != n or gamma.numel() != n or (ks is not None and ks.numel() != n) or not gamma.is_contiguous():
+            raise ValueError("every array needs one contiguous value per particle")
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        cur = self._enter(nh, x, gamma, ks, out)
+        self._check(lib().start_total_ionization(self._h, n, _ptr(nh), _ptr(x), _ptr(gamma), p, _ptr(ks), _ptr(out)),
+                    "start_total_ionization")
+        self._leave(cur)
+        return out
 
     def ionization_equilibrium(self, tree: SourceTree, gas_xyz, gas_h, n_h, x_init, grid_log2: int,
                                theta: float = 1.0, sigma: float = 6.3e-18, alpha: float = 2.6e-13,

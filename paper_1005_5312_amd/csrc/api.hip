@@ -407,6 +407,41 @@ start_status start_equilibrium_update(start_ctx *ctx, int64_t n, const double *n
     return START_OK;
 }
 
+start_status start_recombination_emission(start_ctx *ctx, int64_t n, const double *n_h, const double *x_hi,
+                                          const double *volume_cm3, double sigma_cm2, double alpha_1,
+                                          double *lum_out, double *k_self_out)
+{
+    if (!ctx) return START_EINVAL;
+    if (n < 0) return fail(ctx, START_EINVAL, "n < 0");
+    if (n > ((int64_t)1 << 31) - 1) return fail(ctx, START_EINVAL, "n too large");
+    if (!std::isfinite(sigma_cm2) || !std::isfinite(alpha_1)) return fail(ctx, START_ENONFINITE, "sigma or alpha_1 not finite");
+    if (sigma_cm2 < 0.0 || alpha_1 < 0.0) return fail(ctx, START_EINVAL, "sigma and alpha_1 must be >= 0");
+    if (n > 0 && (!n_h || !x_hi || !volume_cm3)) return fail(ctx, START_EINVAL, "input arrays are NULL");
+    if (n == 0 || (!lum_out && !k_self_out)) return START_OK;
+    hipSetDevice(ctx->c.device);
+    launch_recomb_terms(&ctx->c, n, n_h, x_hi, volume_cm3, sigma_cm2, alpha_1, lum_out, k_self_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    return START_OK;
+}
+
+start_status start_total_ionization(start_ctx *ctx, int64_t n, const double *n_h, const double *x_hi,
+                                    const void *gamma, start_precision gamma_prec, const double *k_self,
+                                    double *k_ion_out)
+{
+    if (!ctx) return START_EINVAL;
+    if (n < 0) return fail(ctx, START_EINVAL, "n < 0");
+    if (n > ((int64_t)1 << 31) - 1) return fail(ctx, START_EINVAL, "n too large");
+    if (gamma_prec != START_FP64 && gamma_prec != START_FP32C) return fail(ctx, START_EINVAL, "unknown precision");
+    if (n > 0 && (!n_h || !x_hi || !gamma || !k_ion_out)) return fail(ctx, START_EINVAL, "input arrays are NULL");
+    if (n == 0) return START_OK;
+    hipSetDevice(ctx->c.device);
+    launch_total_rate(&ctx->c, n, n_h, x_hi, gamma, gamma_prec, k_self, k_ion_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    return START_OK;
+}
+
 start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree, int64_t n_gas,
                                           const double *gas_xyz, const double *gas_h, const double *n_h,
                                           int grid_log2, double theta_crit, double sigma_cm2, double alpha,

@@ -1,4 +1,6 @@
-// Photoionisation equilibrium of pure hydrogen, one particle per thread.
+// Per-particle ionisation balance, one particle per thread: the
+// photoionisation-equilibrium update, and the terms of the transfer of
+// recombination photons of section 4.1 (emission, k_self, total k_ion).
 //
 // With neutral fraction x, total hydrogen density n_H and photoionisation
 // rate per H I atom Gamma (Appendix A, eq. A2 for one frequency), the
@@ -78,7 +80,74 @@ __global__ void __launch_bounds__(kThreads) eq_prepare(int64_t n, const double *
     nhi[k] = xv * nh;
 }
 
+// Recombination photons of each particle (section 4.1): the emission rate
+// alpha_1 n_e n_p V of eq. (19) and the part a particle absorbs itself,
+// k_self = alpha_1 n_e n_p (1 - exp(-tau)) of eq. (30) with the optical depth
+// from its edge to its centre tau = sigma n_HI (3 V / (4 pi))^(1/3) of
+// eq. (28); n_e = n_p = (1 - x) n_H.
+__global__ void __launch_bounds__(kThreads) recomb_terms(int64_t n, const double *__restrict__ n_h,
+                                                         const double *__restrict__ x,
+                                                         const double *__restrict__ vol, double sigma,
+                                                         double alpha_1, double *__restrict__ lum,
+                                                         double *__restrict__ kself, unsigned *flags)
+{
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n) return;
+    const double nh = n_h[k], xv = x[k], v = vol[k];
+    if (!isfinite(nh) || !isfinite(xv) || !isfinite(v) || nh < 0.0 || xv < 0.0 || xv > 1.0 || v < 0.0) {
+        atomicOr(flags, kFlagEqInput);
+        if (lum) lum[k] = 0.0;
+        if (kself) kself[k] = 0.0;
+        return;
+    }
+    const double ne = (1.0 - xv) * nh;
+    const double rec = alpha_1 * ne * ne;
+    if (lum) lum[k] = rec * v;
+    if (kself) {
+        const double tau = sigma * (xv * nh) * cbrt(3.0 * v / (4.0 * M_PI));
+        kself[k] = rec * -expm1(-tau);
+    }
+}
+
+// k_ion = n_HI Gamma + k_self (eq. 25), Gamma the rate per H I atom from all
+// other emitters (eq. 26 with eq. A2).
+template <typename TG>
+__global__ void __launch_bounds__(kThreads) total_rate(int64_t n, const double *__restrict__ n_h,
+                                                       const double *__restrict__ x, const TG *__restrict__ gamma,
+                                                       const double *__restrict__ kself, double *__restrict__ kion,
+                                                       unsigned *flags)
+{
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n) return;
+    const double nh = n_h[k], xv = x[k], g = (double)gamma[k], ks = kself ? kself[k] : 0.0;
+    if (!isfinite(nh) || !isfinite(xv) || !isfinite(g) || !isfinite(ks) || nh < 0.0 || g < 0.0 || ks < 0.0) {
+        atomicOr(flags, kFlagEqInput);
+        kion[k] = 0.0;
+        return;
+    }
+    kion[k] = xv * nh * g + ks;
+}
+
 }  // namespace
+
+void launch_recomb_terms(Ctx *c, int64_t n, const double *n_h, const double *x, const double *vol, double sigma,
+                         double alpha_1, double *lum, double *kself)
+{
+    if (n <= 0) return;
+    recomb_terms<<<blocks_for(n), kThreads, 0, c->stream>>>(n, n_h, x, vol, sigma, alpha_1, lum, kself, c->d_flags);
+}
+
+void launch_total_rate(Ctx *c, int64_t n, const double *n_h, const double *x, const void *gamma, int gamma_prec,
+                       const double *kself, double *kion)
+{
+    if (n <= 0) return;
+    if (gamma_prec == START_FP64)
+        total_rate<double><<<blocks_for(n), kThreads, 0, c->stream>>>(n, n_h, x, (const double *)gamma, kself, kion,
+                                                                       c->d_flags);
+    else
+        total_rate<float><<<blocks_for(n), kThreads, 0, c->stream>>>(n, n_h, x, (const float *)gamma, kself, kion,
+                                                                      c->d_flags);
+}
 
 void launch_eq_update(Ctx *c, int64_t n, const double *n_h, const void *gamma, int gamma_prec, double alpha,
                       double *x, double *nhi, unsigned long long *max_change)

@@ -149,6 +149,13 @@ void launch_eq_update(Ctx *c, int64_t n, const double *n_h, const void *gamma, i
                       double *x, double *nhi, unsigned long long *max_change);
 // nhi <- x n_H after checking n_H >= 0 and x in [0, 1].
 void launch_eq_prepare(Ctx *c, int64_t n, const double *n_h, const double *x, double *nhi);
+// Recombination emission alpha_1 n_e n_p V and k_self per particle (either
+// output may be null).
+void launch_recomb_terms(Ctx *c, int64_t n, const double *n_h, const double *x, const double *vol, double sigma,
+                         double alpha_1, double *lum, double *kself);
+// k_ion = x n_H gamma + k_self (k_self may be null).
+void launch_total_rate(Ctx *c, int64_t n, const double *n_h, const double *x, const void *gamma, int gamma_prec,
+                       const double *kself, double *kion);
 
 // ---- Morton keys (tree.hip) ----
 void launch_keys(const start_box &box, int64_t n, const double *xyz, const double *lum,

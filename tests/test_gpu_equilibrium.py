@@ -159,3 +159,96 @@ def test_stromgren_sphere_full_size(ctx, prec):
     assert abs(ph - 1.0) <= 0.10
     r = np.sqrt(((w.gas_xyz - 0.5 * w.box_size) ** 2).sum(axis=0))
     assert np.mean(x[r < 3.0]) < 0.02 and np.mean(x[r > 6.2]) > 0.99
+
+
+# --- recombination photons (section 4.1) ----------------------------------
+
+ALPHA_1 = 1.58e-13
+
+
+def recomb_inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    nh = 10.0 ** rng.uniform(-5, 2, n)
+    x = rng.random(n)
+    if n >= 3:
+        x[:3] = (0.0, 1.0, 1e-12)
+    vol = 10.0 ** rng.uniform(50, 63, n)
+    return nh, x, vol
+
+
+@pytest.mark.parametrize("n", [1, 300, 65_537])
+def test_recombination_emission_matches_oracle(ctx, n):
+    nh, x, vol = recomb_inputs(n, seed=n)
+    dev = ctx.device
+    lum, ks = ctx.recombination_emission(torch.from_numpy(nh).to(dev), torch.from_numpy(x).to(dev),
+                                         torch.from_numpy(vol).to(dev), 6.3e-18, ALPHA_1)
+    ctx.synchronize()
+    # the same products in the same order: bit for bit
+    assert np.array_equal(lum.cpu().numpy(), E.recombination_emission(nh, x, vol, ALPHA_1))
+    # cube root and expm1 are library functions on both sides: a few ulp
+    want = E.k_self(nh, x, vol, 6.3e-18, ALPHA_1)
+    got = ks.cpu().numpy()
+    big = want > 0
+    assert np.all(got[~big] == 0.0)
+    assert np.max(np.abs(got[big] - want[big]) / want[big]) <= 1e-14
+    # one output only
+    lum2, none = ctx.recombination_emission(nh, x, vol, 6.3e-18, ALPHA_1, want_k_self=False)
+    assert none is None and torch.equal(lum2, lum)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_total_ionization_matches_oracle(ctx, prec):
+    n = 10_001
+    nh, x, vol = recomb_inputs(n, seed=77)
+    rng = np.random.default_rng(78)
+    g = 10.0 ** rng.uniform(-20, -8, n)
+    if prec == "fp32c":
+        g = g.astype(np.float32)
+    ks = E.k_self(nh, x, vol, 6.3e-18, ALPHA_1)
+    dev = ctx.device
+    got = ctx.total_ionization(torch.from_numpy(nh).to(dev), torch.from_numpy(x).to(dev),
+                               torch.from_numpy(g).to(dev), torch.from_numpy(ks).to(dev)).cpu().numpy()
+    assert np.array_equal(got, E.k_ion_total(g.astype(np.float64), nh, x, ks))
+    got0 = ctx.total_ionization(nh, x, torch.from_numpy(g).to(dev)).cpu().numpy()
+    assert np.array_equal(got0, x * nh * g.astype(np.float64))
+
+
+def test_recombination_input_errors(ctx):
+    from paper_1005_5312_amd import binding
+    nh, x, vol = recomb_inputs(100, seed=3)
+    for bad in ((-nh, x, vol), (nh, x + 1.0, vol), (nh, x, -vol)):
+        ctx.recombination_emission(*bad, 6.3e-18, ALPHA_1)
+        with pytest.raises(binding.StartError) as ei:
+            ctx.synchronize()
+        assert ei.value.code == binding.EINVAL
+    with pytest.raises(binding.StartError):
+        ctx.recombination_emission(nh, x, vol, -1.0, ALPHA_1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_diffuse_k_ion_pipeline_matches_oracle(ctx, prec):
+    """Every particle an emitter (eq. 19), Gamma from all other emitters
+    through the tree (self excluded), plus k_self: k_ion of eq. (25) on a
+    partly ionised medium, against the checker."""
+    w = H.W.make_small(seed=12, n_gas=4096, n_src=1)
+    rng = np.random.default_rng(13)
+    nh = np.full(w.n_gas, 1e-3) * np.exp(rng.standard_normal(w.n_gas) * 0.5)
+    x = rng.uniform(0.01, 1.0, w.n_gas)
+    vol = np.full(w.n_gas, (w.box_size * H.KPC) ** 3 / w.n_gas)
+    dev = ctx.device
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    lum, ks = ctx.recombination_emission(d(nh), d(x), d(vol), w.sigma, ALPHA_1)
+    box = H.box_of(w)
+    tree = ctx.build_source_tree(box, d(w.gas_xyz), lum)
+    grid = ctx.build_gas_grid(box, d(w.gas_xyz), d(w.gas_h), d(x * nh), w.grid_log2)
+    ss = d(np.arange(w.n_gas, dtype=np.int64))
+    gam = ctx.compute_rates(tree, grid, d(w.gas_xyz), ss, 1.0, w.sigma, prec)
+    kion = ctx.total_ionization(d(nh), d(x), gam, ks).cpu().numpy()
+    ob = H.obox_of(w)
+    lum_o = E.recombination_emission(nh, x, vol, ALPHA_1)
+    go = O.rates(O.Tree(ob, w.gas_xyz, lum_o), w.grid_log2, O.grid(ob, w.gas_xyz, w.gas_h, x * nh, w.grid_log2),
+                 w.gas_xyz, np.arange(w.n_gas), 1.0, w.sigma)
+    want = E.k_ion_total(go, nh, x, E.k_self(nh, x, vol, w.sigma, ALPHA_1))
+    rel = float(np.max(np.abs(kion - want) / want))
+    print(f"  k_ion {prec}: max rel {rel:.2e}")
+    assert rel <= (H.TOL_FP64 if prec == "fp64" else H.TOL_FP32C)
