@@ -263,6 +263,37 @@ def equilibrium_bench(n_gas=1 << 21, grid_log2=7, tol=1e-4, max_iter=200):
     return out
 
 
+def k_ion_bench(ctx, w, gamma32, reps=20):
+    """The per-particle terms of the transfer of recombination photons on the
+    benchmark workload: emission and k_self (eqs. 19, 28, 30) and the total
+    k_ion of eq. (25) from the FP32C rates; event-timed on the library stream,
+    against the HBM peak (they stream 40 B and 36 B per particle)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    n = w.n_gas
+    nh = torch.full((n,), 1e-3, dtype=torch.float64, device=dev)
+    x = torch.from_numpy(np.ascontiguousarray(w.gas_nhi / 1e-3)).to(dev)
+    vol = torch.full((n,), (w.box_size * w.length_unit_cm) ** 3 / n, dtype=torch.float64, device=dev)
+    out = {}
+    for name, fn, nbytes in (
+            ("recombination_emission", lambda: ctx.recombination_emission(nh, x, vol, w.sigma, 1.58e-13), 40),
+            ("total_ionization", lambda: ctx.total_ionization(nh, x, gamma32, ks), 36)):
+        if name == "recombination_emission":
+            _, ks = fn()
+        fn()
+        ctx.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(ctx.stream)
+        ctx.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = nbytes * n / (ms * 1e-3) / 1e9
+        out[name] = {"ms": ms, "bytes_per_particle": nbytes, "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -400,6 +431,11 @@ def main():
             log(f"[bench] serving: Poisson arrivals at {lam}/s, {args.serve_requests} requests")
             serve_stats.append(serve_bench(lam, args.serve_requests))
 
+    kion_stats = None
+    if not args.rates_only:
+        log("[bench] k_self and total k_ion terms")
+        kion_stats = k_ion_bench(ctx, w, out32)
+
     eq_stats = None
     if not args.no_equilibrium and not args.rates_only:
         log("[bench] photoionisation equilibrium (Test 4 setting)")
@@ -439,6 +475,7 @@ def main():
         "serve": serve_stats,
         "batched": batch_stats,
         "equilibrium": eq_stats,
+        "k_ion_terms": kion_stats,
         "work_per_target": {"opening_tests": float(c[:, 0].mean()), "entries": float(c[:, 1].mean()),
                             "grid_cells": float(c[:, 2].mean())},
         "source_sha": sha,
