@@ -59,6 +59,9 @@ def lib():
         L.or_column.argtypes = [P, C.c_int, P, P, P, P]
         L.or_column.restype = C.c_double
         L.or_rates.argtypes = [P, C.c_int, P, i64, P, P, C.c_double, C.c_double, P, P, C.c_int]
+        L.or_fsh.argtypes = [C.c_double]
+        L.or_fsh.restype = C.c_double
+        L.or_lw_rates.argtypes = [P, C.c_int, P, i64, P, P, C.c_double, P, C.c_int]
         _lib = L
     return _lib
 
@@ -193,3 +196,21 @@ def rates(tree: Tree, grid_log2, grid_values, tgt_xyz, self_src=None, theta=1.0,
     _check(lib().or_rates(tree._h, int(grid_log2), _p(g), nt, _p(tgt), _p(ss), float(theta),
                           float(sigma), _p(out), _p(cnt), int(nthreads)), "or_rates")
     return (out, cnt) if counters else out
+
+
+def fsh(x):
+    """H2 self-shielding function of Appendix B."""
+    return lib().or_fsh(float(x))
+
+
+def lw_rates(tree: Tree, grid_log2, grid_values, tgt_xyz, self_src=None, theta=1.0, nthreads=0):
+    """H2 photodissociation rate (s^-1) per target (Appendix B): the tree holds
+    Lyman-Werner luminosities (erg s^-1 Hz^-1), the grid n_H2 (cm^-3)."""
+    tgt = _f64(tgt_xyz).reshape(3, -1)
+    nt = tgt.shape[1]
+    g = _f64(grid_values).reshape(-1)
+    ss = None if self_src is None else np.ascontiguousarray(self_src, dtype=np.int64)
+    out = np.zeros(nt)
+    _check(lib().or_lw_rates(tree._h, int(grid_log2), _p(g), nt, _p(tgt), _p(ss), float(theta), _p(out),
+                             int(nthreads)), "or_lw_rates")
+    return out

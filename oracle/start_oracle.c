@@ -20,7 +20,10 @@
  *   5. the rate per H I atom, the monochromatic form of Appendix A eq. (A2)
  *      with on-the-spot attenuation (eq. 7):
  *         Gamma_i = sigma / (4 pi) * sum_alpha L_alpha exp(-tau_alpha) / d_alpha^2,
- *      excluding the target's own emission (k_other of eqs. 25-26).
+ *      excluding the target's own emission (k_other of eqs. 25-26);
+ *   6. the H2 photodissociation rate of Appendix B on the same lists and
+ *      rays: 1.13e8 sum_alpha L_alpha / (4 pi d_alpha^2) f_sh(N_H2 / 1e14),
+ *      with the H2 column integrated like tau.
  *
  * Built with -O2 -ffp-contract=off and no fast-math: every rounding is the
  * one written here.
@@ -764,6 +767,77 @@ int or_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n_t,
                 counters[4 * i + 2] = ncell_tot;
                 counters[4 * i + 3] = nzero;
             }
+        }
+        free(ts);
+        free(L.e);
+    }
+    return err;
+}
+
+/* H2 self-shielding function of Appendix B (eq. B2): 1 up to a column of
+ * 1e14 cm^-2, then (N / 1e14)^(-3/4). */
+double or_fsh(double x)
+{
+    return x <= 1.0 ? 1.0 : pow(x, -0.75);
+}
+
+int or_lw_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n_t,
+                const double *tgt_xyz, const int64_t *self_src, double theta,
+                double *kdis_out, int nthreads)
+{
+    if (!t || !kdis_out || grid_log2 < 0 || grid_log2 > 10 || !grid) return OR_EINVAL;
+    int rc = check_targets(&t->box, n_t, tgt_xyz, self_src, t->n, theta);
+    if (rc) return rc;
+    const int G = 1 << grid_log2;
+    const double ucm = t->box.unit_cm;
+    const double four_pi = 4.0 * M_PI;
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        or_list L = {0};
+        double *ts = (double *)malloc((size_t)(3 * G + 4) * sizeof(double));
+        if (!ts) {
+#pragma omp atomic write
+            err = OR_ENOMEM;
+        }
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n_t; ++i) {
+            if (!ts) continue;
+            double x[3] = {tgt_xyz[i], tgt_xyz[n_t + i], tgt_xyz[2 * n_t + i]};
+            if (list_for(t, x, self_src ? self_src[i] : -1, theta, &L) != OR_OK) {
+#pragma omp atomic write
+                err = OR_ENOMEM;
+                continue;
+            }
+            double sum = 0.0;
+            for (int64_t e = 0; e < L.n; ++e) {
+                const double *r;
+                double ra[3], La;
+                if (L.e[e].cell >= 0) {
+                    const or_cell *c = &t->cells[L.e[e].cell];
+                    r = c->com;
+                    La = c->lum;
+                } else {
+                    int64_t j = L.e[e].src;
+                    for (int k = 0; k < 3; ++k) ra[k] = t->x[(int64_t)k * t->n + j];
+                    r = ra;
+                    La = t->lum[j];
+                }
+                double dx = x[0] - r[0], dy = x[1] - r[1], dz = x[2] - r[2];
+                double dist = sqrt(dx * dx + dy * dy + dz * dz);
+                if (dist == 0.0) continue;
+                int64_t nc = 0;
+                /* H2 column in cm^-2 along the ray, unshielded flux L / (4 pi d^2) */
+                double col = column_buf(&t->box, grid_log2, grid, r, x, &nc, ts) * ucm;
+                double dcm = dist * ucm;
+                sum += La / (four_pi * dcm * dcm) * or_fsh(col / 1e14);
+            }
+            kdis_out[i] = 1.13e8 * sum;
         }
         free(ts);
         free(L.e);

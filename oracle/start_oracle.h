@@ -108,6 +108,20 @@ int or_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n_t,
              const double *tgt_xyz, const int64_t *self_src, double theta, double sigma,
              double *gamma_out, int64_t *counters, int nthreads);
 
+/* H2 self-shielding function of Appendix B: f_sh(x) = 1 for x <= 1 and
+ * x^(-3/4) above, x = N_H2 / 1e14 cm^-2. */
+double or_fsh(double x);
+
+/* H2 photodissociation rate (s^-1) of each target, Appendix B eq. (B1) summed
+ * over the interaction list as in eq. (A5):
+ *   k_dis,i = 1.13e8 sum_alpha F_alpha f_sh(N_H2,alpha / 1e14 cm^-2),
+ * F_alpha = L_alpha / (4 pi d_alpha^2) the Lyman-Werner flux without
+ * shielding (L in erg s^-1 Hz^-1 as the tree's luminosities), N_H2,alpha the
+ * column of the gridded n_H2 (grid as or_grid_build of n_H2) along the ray. */
+int or_lw_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n_t,
+                const double *tgt_xyz, const int64_t *self_src, double theta,
+                double *kdis_out, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif
