@@ -263,24 +263,34 @@ def equilibrium_bench(n_gas=1 << 21, grid_log2=7, tol=1e-4, max_iter=200):
     return out
 
 
-def k_ion_bench(ctx, w, gamma32, reps=20):
+def k_ion_bench(ctx, w, gamma32, reps=200):
     """The per-particle terms of the transfer of recombination photons on the
     benchmark workload: emission and k_self (eqs. 19, 28, 30) and the total
-    k_ion of eq. (25) from the FP32C rates; event-timed on the library stream,
-    against the HBM peak (they stream 40 B and 36 B per particle)."""
+    k_ion of eq. (25) from the FP32C rates.  The C-ABI is called directly on
+    preallocated buffers, event-timed on the library stream, against the HBM
+    peak (the kernels stream 40 B and 36 B per particle)."""
+    import ctypes
     import torch
+    from paper_1005_5312_amd import binding as B
     dev = torch.device("cuda", 0)
     n = w.n_gas
     nh = torch.full((n,), 1e-3, dtype=torch.float64, device=dev)
     x = torch.from_numpy(np.ascontiguousarray(w.gas_nhi / 1e-3)).to(dev)
     vol = torch.full((n,), (w.box_size * w.length_unit_cm) ** 3 / n, dtype=torch.float64, device=dev)
+    lum = torch.empty(n, dtype=torch.float64, device=dev)
+    ks = torch.empty(n, dtype=torch.float64, device=dev)
+    kion = torch.empty(n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    L = B.lib()
+    calls = (
+        ("recombination_emission", 40,
+         lambda: L.start_recombination_emission(ctx._h, n, p(nh), p(x), p(vol), w.sigma, 1.58e-13, p(lum), p(ks))),
+        ("total_ionization", 36,
+         lambda: L.start_total_ionization(ctx._h, n, p(nh), p(x), p(gamma32), B.FP32C, p(ks), p(kion))))
     out = {}
-    for name, fn, nbytes in (
-            ("recombination_emission", lambda: ctx.recombination_emission(nh, x, vol, w.sigma, 1.58e-13), 40),
-            ("total_ionization", lambda: ctx.total_ionization(nh, x, gamma32, ks), 36)):
-        if name == "recombination_emission":
-            _, ks = fn()
-        fn()
+    for name, nbytes, fn in calls:
+        assert fn() == 0
         ctx.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(ctx.stream)
@@ -291,6 +301,40 @@ def k_ion_bench(ctx, w, gamma32, reps=20):
         ms = e0.elapsed_time(e1) / reps
         gbs = nbytes * n / (ms * 1e-3) / 1e9
         out[name] = {"ms": ms, "bytes_per_particle": nbytes, "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    return out
+
+
+def lw_bench(n_gas=1 << 20, n_src=1024, reps=5):
+    """H2 photodissociation rates (Appendix B) for every particle of a 2^20
+    lognormal medium lit by 1024 Lyman-Werner sources at theta = 1."""
+    import torch
+    import paper_1005_5312_amd as S
+    from paper_1005_5312_amd import workloads as W
+    w = W.make_lw(n_gas=n_gas, n_src=n_src)
+    ctx = S.Context(0)
+    dev = torch.device("cuda", 0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    box = S.Box(tuple(float(v) for v in w.box_lo), float(w.box_size), float(w.length_unit_cm))
+    tree = ctx.build_source_tree(box, d(w.src_xyz), d(w.src_lum))
+    grid = ctx.build_gas_grid(box, d(w.gas_xyz), d(w.gas_h), d(w.gas_nh2), w.grid_log2)
+    tgt = d(w.tgt_xyz)
+    out = {"workload": f"{n_gas} particles, lognormal n_H, H2 fraction 10^U[-7,-3], {n_src} sources, "
+                       f"G = {1 << w.grid_log2}, theta = 1"}
+    for prec in ("fp32c", "fp64"):
+        ctx.compute_dissociation_rates(tree, grid, tgt, None, 1.0, prec)
+        ctx.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            ctx.compute_dissociation_rates(tree, grid, tgt, None, 1.0, prec)
+        e1.record(ctx.stream)
+        ctx.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[prec] = {"ms_per_call": ms, "evals_per_s": n_gas / (ms * 1e-3)}
+        log(f"[bench] H2 dissociation {prec}: {ms:.3f} ms/call")
+    tree.free()
+    grid.free()
+    ctx.close()
     return out
 
 
@@ -436,6 +480,11 @@ def main():
         log("[bench] k_self and total k_ion terms")
         kion_stats = k_ion_bench(ctx, w, out32)
 
+    lw_stats = None
+    if not args.rates_only:
+        log("[bench] H2 photodissociation rates")
+        lw_stats = lw_bench()
+
     eq_stats = None
     if not args.no_equilibrium and not args.rates_only:
         log("[bench] photoionisation equilibrium (Test 4 setting)")
@@ -476,6 +525,7 @@ def main():
         "batched": batch_stats,
         "equilibrium": eq_stats,
         "k_ion_terms": kion_stats,
+        "h2_dissociation": lw_stats,
         "work_per_target": {"opening_tests": float(c[:, 0].mean()), "entries": float(c[:, 1].mean()),
                             "grid_cells": float(c[:, 2].mean())},
         "source_sha": sha,

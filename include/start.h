@@ -120,6 +120,19 @@ start_status start_compute_rates(start_ctx *ctx, const start_tree *tree, const s
                                  const double *tgt_xyz, const int64_t *self_src, double theta_crit,
                                  double sigma_cm2, start_precision prec, void *gamma_out);
 
+/* H2 photodissociation rate (s^-1) of each target by the Lyman-Werner band
+ * (Appendix B, eq. B1, summed over the interaction list as in eq. A5):
+ *   k_dis,i = 1.13e8 * sum_alpha L_alpha / (4 pi d_alpha^2) * f_sh(N_alpha / 1e14),
+ * f_sh(x) = 1 for x <= 1 and x^(-3/4) above (eq. B2), N_alpha the H2 column
+ * (cm^-2) along the ray through the grid.  Same walk, lists and rays as
+ * start_compute_rates; the tree holds Lyman-Werner luminosities
+ * (erg s^-1 Hz^-1) and the grid n_H2 (cm^-3, built by start_build_gas_grid
+ * from per-particle n_H2).  kdis_out [n_t]: double (FP64) or float (FP32C).
+ * Asynchronous, errors as start_compute_rates. */
+start_status start_compute_dissociation_rates(start_ctx *ctx, const start_tree *tree, const start_grid *grid,
+                                              int64_t n_t, const double *tgt_xyz, const int64_t *self_src,
+                                              double theta_crit, start_precision prec, void *kdis_out);
+
 /* One independent rate problem for start_compute_rates_batched. */
 typedef struct {
     const start_tree *tree;

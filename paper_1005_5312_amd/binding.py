@@ -28,7 +28,8 @@ EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_s
            "start_grid_free", "start_grid_size", "start_compute_rates", "start_compute_rates_batched",
            "start_estimate_bytes", "start_tree_export", "start_interaction_lists", "start_grid_export",
            "start_rate_counters", "start_profile_enable", "start_profile_read", "start_equilibrium_update",
-           "start_ionization_equilibrium", "start_recombination_emission", "start_total_ionization")
+           "start_ionization_equilibrium", "start_recombination_emission", "start_total_ionization",
+           "start_compute_dissociation_rates")
 
 
 class LibraryMissing(RuntimeError):
@@ -103,6 +104,7 @@ def lib():
                                          C.c_int),
         "start_recombination_emission": ([P, i64, P, P, P, d, d, P, P], C.c_int),
         "start_total_ionization": ([P, i64, P, P, P, C.c_int, P, P], C.c_int),
+        "start_compute_dissociation_rates": ([P, P, P, i64, P, P, d, C.c_int, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -277,6 +279,30 @@ class Context:
         cur = self._enter(xyz, ss, out)
         self._check(lib().start_compute_rates(self._h, tree._h, grid._h, n, _ptr(xyz), _ptr(ss), float(theta),
                                               float(sigma), p, _ptr(out)), "start_compute_rates")
+        self._leave(cur)
+        return out
+
+    def compute_dissociation_rates(self, tree: SourceTree, grid: GasGrid, tgt_xyz, self_src=None,
+                                   theta: float = 1.0, prec="fp32c", out=None):
+        """H2 photodissociation rate per target (s^-1): `tree` built from
+        Lyman-Werner luminosities, `grid` from n_H2.  float64 for fp64 and
+        float32 for fp32c.  Asynchronous."""
+        import torch
+        p = _prec(prec)
+        xyz = _xyz(tgt_xyz, self.device)
+        n = xyz.shape[1]
+        ss = None if self_src is None else _vec(self_src, self.device, torch.int64)
+        if ss is not None and ss.numel() != n:
+            raise ValueError("self_src length does not match targets")
+        dt = torch.float64 if p == FP64 else torch.float32
+        if out is None:
+            out = torch.empty(n, dtype=dt, device=self.device)
+        elif out.dtype != dt or out.numel() != n or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype, size or layout")
+        cur = self._enter(xyz, ss, out)
+        self._check(lib().start_compute_dissociation_rates(self._h, tree._h, grid._h, n, _ptr(xyz), _ptr(ss),
+                                                           float(theta), p, _ptr(out)),
+                    "start_compute_dissociation_rates")
         self._leave(cur)
         return out
 

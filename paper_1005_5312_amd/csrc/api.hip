@@ -347,6 +347,21 @@ start_status start_compute_rates(start_ctx *ctx, const start_tree *tree, const s
     return enqueue(ctx, &r, 1, 0);
 }
 
+start_status start_compute_dissociation_rates(start_ctx *ctx, const start_tree *tree, const start_grid *grid,
+                                              int64_t n_t, const double *tgt_xyz, const int64_t *self_src,
+                                              double theta_crit, start_precision prec, void *kdis_out)
+{
+    start_status st = check_rate_args(ctx, tree, grid, n_t, tgt_xyz, theta_crit, 0.0, prec, true);
+    if (st) return st;
+    if (n_t == 0) return START_OK;
+    if (!kdis_out) return fail(ctx, START_EINVAL, "kdis_out is NULL");
+    hipSetDevice(ctx->c.device);
+    RateSpec r = spec_of(tree, grid, n_t, tgt_xyz, self_src, theta_crit, 0.0, prec);
+    r.channel = 1;
+    r.gamma = kdis_out;
+    return enqueue(ctx, &r, 1, 0);
+}
+
 start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const start_item *items)
 {
     if (!ctx) return START_EINVAL;

@@ -129,6 +129,7 @@ struct RateSpec {
     double theta;
     double sigma;
     int prec;
+    int channel;               // 0 photoionisation (eq. A2), 1 H2 photodissociation (eq. B1)
     void *gamma;               // rates
     int64_t *stats;            // counters [n_t][4]
     int64_t *counts;           // list counts [n_t]

@@ -66,6 +66,11 @@ struct Item {
     double cell_cm;     // size / G * unit_cm
     double theta2;
     double sigma;
+    // channel 0: photoionisation, term L exp(-sigma N) / d^2 (eq. A2);
+    // channel 1: H2 photodissociation, term L f_sh(N / 1e14) / d^2 (eq. B1)
+    int channel;
+    double col_scale;   // column in cells x density -> sigma N (0) or N / 1e14 (1)
+    double rate_scale;  // sigma / (4 pi) (0) or 1.13e8 / (4 pi) (1)
     // targets: caller's positions, and this item's run of the sorted arrays
     int64_t n_t;
     const double *tgt_xyz;   // [3][n_t], caller order
@@ -175,6 +180,19 @@ __device__ inline double vmin(double x, double y)
 }
 
 __device__ inline double min3(double x, double y, double z) { return vmin(vmin(x, y), z); }
+
+// H2 self-shielding function of Appendix B: 1 up to x = 1, x^(-3/4) above,
+// as (1 / x^(1/4))^3 with two square roots (a few ulp; far lighter than pow)
+__device__ inline float fsh(float x)
+{
+    const float r = 1.0f / sqrtf(sqrtf(x));
+    return x <= 1.0f ? 1.0f : r * r * r;
+}
+__device__ inline double fsh(double x)
+{
+    const double r = 1.0 / sqrt(sqrt(x));
+    return x <= 1.0 ? 1.0 : r * r * r;
+}
 
 typedef const __attribute__((address_space(1))) char gchar_t;
 
@@ -434,7 +452,7 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
     T acc = T(0), accc = T(0);
     int64_t st_test = 0, st_entries = 0, st_cells = 0, st_zero = 0;
     int head = 0, tail = 0, rhead = 0, rtail = 0;   // wave-uniform ring counters
-    const T tau_scale = (T)(P.sigma * P.cell_cm);
+    const T col_scale = (T)P.col_scale;
     const int sh = 32 - gl;
 
     // March one item: the term L e^-tau / d^2 (d in cells) of ring slot `slot`.
@@ -472,8 +490,11 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             const T col = march<T, STATS>(PREC == START_FP64 ? (const T *)P.grid : (const T *)P.gridf, G,
                                           (unsigned)ncell_m1, tcell, fb, D, nc);
             const T dist = (T)sqrt(d2);                        // grid units
-            const T tau = tau_scale * (col * dist);
-            term = w * exp(-tau) / (T)d2;
+            const T c = col_scale * (col * dist);
+            if (P.channel == 0)
+                term = w * exp(-c) / (T)d2;                    // c = tau
+            else
+                term = w * fsh(c) / (T)d2;                     // c = N_H2 / 1e14
         } else {
             term = T(0);
             nc = -1;                                           // zero distance: skipped
@@ -584,16 +605,15 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
         o[3] = st_zero;
         return;
     }
-    const double four_pi = 4.0 * M_PI;
     if (PREC == START_FP64) {
         // terms are L / d^2 with d in cells: restore cm
-        static_cast<double *>(P.gamma)[orig] = P.sigma / four_pi * (double)acc / (P.cell_cm * P.cell_cm);
+        static_cast<double *>(P.gamma)[orig] = P.rate_scale * (double)acc / (P.cell_cm * P.cell_cm);
     } else {
         // L' = L / L_root and lengths in cells: restore units in FP64
         const double L0 = P.n_nodes > 0 ? P.mom[0].w : 0.0;   // empty tree: no arrays
         const double Lref = L0 > 0.0 ? L0 : 1.0;
         const double sum = (double)acc - (double)accc;
-        static_cast<float *>(P.gamma)[orig] = (float)(P.sigma / four_pi * sum * Lref / (P.cell_cm * P.cell_cm));
+        static_cast<float *>(P.gamma)[orig] = (float)(P.rate_scale * sum * Lref / (P.cell_cm * P.cell_cm));
     }
 }
 
@@ -848,6 +868,9 @@ void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, void *scratch, hi
         I.cell_cm = t->box.size / I.G * t->box.length_unit_cm;
         I.theta2 = r.theta * r.theta;
         I.sigma = r.sigma;
+        I.channel = r.channel;
+        I.col_scale = r.channel == 0 ? r.sigma * I.cell_cm : I.cell_cm * 1e-14;
+        I.rate_scale = (r.channel == 0 ? r.sigma : 1.13e8) / (4.0 * M_PI);
         I.n_t = r.n_t;
         I.tgt_xyz = r.tgt_xyz;
         I.tgt = bs.tgt + off;

@@ -22,6 +22,11 @@ from the paper is available):
   200x overdensity and radius 0.05 box in one hemisphere around the star
   (the shadowing setting of Test 6, section 4.2.3).
 
+* ``lw``        H2 photodissociation by the Lyman-Werner band (Appendix B):
+  lognormal gas as ``clumpy`` with H2 fractions 10^U[-7, -3] of n_H and
+  sources of 10^U[23, 25] erg s^-1 Hz^-1 in the band (``src_lum`` holds the
+  Lyman-Werner luminosities, ``gas_nh2`` the H2 densities).
+
 Equilibrium problems (``make_stromgren``) add the total hydrogen density of
 each particle and an initial neutral fraction: one 5e48 photons/s source at
 the centre of a 13.2 kpc box of uniform gas with n_H = 1e-3 cm^-3, the
@@ -57,6 +62,7 @@ class Workload:
     thetas: tuple
     grid_log2: int
     sigma: float = SIGMA_HI
+    gas_nh2: np.ndarray | None = None   # (N_gas,) H2 density, cm^-3 (Lyman-Werner workloads)
 
     @property
     def n_gas(self):
@@ -210,8 +216,20 @@ def make_stromgren(seed: int = 5, n_gas: int = 1 << 15, box_kpc: float = 13.2, l
     return Equilibrium(w, nh, x0, vol)
 
 
+def make_lw(seed: int = 6, n_gas: int = 1 << 16, n_src: int = 256) -> Workload:
+    rng = np.random.default_rng(seed)
+    L = BOX_KPC
+    gas = _uniform_positions(rng, n_gas, L)
+    src = _uniform_positions(rng, n_src, L)
+    lum = 10.0 ** rng.uniform(23.0, 25.0, n_src)
+    nh = 1e-3 * np.exp(rng.standard_normal(n_gas) - 0.5)
+    nh2 = nh * 10.0 ** rng.uniform(-7.0, -3.0, n_gas)
+    return Workload("lw", np.zeros(3), L, KPC_CM, gas, smoothing_lengths(gas), np.zeros(n_gas),
+                    src, lum, gas, None, (0.0, 0.5, 1.0), auto_grid_log2(n_gas), gas_nh2=nh2)
+
+
 MAKERS = {"small": make_small, "clumpy": make_clumpy, "diffuse": make_diffuse,
-          "shadow": make_shadow}
+          "shadow": make_shadow, "lw": make_lw}
 
 
 def make(name: str, **kw) -> Workload:
