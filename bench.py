@@ -138,13 +138,13 @@ def make_scene_pool(n, seed, lo_log2=14, hi_log2=17):
     return pool
 
 
-def serve_bench(lam, n_req, seed=5):
+def serve_bench(lam, n_req, seed=5, autotune=False):
     """Poisson arrivals at `lam` requests/s; each request asks for the rates of
     every particle of a scene drawn from a resident pool."""
     import threading
     from paper_1005_5312_amd import serve
     pool = make_scene_pool(6, seed)
-    ex = serve.GpuExecutor(0, n_slots=2)
+    ex = serve.GpuExecutor(0, n_slots=2, autotune=autotune)
     srv = serve.Server(ex, hbm_budget=64 << 30, max_batch=32).start()
     rng = np.random.default_rng(seed + 1)
     # warm: build every scene once (resident afterwards)
@@ -175,6 +175,7 @@ def serve_bench(lam, n_req, seed=5):
     srv.stop()
     st = srv.latency_stats()
     st["arrival_rate_per_s"] = lam
+    st["autotuned_tiles"] = autotune
     st["scene_sizes"] = sorted(int(w.n_tgt) for _, w in pool)
     return st
 
@@ -211,6 +212,22 @@ def batch_bench(n_inst=256, n_p=1 << 14, seed=9, reps=3):
                                   it["out"])
     ctx.synchronize()
     t_single = (time.perf_counter() - t0) / reps
+    # autotuned tiles: the whole batch, and one instance (its own size class)
+    best_batch, _ = ctx.autotune_rates(items, reps=3)
+    best_single, _ = ctx.autotune_rates(items[:1], reps=5)
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.compute_rates_batched(items)
+    ctx.synchronize()
+    t_batched_tuned = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for it in items:
+            ctx.compute_rates_raw(it["tree"], it["grid"], it["tgt_xyz"], it["self_src"], 1.0, it["sigma"], "fp32c",
+                                  it["out"])
+    ctx.synchronize()
+    t_single_tuned = (time.perf_counter() - t0) / reps
     n_total = sum(it["tgt_xyz"].shape[1] for it in items)
     for tree, grid, *_ in built:
         tree.free()
@@ -218,7 +235,12 @@ def batch_bench(n_inst=256, n_p=1 << 14, seed=9, reps=3):
     ctx.close()
     return {"instances": n_inst, "targets_each": n_p, "batched_ms": t_batched * 1e3,
             "one_call_each_ms": t_single * 1e3, "batched_evals_per_s": n_total / t_batched,
-            "one_call_each_evals_per_s": n_total / t_single}
+            "one_call_each_evals_per_s": n_total / t_single,
+            "autotuned": {"batch_tile_targets": best_batch, "batched_ms": t_batched_tuned * 1e3,
+                          "batched_evals_per_s": n_total / t_batched_tuned,
+                          "single_tile_targets": best_single, "one_call_each_ms": t_single_tuned * 1e3,
+                          "one_call_each_evals_per_s": n_total / t_single_tuned},
+            "default_tiles": "from the call size: about total targets / 4096, a power of two in [1, 64]"}
 
 
 def equilibrium_bench(n_gas=1 << 21, grid_log2=7, tol=1e-4, max_iter=200):

@@ -150,6 +150,26 @@ typedef struct {
  * compute it) enqueued together on the context stream. */
 start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const start_item *items);
 
+/* Work decomposition of the rate kernels: each wavefront walks the tree for
+ * a tile of up to tile_targets targets (one per lane) and marches the rays of
+ * that tile 64 at a time.  1 <= tile_targets <= 64 fixes the tile size for
+ * every call on the context; 0 (the default) takes it from the autotuned
+ * table for the call's total number of targets, or else uses about
+ * total / 4096 (a power of two in [1, 64]) so that small calls still fill
+ * the GPU.  Results do not depend on the tile size (bit for bit). */
+start_status start_set_tile_targets(start_ctx *ctx, int tile_targets);
+
+/* Times the batch (as start_compute_rates_batched, which it runs, writing
+ * the outputs) with tiles of 64, 32, 16, 8, 4 and 1 targets, `reps` times
+ * each (a size twice as slow as the best so far on its first run is not
+ * repeated), and records the fastest for the batch's size class (total
+ * targets rounded up to a power of two) in the context's table; 64 is kept
+ * unless another size is at least 3% faster.  best_tile
+ * and best_ms (host, may be NULL) receive the choice and its mean time.
+ * Synchronous. */
+start_status start_autotune_rates(start_ctx *ctx, int n_items, const start_item *items, int reps, int *best_tile,
+                                  double *best_ms);
+
 /* Upper bound of the device bytes a tree, grid and rate call of these sizes
  * hold at once (for admission by memory). */
 size_t start_estimate_bytes(int64_t n_t, int64_t n_s, int64_t n_gas, int grid_log2, start_precision prec);

@@ -29,7 +29,7 @@ EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_s
            "start_estimate_bytes", "start_tree_export", "start_interaction_lists", "start_grid_export",
            "start_rate_counters", "start_profile_enable", "start_profile_read", "start_equilibrium_update",
            "start_ionization_equilibrium", "start_recombination_emission", "start_total_ionization",
-           "start_compute_dissociation_rates")
+           "start_compute_dissociation_rates", "start_set_tile_targets", "start_autotune_rates")
 
 
 class LibraryMissing(RuntimeError):
@@ -105,6 +105,8 @@ def lib():
         "start_recombination_emission": ([P, i64, P, P, P, d, d, P, P], C.c_int),
         "start_total_ionization": ([P, i64, P, P, P, C.c_int, P, P], C.c_int),
         "start_compute_dissociation_rates": ([P, P, P, i64, P, P, d, C.c_int, P], C.c_int),
+        "start_set_tile_targets": ([P, C.c_int], C.c_int),
+        "start_autotune_rates": ([P, C.c_int, P, C.c_int, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -313,10 +315,7 @@ class Context:
                                               float(theta), float(sigma), _prec(prec), _ptr(out)),
                     "start_compute_rates")
 
-    def compute_rates_batched(self, items):
-        """items: list of dicts with keys tree, grid, tgt_xyz, self_src, theta,
-        sigma, prec, out (tensors prepared as for compute_rates)."""
-        import torch
+    def _items(self, items):
         arr = (_Item * len(items))()
         keep = []
         for k, it in enumerate(items):
@@ -333,9 +332,32 @@ class Context:
             arr[k].prec = _prec(it.get("prec", "fp32c"))
             arr[k].gamma_out = it["out"].data_ptr()
             keep += [ss, it["out"]]
+        return arr, keep
+
+    def compute_rates_batched(self, items):
+        """items: list of dicts with keys tree, grid, tgt_xyz, self_src, theta,
+        sigma, prec, out (tensors prepared as for compute_rates)."""
+        arr, keep = self._items(items)
         cur = self._enter(*keep)
         self._check(lib().start_compute_rates_batched(self._h, len(items), arr), "start_compute_rates_batched")
         self._leave(cur)
+
+    def set_tile_targets(self, tile_targets: int):
+        """Targets per wavefront of the rate kernels (1..64), or 0 for the
+        autotuned choice by problem size."""
+        self._check(lib().start_set_tile_targets(self._h, int(tile_targets)), "start_set_tile_targets")
+
+    def autotune_rates(self, items, reps: int = 2):
+        """Times the batch with every tile size and records the fastest for
+        its size class; returns (best tile, mean ms).  Runs the batch (the
+        outputs are written)."""
+        arr, keep = self._items(items)
+        cur = self._enter(*keep)
+        best, ms = C.c_int(), C.c_double()
+        self._check(lib().start_autotune_rates(self._h, len(items), arr, int(reps), C.byref(best), C.byref(ms)),
+                    "start_autotune_rates")
+        self._leave(cur)
+        return best.value, ms.value
 
     def synchronize(self):
         self._check(lib().start_synchronize(self._h), "start_synchronize")

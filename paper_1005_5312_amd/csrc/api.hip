@@ -106,12 +106,51 @@ start_status ensure_stage(start_ctx *ctx, size_t bytes)
 
 // Enqueues a batch of rate problems (mode 0 rates, 1 counters, 2 list
 // counts, 3 lists), growing scratch and staging when needed.
-start_status enqueue(start_ctx *ctx, const RateSpec *specs, int n, int mode)
+int size_class(int64_t v, int top)
+{
+    int k = 0;
+    while (k < top && ((int64_t)1 << k) < v) ++k;
+    return k;
+}
+
+// Total targets and largest source count of a batch (the autotuning key).
+void batch_size(const RateSpec *specs, int n, int64_t *total, int64_t *max_src)
+{
+    *total = 0;
+    *max_src = 0;
+    for (int i = 0; i < n; ++i) {
+        *total += specs[i].n_t;
+        if (specs[i].tree->n_src > *max_src) *max_src = specs[i].tree->n_src;
+    }
+}
+
+// About total / 4096 targets per wave (a power of two in [1, 64]), which
+// keeps ~4096 waves in flight for small calls (measured on MI355X: 2^12
+// targets run 3x faster with one target per wave than with 64, 2^14 2.4x
+// with 4, 2^16 1.7x with 16; from 2^18 on, 64 is as fast as any).
+int tile_from_size(int64_t total)
+{
+    int h = 1;
+    while (h < 64 && (int64_t)h * 2 * 4096 <= total) h *= 2;
+    return h;
+}
+
+// Targets per wavefront: the fixed choice, else the autotuned one for the
+// size class, else from the size.
+int tile_for(const Ctx &c, int64_t total, int64_t max_src)
+{
+    if (c.tile_fixed > 0) return c.tile_fixed;
+    const int t = c.tile_by_class[size_class(total, 39)][size_class(max_src, 31)];
+    return t > 0 ? t : tile_from_size(total);
+}
+
+start_status enqueue(start_ctx *ctx, const RateSpec *specs, int n, int mode, int tile_override = 0)
 {
     Ctx &c = ctx->c;
-    int64_t total = 0;
-    for (int i = 0; i < n; ++i) total += specs[i].n_t;
-    const int64_t tiles = batch_tiles(specs, n);
+    int64_t total = 0, max_src = 0;
+    batch_size(specs, n, &total, &max_src);
+    const int tile = tile_override > 0 ? tile_override : tile_for(c, total, max_src);
+    const int64_t tiles = batch_tiles(specs, n, tile);
     start_status st = ensure_scratch(ctx, batch_scratch_bytes(total, n, tiles));
     if (st) return st;
     st = ensure_stage(ctx, batch_stage_bytes(n, tiles));
@@ -129,7 +168,7 @@ start_status enqueue(start_ctx *ctx, const RateSpec *specs, int n, int mode)
         ev1 = c.ev_pool[c.ev_used + 1];
         c.ev_used += 2;
     }
-    run_batch(&c, specs, n, mode, c.scratch, ev0, ev1);
+    run_batch(&c, specs, n, mode, tile, c.scratch, ev0, ev1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
     return START_OK;
@@ -534,6 +573,95 @@ start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree
     return cleanup(START_OK);
 }
 
+start_status start_set_tile_targets(start_ctx *ctx, int tile_targets)
+{
+    if (!ctx) return START_EINVAL;
+    if (tile_targets < 0 || tile_targets > 64) return fail(ctx, START_EINVAL, "tile_targets must be in [0, 64]");
+    ctx->c.tile_fixed = tile_targets;
+    return START_OK;
+}
+
+start_status start_autotune_rates(start_ctx *ctx, int n_items, const start_item *items, int reps, int *best_tile,
+                                  double *best_ms)
+{
+    if (best_tile) *best_tile = 0;
+    if (best_ms) *best_ms = 0.0;
+    if (!ctx) return START_EINVAL;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, START_EINVAL, "bad item array");
+    if (reps < 1) return fail(ctx, START_EINVAL, "reps must be >= 1");
+    std::vector<RateSpec> specs;
+    for (int i = 0; i < n_items; ++i) {
+        const start_item &it = items[i];
+        start_status st = check_rate_args(ctx, it.tree, it.grid, it.n_t, it.tgt_xyz, it.theta_crit, it.sigma_cm2,
+                                          it.prec, true);
+        if (st) return st;
+        if (it.n_t > 0 && !it.gamma_out) return fail(ctx, START_EINVAL, "gamma_out is NULL");
+        if (it.n_t == 0) continue;
+        RateSpec r = spec_of(it.tree, it.grid, it.n_t, it.tgt_xyz, it.self_src, it.theta_crit, it.sigma_cm2, it.prec);
+        r.gamma = it.gamma_out;
+        specs.push_back(r);
+    }
+    if (specs.empty()) return START_OK;
+    int64_t total = 0, max_src = 0;
+    batch_size(specs.data(), (int)specs.size(), &total, &max_src);
+    hipSetDevice(ctx->c.device);
+    start_status st = start_synchronize(ctx);
+    if (st) return st;
+    Ctx &c = ctx->c;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return fail(ctx, START_EHIP, "hipEventCreate failed");
+    }
+    // candidates: the size-based choice first, then 64 (one target per lane)
+    // down to one target per wave (the whole wave on one target's rays); a
+    // candidate twice as slow as the best so far on its first run is not
+    // repeated
+    const int first = tile_from_size(total);
+    const int cand[] = {first, 64, 32, 16, 8, 4, 1};
+    int best = first;
+    double best_t = 0.0;
+    for (int ci = 0; ci < (int)(sizeof(cand) / sizeof(cand[0])) && st == START_OK; ++ci) {
+        const int tile = cand[ci];
+        if (ci > 0 && tile == first) continue;
+        st = enqueue(ctx, specs.data(), (int)specs.size(), 0, tile);   // warm (and sizes scratch)
+        if (st) break;
+        double sum = 0.0;
+        int runs = 0;
+        for (int r = 0; r < reps; ++r) {
+            hipEventRecord(e0, c.stream);
+            st = enqueue(ctx, specs.data(), (int)specs.size(), 0, tile);
+            if (st) break;
+            hipEventRecord(e1, c.stream);
+            if (hipEventSynchronize(e1) != hipSuccess) { st = fail(ctx, START_EHIP, "event wait failed"); break; }
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            sum += ms;
+            ++runs;
+            if (r == 0 && best_t > 0.0 && ms > 2.0 * best_t) break;
+        }
+        if (st || runs == 0) break;
+        const double t = sum / runs;
+        // the size-based choice is kept unless another size is clearly (3%)
+        // faster: run-to-run noise must not pick a worse default
+        if (best_t == 0.0 || t < (best == first ? 0.97 : 1.0) * best_t) {
+            best_t = t;
+            best = tile;
+        } else if (tile < best && t > 1.25 * best_t) {
+            break;   // still smaller tiles only add walk work
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    st = start_synchronize(ctx);
+    if (st) return st;
+    c.tile_by_class[size_class(total, 39)][size_class(max_src, 31)] = best;
+    if (best_tile) *best_tile = best;
+    if (best_ms) *best_ms = best_t;
+    return START_OK;
+}
+
 size_t start_estimate_bytes(int64_t n_t, int64_t n_s, int64_t n_gas, int grid_log2, start_precision prec)
 {
     (void)prec;
@@ -543,7 +671,7 @@ size_t start_estimate_bytes(int64_t n_t, int64_t n_s, int64_t n_gas, int grid_lo
     const size_t tree = (size_t)n_s * (8 + 4 + 32 + 16) + (size_t)2 * n_s * (16 + 16 + 32 + 16) +
                         radix_temp_bytes(2 * n_s) + (size_t)n_s * 48 + (size_t)2 * n_s * 44 + 65536;
     const size_t grid = G3 * 12 + (size_t)n_gas * 56 + radix_temp_bytes(n_gas) + G3 * 4 + 65536;
-    const size_t rates = (batch_scratch_bytes(n_t, 1, (n_t + 63) / 64) * 5) / 4 + 65536;
+    const size_t rates = (batch_scratch_bytes(n_t, 1, n_t) * 5) / 4 + 65536;   // up to one tile per target
     return tree + grid + rates;
 }
 

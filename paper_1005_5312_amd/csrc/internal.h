@@ -39,6 +39,11 @@ struct Ctx {
     void *host_stage = nullptr;
     size_t host_stage_bytes = 0;
     hipEvent_t stage_ev = nullptr;
+    // targets per wave of the rate kernels: fixed (1..64), or 0 = from the
+    // autotuned table by size class (ceil(log2) of the total targets and of
+    // the largest tree's sources; 0 entries: chosen from the size)
+    int tile_fixed = 0;
+    int tile_by_class[40][32] = {};
     // walk-kernel timing (start_profile_enable)
     bool profile = false;
     std::vector<hipEvent_t> ev_pool;   // pairs (start, stop)
@@ -138,8 +143,10 @@ struct RateSpec {
 };
 size_t batch_scratch_bytes(int64_t n_targets, int n_items, int64_t n_tiles);
 size_t batch_stage_bytes(int n_items, int64_t n_tiles);
-int64_t batch_tiles(const RateSpec *specs, int n);
-void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, void *scratch, hipEvent_t ev0, hipEvent_t ev1);
+// Tiles of at most `tile` targets (1..64) of one item, one wave each.
+int64_t batch_tiles(const RateSpec *specs, int n, int tile);
+void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *scratch, hipEvent_t ev0,
+               hipEvent_t ev1);
 
 // ---- photoionisation equilibrium (equilibrium.hip) ----
 // x <- equilibrium neutral fraction for gamma (double or float by

@@ -807,22 +807,23 @@ size_t batch_scratch_bytes(int64_t n, int n_items, int64_t n_tiles)
            al256((size_t)nk * sizeof(unsigned)) + al256(radix_temp_bytes(nk)) + 256;
 }
 
-int64_t batch_tiles(const RateSpec *specs, int n)
+int64_t batch_tiles(const RateSpec *specs, int n, int tile)
 {
     int64_t t = 0;
-    for (int i = 0; i < n; ++i) t += (specs[i].n_t + kWave - 1) / kWave;
+    for (int i = 0; i < n; ++i) t += (specs[i].n_t + tile - 1) / tile;
     return t;
 }
 
 // Enqueues a batch (the scratch and the pinned staging area must be large
 // enough: batch_scratch_bytes / stage_bytes).  mode: 0 rates, 1 counters,
 // 2 list counts, 3 lists.  ev0/ev1 (may be null) bracket the rate kernels.
-void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, void *scratch, hipEvent_t ev0, hipEvent_t ev1)
+void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *scratch, hipEvent_t ev0,
+               hipEvent_t ev1)
 {
     hipStream_t s = c->stream;
     int64_t N = 0;
     for (int i = 0; i < n; ++i) N += specs[i].n_t;
-    const int64_t n_tiles = batch_tiles(specs, n);
+    const int64_t n_tiles = batch_tiles(specs, n, tile);
     BatchScratch bs = carve_batch(scratch, N, n, n_tiles);
 
     // host side: item table, offsets, tiles (FP64 items' tiles first)
@@ -890,12 +891,12 @@ void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, void *scratch, hi
     for (int pass = 0; pass < 2; ++pass)   // FP64 items, then FP32C items
         for (int i = 0; i < n; ++i) {
             if ((specs[i].prec == START_FP64) != (pass == 0)) continue;
-            for (int64_t f = 0; f < specs[i].n_t; f += kWave)
-                ht[t64++] = make_int4(i, (int)f, (int)(specs[i].n_t - f < kWave ? specs[i].n_t - f : kWave), 0);
+            for (int64_t f = 0; f < specs[i].n_t; f += tile)
+                ht[t64++] = make_int4(i, (int)f, (int)(specs[i].n_t - f < tile ? specs[i].n_t - f : tile), 0);
         }
     int64_t n64 = 0;
     for (int i = 0; i < n; ++i)
-        if (specs[i].prec == START_FP64) n64 += (specs[i].n_t + kWave - 1) / kWave;
+        if (specs[i].prec == START_FP64) n64 += (specs[i].n_t + tile - 1) / tile;
     hipMemcpyAsync(bs.items, h, stage_bytes(n, n_tiles), hipMemcpyHostToDevice, s);
     hipEventRecord(c->stage_ev, s);
 

@@ -104,9 +104,20 @@ class Executor:
 
 class GpuExecutor(Executor):
     """libstart on one GPU: one Context (HIP stream) per slot; scenes are
-    built on slot 0's context and used from every slot (builds synchronise)."""
+    built on slot 0's context and used from every slot (builds synchronise).
 
-    def __init__(self, device: int = 0, n_slots: int = 2):
+    Without autotune the library picks the tile size from the call's size.
+    With autotune, the first batch of each size class (total targets and
+    largest source count, each rounded up to a power of two) up to 2^17
+    targets on a slot is run through
+    start_autotune_rates, which computes it with several tile sizes and keeps
+    the fastest for that class; later batches of the class use it (results
+    do not depend on it).  This tunes on the request path, so the first
+    batch of a class is slow."""
+
+    TUNE_MAX_CLASS = 17
+
+    def __init__(self, device: int = 0, n_slots: int = 2, autotune: bool = False):
         import torch
 
         from . import binding
@@ -115,6 +126,8 @@ class GpuExecutor(Executor):
         self.n_slots = n_slots
         self.ctxs = [binding.Context(device) for _ in range(n_slots)]
         self.dev = self.ctxs[0].device
+        self.autotune = autotune
+        self.tuned = [set() for _ in range(n_slots)]
 
     def _est(self, n_t, n_s, n_gas, grid_log2, prec):
         return self.binding.estimate_bytes(n_t, n_s, n_gas, grid_log2, prec)
@@ -152,7 +165,14 @@ class GpuExecutor(Executor):
                 out = t.empty(r.n_t, dtype=dt, device=self.dev)
                 items.append(dict(tree=tree, grid=grid, tgt_xyz=xyz, self_src=ss, theta=r.theta, sigma=r.sigma,
                                   prec=r.prec, out=out))
-            ctx.compute_rates_batched(items)
+            total = sum(r.n_t for r in batch)
+            n_src = max(r.scene.n_src for r in batch)
+            key = (max(0, (total - 1).bit_length()), max(0, (n_src - 1).bit_length()))
+            if self.autotune and key[0] <= self.TUNE_MAX_CLASS and key not in self.tuned[slot]:
+                ctx.autotune_rates(items, reps=2)
+                self.tuned[slot].add(key)
+            else:
+                ctx.compute_rates_batched(items)
             ev = t.cuda.Event()
             ev.record(ctx.stream)
         return (ctx, ev, items)

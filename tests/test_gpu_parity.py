@@ -394,3 +394,44 @@ def test_batched_many_uneven_items_bitwise(ctx):
     ctx.synchronize()
     for it, ref in zip(items, singles):
         assert torch.equal(it["out"], ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_tile_size_does_not_change_results(ctx, prec):
+    """Targets per wavefront from 1 (the wave on one target's rays) to 64:
+    every target's terms are summed in its own depth-first order, so the
+    rates are identical bit for bit."""
+    w = H.workload("clumpy", n_gas=1 << 14, n_src=256)
+    dev = ctx.device
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    box = H.box_of(w)
+    tree = ctx.build_source_tree(box, d(w.src_xyz), d(w.src_lum))
+    grid = ctx.build_gas_grid(box, d(w.gas_xyz), d(w.gas_h), d(w.gas_nhi), w.grid_log2)
+    tgt = d(w.tgt_xyz[:, :3001])
+    outs = {}
+    try:
+        for t in (64, 32, 7, 4, 1):
+            ctx.set_tile_targets(t)
+            outs[t] = ctx.compute_rates(tree, grid, tgt, None, 1.0, w.sigma, prec).cpu().numpy()
+    finally:
+        ctx.set_tile_targets(0)
+    for t in outs:
+        assert np.array_equal(outs[t], outs[64]), t
+
+
+def test_autotune_picks_a_tile_and_keeps_results(ctx):
+    w = H.workload("clumpy", n_gas=1 << 14, n_src=256)
+    dev = ctx.device
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    box = H.box_of(w)
+    tree = ctx.build_source_tree(box, d(w.src_xyz), d(w.src_lum))
+    grid = ctx.build_gas_grid(box, d(w.gas_xyz), d(w.gas_h), d(w.gas_nhi), w.grid_log2)
+    items = [dict(tree=tree, grid=grid, tgt_xyz=d(w.tgt_xyz[:, :2000]), self_src=None, theta=1.0, sigma=w.sigma,
+                  prec="fp32c", out=torch.empty(2000, dtype=torch.float32, device=dev))]
+    ref = ctx.compute_rates(tree, grid, items[0]["tgt_xyz"], None, 1.0, w.sigma, "fp32c").cpu().numpy()
+    best, ms = ctx.autotune_rates(items, reps=2)
+    print(f"  autotune 2000 targets: tile {best}, {ms:.3f} ms")
+    assert best in (1, 4, 8, 16, 32, 64) and ms > 0
+    assert np.array_equal(items[0]["out"].cpu().numpy(), ref)
+    again = ctx.compute_rates(tree, grid, items[0]["tgt_xyz"], None, 1.0, w.sigma, "fp32c").cpu().numpy()
+    assert np.array_equal(again, ref)

@@ -38,10 +38,11 @@ def make_requests(scenes, n, seed):
     return reqs
 
 
-def test_alone_equals_mixed_and_oracle():
+@pytest.mark.parametrize("autotune", [False, True])
+def test_alone_equals_mixed_and_oracle(autotune):
     from paper_1005_5312_amd import serve
     scenes = make_scenes()
-    ex = serve.GpuExecutor(0, n_slots=2)
+    ex = serve.GpuExecutor(0, n_slots=2, autotune=autotune)
     # alone: one request at a time
     alone = []
     srv = serve.Server(ex, hbm_budget=8 << 30, max_batch=16).start()
