@@ -213,12 +213,21 @@ start_status start_equilibrium_update(start_ctx *ctx, int64_t n, const double *n
  *   iterations, last_change (host, may be NULL): iterations run and the
  *           largest change of the last one
  * Synchronous (one stream synchronisation per iteration); allocates its
- * grid, particle bins and one n_HI buffer for the duration of the call. */
+ * grid, particle bins and one n_HI buffer for the duration of the call.  The
+ * first iteration stages the rate call (tables, target order); the others
+ * repeat its kernels with the grid refill and the update, replayed from one
+ * captured HIP graph unless start_set_graph_replay turned graphs off.  The
+ * context stream must not be used by other threads during the call. */
 start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree, int64_t n_gas,
                                           const double *gas_xyz, const double *gas_h, const double *n_h,
                                           int grid_log2, double theta_crit, double sigma_cm2, double alpha,
                                           start_precision prec, int max_iter, double tol, double *x_hi,
                                           void *gamma_out, int *iterations, double *last_change);
+
+/* Whether start_ionization_equilibrium replays its iterations from a
+ * captured HIP graph (default on) or launches them one by one.  The results
+ * are the same either way (bit for bit). */
+start_status start_set_graph_replay(start_ctx *ctx, int enable);
 
 /* ---- transfer of recombination photons (section 4.1) ---- */
 

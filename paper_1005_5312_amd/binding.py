@@ -29,7 +29,8 @@ EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_s
            "start_estimate_bytes", "start_tree_export", "start_interaction_lists", "start_grid_export",
            "start_rate_counters", "start_profile_enable", "start_profile_read", "start_equilibrium_update",
            "start_ionization_equilibrium", "start_recombination_emission", "start_total_ionization",
-           "start_compute_dissociation_rates", "start_set_tile_targets", "start_autotune_rates")
+           "start_compute_dissociation_rates", "start_set_tile_targets", "start_autotune_rates",
+           "start_set_graph_replay")
 
 
 class LibraryMissing(RuntimeError):
@@ -106,6 +107,7 @@ def lib():
         "start_total_ionization": ([P, i64, P, P, P, C.c_int, P, P], C.c_int),
         "start_compute_dissociation_rates": ([P, P, P, i64, P, P, d, C.c_int, P], C.c_int),
         "start_set_tile_targets": ([P, C.c_int], C.c_int),
+        "start_set_graph_replay": ([P, C.c_int], C.c_int),
         "start_autotune_rates": ([P, C.c_int, P, C.c_int, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -341,6 +343,11 @@ class Context:
         cur = self._enter(*keep)
         self._check(lib().start_compute_rates_batched(self._h, len(items), arr), "start_compute_rates_batched")
         self._leave(cur)
+
+    def set_graph_replay(self, enable: bool):
+        """Replay the equilibrium iterations from a captured HIP graph (default)
+        or launch them one by one."""
+        self._check(lib().start_set_graph_replay(self._h, 1 if enable else 0), "start_set_graph_replay")
 
     def set_tile_targets(self, tile_targets: int):
         """Targets per wavefront of the rate kernels (1..64), or 0 for the

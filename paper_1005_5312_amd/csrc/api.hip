@@ -144,7 +144,8 @@ int tile_for(const Ctx &c, int64_t total, int64_t max_src)
     return t > 0 ? t : tile_from_size(total);
 }
 
-start_status enqueue(start_ctx *ctx, const RateSpec *specs, int n, int mode, int tile_override = 0)
+start_status enqueue(start_ctx *ctx, const RateSpec *specs, int n, int mode, int tile_override = 0,
+                     BatchLaunch *launch = nullptr)
 {
     Ctx &c = ctx->c;
     int64_t total = 0, max_src = 0;
@@ -168,7 +169,7 @@ start_status enqueue(start_ctx *ctx, const RateSpec *specs, int n, int mode, int
         ev1 = c.ev_pool[c.ev_used + 1];
         c.ev_used += 2;
     }
-    run_batch(&c, specs, n, mode, tile, c.scratch, ev0, ev1);
+    run_batch(&c, specs, n, mode, tile, c.scratch, ev0, ev1, launch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
     return START_OK;
@@ -553,24 +554,79 @@ start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree
     gh.g = grid;
     RateSpec r = spec_of(tree, &gh, n_gas, gas_xyz, nullptr, theta_crit, sigma_cm2, prec);
     r.gamma = gamma_out;
-    for (int it = 1; it <= max_iter; ++it) {
-        fill_grid(&c, bins, it == 1 ? nullptr : nhi, &grid);
-        st = enqueue(ctx, &r, 1, 0);
-        if (st) return cleanup(st);
-        hipMemsetAsync(word, 0, sizeof(*word), c.stream);
+    // The first iteration stages the rate call (tables, target sort); the
+    // later ones repeat the same kernels on the same buffers (grid refill,
+    // rate kernels, equilibrium update), replayed from a HIP graph when
+    // graphs are on.
+    BatchLaunch bl{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    auto iteration_kernels = [&]() {
+        fill_grid(&c, bins, nhi, &grid);
+        relaunch_batch(bl, c.stream);
+        launch_clear_word(&c, word);
         launch_eq_update(&c, n_gas, n_h, gamma_out, prec, alpha, x_hi, nhi, word);
+    };
+    auto drop_graph = [&]() {
+        if (gexec) hipGraphExecDestroy(gexec);
+        if (graph) hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+    };
+    for (int it = 1; it <= max_iter; ++it) {
+        if (it == 1) {
+            fill_grid(&c, bins, nullptr, &grid);
+            st = enqueue(ctx, &r, 1, 0, 0, &bl);
+            if (st) return cleanup(st);
+            launch_clear_word(&c, word);
+            launch_eq_update(&c, n_gas, n_h, gamma_out, prec, alpha, x_hi, nhi, word);
+        } else if (c.graphs) {
+            if (!gexec) {
+                hipError_t e = hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    iteration_kernels();
+                    e = hipStreamEndCapture(c.stream, &graph);
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    drop_graph();
+                    return cleanup(fail(ctx, START_EHIP, hipGetErrorString(e)));
+                }
+            }
+            hipError_t e = hipGraphLaunch(gexec, c.stream);
+            if (e != hipSuccess) {
+                drop_graph();
+                return cleanup(fail(ctx, START_EHIP, hipGetErrorString(e)));
+            }
+        } else {
+            iteration_kernels();
+        }
         unsigned long long bits = 0;
         hipError_t e = hipMemcpyAsync(&bits, word, sizeof(bits), hipMemcpyDeviceToHost, c.stream);
-        if (e != hipSuccess) return cleanup(fail(ctx, START_EHIP, hipGetErrorString(e)));
+        if (e != hipSuccess) {
+            drop_graph();
+            return cleanup(fail(ctx, START_EHIP, hipGetErrorString(e)));
+        }
         st = start_synchronize(ctx);
-        if (st) return cleanup(st);
+        if (st) {
+            drop_graph();
+            return cleanup(st);
+        }
         double change;
         std::memcpy(&change, &bits, sizeof(double));
         if (iterations) *iterations = it;
         if (last_change) *last_change = change;
         if (change <= tol) break;
     }
+    drop_graph();
     return cleanup(START_OK);
+}
+
+start_status start_set_graph_replay(start_ctx *ctx, int enable)
+{
+    if (!ctx) return START_EINVAL;
+    ctx->c.graphs = enable != 0;
+    return START_OK;
 }
 
 start_status start_set_tile_targets(start_ctx *ctx, int tile_targets)

@@ -128,7 +128,11 @@ __global__ void __launch_bounds__(kThreads) total_rate(int64_t n, const double *
     kion[k] = xv * nh * g + ks;
 }
 
+__global__ void clear_u64(unsigned long long *w) { *w = 0ull; }
+
 }  // namespace
+
+void launch_clear_word(Ctx *c, unsigned long long *w) { clear_u64<<<1, 1, 0, c->stream>>>(w); }
 
 void launch_recomb_terms(Ctx *c, int64_t n, const double *n_h, const double *x, const double *vol, double sigma,
                          double alpha_1, double *lum, double *kself)

@@ -44,6 +44,9 @@ struct Ctx {
     // the largest tree's sources; 0 entries: chosen from the size)
     int tile_fixed = 0;
     int tile_by_class[40][32] = {};
+    // replay repeated kernel sequences (the equilibrium iterations) from a
+    // captured HIP graph
+    bool graphs = true;
     // walk-kernel timing (start_profile_enable)
     bool profile = false;
     std::vector<hipEvent_t> ev_pool;   // pairs (start, stop)
@@ -145,8 +148,22 @@ size_t batch_scratch_bytes(int64_t n_targets, int n_items, int64_t n_tiles);
 size_t batch_stage_bytes(int n_items, int64_t n_tiles);
 // Tiles of at most `tile` targets (1..64) of one item, one wave each.
 int64_t batch_tiles(const RateSpec *specs, int n, int tile);
+// The rate kernels of a staged batch: item and tile tables and the sorted
+// targets already in the scratch (rates and counter modes only).  They can
+// be launched again while the scratch, the trees and the grids are
+// unchanged, and contain no host work, so they can be captured in a graph.
+struct BatchLaunch {
+    const void *items;
+    const int4 *tiles;
+    int64_t n_tiles;
+    int64_t n64;     // tiles of FP64 items (first)
+    int mode;
+};
+// Stages a batch (host tables, upload, target sort) and launches it; the
+// launch is described in *launch when non-null.
 void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *scratch, hipEvent_t ev0,
-               hipEvent_t ev1);
+               hipEvent_t ev1, BatchLaunch *launch = nullptr);
+void relaunch_batch(const BatchLaunch &b, hipStream_t s);
 
 // ---- photoionisation equilibrium (equilibrium.hip) ----
 // x <- equilibrium neutral fraction for gamma (double or float by
@@ -155,6 +172,8 @@ void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *s
 // kFlagEqInput in the context's flags word.
 void launch_eq_update(Ctx *c, int64_t n, const double *n_h, const void *gamma, int gamma_prec, double alpha,
                       double *x, double *nhi, unsigned long long *max_change);
+// *w = 0 by a one-thread kernel (graph-safe, unlike a memset node).
+void launch_clear_word(Ctx *c, unsigned long long *w);
 // nhi <- x n_H after checking n_H >= 0 and x in [0, 1].
 void launch_eq_prepare(Ctx *c, int64_t n, const double *n_h, const double *x, double *nhi);
 // Recombination emission alpha_1 n_e n_p V and k_self per particle (either

@@ -818,7 +818,7 @@ int64_t batch_tiles(const RateSpec *specs, int n, int tile)
 // enough: batch_scratch_bytes / stage_bytes).  mode: 0 rates, 1 counters,
 // 2 list counts, 3 lists.  ev0/ev1 (may be null) bracket the rate kernels.
 void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *scratch, hipEvent_t ev0,
-               hipEvent_t ev1)
+               hipEvent_t ev1, BatchLaunch *launch)
 {
     hipStream_t s = c->stream;
     int64_t N = 0;
@@ -914,16 +914,24 @@ void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *s
         else list_kernel<kList><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
         return;
     }
+    BatchLaunch bl{bs.items, bs.tiles, n_tiles, n64, mode};
+    if (launch) *launch = bl;
     if (ev0) hipEventRecord(ev0, s);
-    if (n64 > 0) {
-        if (mode == 1) launch_tiles<START_FP64, true>(bs.items, bs.tiles, n64, s);
-        else launch_tiles<START_FP64, false>(bs.items, bs.tiles, n64, s);
-    }
-    if (n_tiles - n64 > 0) {
-        if (mode == 1) launch_tiles<START_FP32C, true>(bs.items, bs.tiles + n64, n_tiles - n64, s);
-        else launch_tiles<START_FP32C, false>(bs.items, bs.tiles + n64, n_tiles - n64, s);
-    }
+    relaunch_batch(bl, s);
     if (ev1) hipEventRecord(ev1, s);
+}
+
+void relaunch_batch(const BatchLaunch &b, hipStream_t s)
+{
+    const Item *items = static_cast<const Item *>(b.items);
+    if (b.n64 > 0) {
+        if (b.mode == 1) launch_tiles<START_FP64, true>(items, b.tiles, b.n64, s);
+        else launch_tiles<START_FP64, false>(items, b.tiles, b.n64, s);
+    }
+    if (b.n_tiles - b.n64 > 0) {
+        if (b.mode == 1) launch_tiles<START_FP32C, true>(items, b.tiles + b.n64, b.n_tiles - b.n64, s);
+        else launch_tiles<START_FP32C, false>(items, b.tiles + b.n64, b.n_tiles - b.n64, s);
+    }
 }
 
 }  // namespace start

@@ -252,3 +252,22 @@ def test_diffuse_k_ion_pipeline_matches_oracle(ctx, prec):
     rel = float(np.max(np.abs(kion - want) / want))
     print(f"  k_ion {prec}: max rel {rel:.2e}")
     assert rel <= (H.TOL_FP64 if prec == "fp64" else H.TOL_FP32C)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_graph_replay_equals_eager_loop(ctx, prec):
+    """The iterations after the first are replayed from one captured HIP graph;
+    after 1, 2, 3, 7 and 25 iterations (one synchronisation and a host read
+    between replays) x and Gamma equal those of the loop launched kernel by
+    kernel, bit for bit."""
+    w, nh, x0, theta = loop_case("small")
+    for iters in (1, 2, 3, 7, 25):
+        outs = {}
+        for graphs in (False, True):
+            ctx.set_graph_replay(graphs)
+            outs[graphs] = gpu_loop(ctx, w, nh, x0, theta, prec, iters, 0.0)
+        ctx.set_graph_replay(True)
+        (xa, ga, ia, ca), (xb, gb, ib, cb) = outs[False], outs[True]
+        # (the loop also stops early once no x changes at all)
+        assert ia == ib and ia <= iters and ca == cb
+        assert np.array_equal(xa, xb) and np.array_equal(ga, gb), iters
