@@ -62,6 +62,7 @@ def lib():
         L.or_fsh.argtypes = [C.c_double]
         L.or_fsh.restype = C.c_double
         L.or_lw_rates.argtypes = [P, C.c_int, P, i64, P, P, C.c_double, P, C.c_int]
+        L.or_upstream_rates.argtypes = [P, C.c_int, P, i64, P, P, P, P, C.c_double, C.c_double, P, P, P, i64, P]
         _lib = L
     return _lib
 
@@ -214,3 +215,30 @@ def lw_rates(tree: Tree, grid_log2, grid_values, tgt_xyz, self_src=None, theta=1
     _check(lib().or_lw_rates(tree._h, int(grid_log2), _p(g), nt, _p(tgt), _p(ss), float(theta), _p(out),
                              int(nthreads)), "or_lw_rates")
     return out
+
+
+def upstream_rates(tree: Tree, grid_log2, grid_values, xyz, h, nhi, self_src=None, theta=1.0, sigma=6.3e-18,
+                   structure=False):
+    """Gamma per particle with the upstream-particle chain optical depths of
+    section 2.2.1 (the particles are the targets).  With structure=True also
+    returns (offsets [n+1], parents [pairs] as upstream particle index or -1,
+    stats [n, 2] = pairs, pairs integrated along the ray)."""
+    xyz = _f64(xyz).reshape(3, -1)
+    n = xyz.shape[1]
+    g = _f64(grid_values).reshape(-1)
+    ss = None if self_src is None else np.ascontiguousarray(self_src, dtype=np.int64)
+    out = np.zeros(n)
+    offs = np.zeros(n + 1, np.int64)
+    stats = np.zeros((n, 2), np.int64)
+    cap = 0
+    par = None
+    if structure:
+        _check(lib().or_upstream_rates(tree._h, int(grid_log2), _p(g), n, _p(xyz), _p(_f64(h)), _p(_f64(nhi)),
+                                       _p(ss), float(theta), float(sigma), _p(out), _p(offs), None, 0, None),
+               "or_upstream_rates")
+        cap = int(offs[-1])
+        par = np.zeros(max(cap, 1), np.int64)
+    _check(lib().or_upstream_rates(tree._h, int(grid_log2), _p(g), n, _p(xyz), _p(_f64(h)), _p(_f64(nhi)), _p(ss),
+                                   float(theta), float(sigma), _p(out), _p(offs), _p(par), cap, _p(stats)),
+           "or_upstream_rates")
+    return (out, offs, par[:cap], stats) if structure else out

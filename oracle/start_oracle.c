@@ -844,3 +844,197 @@ int or_lw_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n_t
     }
     return err;
 }
+
+/* ------------------------------------------------ upstream-particle chain --- */
+
+typedef struct {
+    int64_t id;    /* virtual source: cell index; individual source: ncells + index */
+    int64_t pos;   /* position in the target's list */
+} or_idpos;
+
+static int cmp_idpos(const void *a, const void *b)
+{
+    const or_idpos *x = (const or_idpos *)a, *y = (const or_idpos *)b;
+    return x->id < y->id ? -1 : (x->id > y->id ? 1 : 0);
+}
+
+int or_upstream_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n,
+                      const double *xyz, const double *h, const double *nhi,
+                      const int64_t *self_src, double theta, double sigma,
+                      double *gamma_out, int64_t *offsets_out, int64_t *parent_out,
+                      int64_t capacity, int64_t *stats)
+{
+    if (!t || !gamma_out || !grid || !h || !nhi || grid_log2 < 0 || grid_log2 > 10) return OR_EINVAL;
+    if (!isfinite(sigma)) return OR_ENONFINITE;
+    if (sigma < 0.0) return OR_EINVAL;
+    int rc = check_targets(&t->box, n, xyz, self_src, t->n, theta);
+    if (rc) return rc;
+    const double ucm = t->box.unit_cm;
+    const int G = 1 << grid_log2;
+    /* 1. the interaction list of every particle (eqs. 12-13) */
+    int64_t *off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t cap = 1024, E = 0;
+    int64_t *ids = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    if (!off || !ids) { free(off); free(ids); return OR_ENOMEM; }
+    or_list L = {0};
+    for (int64_t i = 0; i < n; ++i) {
+        double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
+        rc = list_for(t, x, self_src ? self_src[i] : -1, theta, &L);
+        if (rc) break;
+        if (E + L.n > cap) {
+            while (E + L.n > cap) cap *= 2;
+            int64_t *p = (int64_t *)realloc(ids, (size_t)cap * sizeof(int64_t));
+            if (!p) { rc = OR_ENOMEM; break; }
+            ids = p;
+        }
+        for (int64_t k = 0; k < L.n; ++k)
+            ids[E + k] = L.e[k].cell >= 0 ? L.e[k].cell : t->ncells + L.e[k].src;
+        E += L.n;
+        off[i + 1] = E;
+    }
+    free(L.e);
+    if (rc) { free(off); free(ids); return rc; }
+    if (offsets_out) memcpy(offsets_out, off, ((size_t)n + 1) * sizeof(int64_t));
+    if (parent_out && E > capacity) { free(off); free(ids); return OR_ECAPACITY; }
+
+    /* per pair: source position, luminosity, distance to the particle */
+    double *ra = (double *)malloc((size_t)(E ? E : 1) * 3 * sizeof(double));
+    double *La = (double *)malloc((size_t)(E ? E : 1) * sizeof(double));
+    double *dist = (double *)malloc((size_t)(E ? E : 1) * sizeof(double));
+    int64_t *par = (int64_t *)malloc((size_t)(E ? E : 1) * sizeof(int64_t));
+    double *tau = (double *)malloc((size_t)(E ? E : 1) * sizeof(double));
+    char *done = (char *)calloc((size_t)(E ? E : 1), 1);
+    or_idpos *sorted = (or_idpos *)malloc((size_t)(E ? E : 1) * sizeof(or_idpos));
+    double *ts = (double *)malloc((size_t)(3 * G + 4) * sizeof(double));
+    int64_t *stack = (int64_t *)malloc((size_t)(E ? E : 1) * sizeof(int64_t));
+    if (!ra || !La || !dist || !par || !tau || !done || !sorted || !ts || !stack) { rc = OR_ENOMEM; goto out; }
+    for (int64_t i = 0; i < n; ++i) {
+        const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
+        for (int64_t p = off[i]; p < off[i + 1]; ++p) {
+            const int64_t id = ids[p];
+            if (id < t->ncells) {
+                const or_cell *c = &t->cells[id];
+                for (int k = 0; k < 3; ++k) ra[3 * p + k] = c->com[k];
+                La[p] = c->lum;
+            } else {
+                const int64_t j = id - t->ncells;
+                for (int k = 0; k < 3; ++k) ra[3 * p + k] = t->x[(int64_t)k * t->n + j];
+                La[p] = t->lum[j];
+            }
+            const double dx = x[0] - ra[3 * p], dy = x[1] - ra[3 * p + 1], dz = x[2] - ra[3 * p + 2];
+            dist[p] = sqrt(dx * dx + dy * dy + dz * dz);
+            sorted[p].id = id;
+            sorted[p].pos = p;
+        }
+        qsort(sorted + off[i], (size_t)(off[i + 1] - off[i]), sizeof(or_idpos), cmp_idpos);
+    }
+
+    /* 2-3. the upstream particle of every (particle, source) pair: among the
+     * particle's neighbours (within its 2h) that are closer to the same
+     * (virtual) source and have it in their own list, the one nearest to the
+     * ray (largest cos phi; the lowest index on ties).  None: the pair is a
+     * list-boundary particle and integrates along the ray. */
+    for (int64_t i = 0; i < n; ++i) {
+        const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
+        const double r2 = (2.0 * h[i]) * (2.0 * h[i]);
+        for (int64_t p = off[i]; p < off[i + 1]; ++p) par[p] = -1;
+        double *best = (double *)malloc((size_t)(off[i + 1] - off[i] + 1) * sizeof(double));
+        if (!best) { rc = OR_ENOMEM; goto out; }
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double ex = xyz[j] - x[0], ey = xyz[n + j] - x[1], ez = xyz[2 * n + j] - x[2];
+            if (!(ex * ex + ey * ey + ez * ez <= r2)) continue;       /* not a neighbour */
+            const double y[3] = {xyz[j], xyz[n + j], xyz[2 * n + j]};
+            for (int64_t p = off[i]; p < off[i + 1]; ++p) {
+                or_idpos key = {ids[p], 0};
+                const or_idpos *f = (const or_idpos *)bsearch(&key, sorted + off[j], (size_t)(off[j + 1] - off[j]),
+                                                              sizeof(or_idpos), cmp_idpos);
+                if (!f) continue;                                     /* not in the same list */
+                const int64_t q = f->pos;
+                if (!(dist[q] < dist[p])) continue;                   /* not upstream */
+                const double *a = ra + 3 * p;
+                const double dot = (x[0] - a[0]) * (y[0] - a[0]) + (x[1] - a[1]) * (y[1] - a[1]) +
+                                   (x[2] - a[2]) * (y[2] - a[2]);
+                const double cphi = dot / (dist[p] * dist[q]);
+                if (par[p] < 0 || cphi > best[p - off[i]]) {
+                    par[p] = q;
+                    best[p - off[i]] = cphi;
+                }
+            }
+        }
+        free(best);
+    }
+
+    /* 4. optical depths: tau = tau_up + sigma dl (n_target + n_up) / 2
+     * (eqs. 8-9), dl = d_target - d_up; a pair without an upstream particle
+     * integrates the column along the ray (exact, through the grid). */
+    for (int64_t p0 = 0; p0 < E; ++p0) {
+        int64_t sp = 0, p = p0;
+        while (p >= 0 && !done[p]) {
+            stack[sp++] = p;
+            p = par[p];
+        }
+        while (sp > 0) {
+            p = stack[--sp];
+            /* target particle of pair p */
+            int64_t lo = 0, hi = n;
+            while (hi - lo > 1) {
+                int64_t mid = (lo + hi) / 2;
+                if (off[mid] <= p) lo = mid; else hi = mid;
+            }
+            const int64_t i = lo;
+            const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
+            if (par[p] < 0) {
+                if (dist[p] == 0.0) {
+                    tau[p] = 0.0;
+                } else {
+                    int64_t nc = 0;
+                    tau[p] = sigma * column_buf(&t->box, grid_log2, grid, ra + 3 * p, x, &nc, ts) * ucm;
+                }
+            } else {
+                const int64_t q = par[p];
+                int64_t lo2 = 0, hi2 = n;
+                while (hi2 - lo2 > 1) {
+                    int64_t mid = (lo2 + hi2) / 2;
+                    if (off[mid] <= q) lo2 = mid; else hi2 = mid;
+                }
+                const int64_t j = lo2;
+                tau[p] = tau[q] + sigma * ((dist[p] - dist[q]) * ucm) * (0.5 * (nhi[i] + nhi[j]));
+            }
+            done[p] = 1;
+        }
+    }
+
+    /* 5. the rate per H I atom (eq. A2) with these optical depths */
+    for (int64_t i = 0; i < n; ++i) {
+        double sum = 0.0;
+        int64_t roots = 0;
+        for (int64_t p = off[i]; p < off[i + 1]; ++p) {
+            if (par[p] < 0) ++roots;
+            if (dist[p] == 0.0) continue;
+            const double dcm = dist[p] * ucm;
+            sum += La[p] * exp(-tau[p]) / (dcm * dcm);
+        }
+        gamma_out[i] = sigma / (4.0 * M_PI) * sum;
+        if (stats) {
+            stats[2 * i] = off[i + 1] - off[i];
+            stats[2 * i + 1] = roots;
+        }
+    }
+    if (parent_out) {
+        /* parent as the upstream particle's index (-1: integrated along the ray) */
+        for (int64_t p = 0; p < E; ++p) {
+            if (par[p] < 0) { parent_out[p] = -1; continue; }
+            int64_t lo = 0, hi = n;
+            while (hi - lo > 1) {
+                int64_t mid = (lo + hi) / 2;
+                if (off[mid] <= par[p]) lo = mid; else hi = mid;
+            }
+            parent_out[p] = lo;
+        }
+    }
+out:
+    free(off); free(ids); free(ra); free(La); free(dist); free(par); free(tau); free(done);
+    free(sorted); free(ts); free(stack);
+    return rc;
+}

@@ -122,6 +122,25 @@ int or_lw_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n_t
                 const double *tgt_xyz, const int64_t *self_src, double theta,
                 double *kdis_out, int nthreads);
 
+/* Photoionization rates with the optical depths of the upstream-particle
+ * chain of section 2.2.1 (eqs. 8-9) on the lists of section 2.2.2: the gas
+ * particles are the targets; for each (particle i, virtual source alpha) the
+ * upstream particle is the neighbour j of i (|r_j - r_i| <= 2 h_i, j != i)
+ * that is closer to alpha, has alpha in its own list, and is nearest to the
+ * ray (largest cos phi, lowest index on ties); then
+ *   tau_i = tau_j + sigma (d_i - d_j) (n_HI,i + n_HI,j) / 2,
+ * and a pair without an upstream particle (a list-boundary particle)
+ * integrates the column along the ray through the grid.  nhi: particle
+ * n_HI.  offsets_out [n+1] (may be NULL) receives the list offsets;
+ * parent_out [capacity] (may be NULL) the upstream particle of each pair of
+ * each list, in list order, or -1.  stats [n][2] (may be NULL): pairs, pairs
+ * integrated along the ray.  O(n^2) neighbour search: small n only. */
+int or_upstream_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n,
+                      const double *xyz, const double *h, const double *nhi,
+                      const int64_t *self_src, double theta, double sigma,
+                      double *gamma_out, int64_t *offsets_out, int64_t *parent_out,
+                      int64_t capacity, int64_t *stats);
+
 #ifdef __cplusplus
 }
 #endif
