@@ -360,6 +360,41 @@ def lw_bench(n_gas=1 << 20, n_src=1024, reps=5):
     return out
 
 
+def upstream_bench(reps=3):
+    """Rates with the upstream-particle chain optical depths (section 2.2.1)
+    on the clumpy medium (2^18 particles, 1024 sources, theta = 1), against
+    the ray-integrated rates of the same lists."""
+    import torch
+    import paper_1005_5312_amd as S
+    from paper_1005_5312_amd import workloads as W
+    w = W.make_clumpy()
+    ctx = S.Context(0)
+    dev = torch.device("cuda", 0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    box = S.Box(tuple(float(v) for v in w.box_lo), float(w.box_size), float(w.length_unit_cm))
+    tree = ctx.build_source_tree(box, d(w.src_xyz), d(w.src_lum))
+    grid = ctx.build_gas_grid(box, d(w.gas_xyz), d(w.gas_h), d(w.gas_nhi), w.grid_log2)
+    xyz, h, nhi = d(w.gas_xyz), d(w.gas_h), d(w.gas_nhi)
+    g, offs, _, roots = ctx.compute_rates_upstream(tree, grid, xyz, h, nhi, None, 1.0, w.sigma, structure=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g = ctx.compute_rates_upstream(tree, grid, xyz, h, nhi, None, 1.0, w.sigma)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    ray = ctx.compute_rates(tree, grid, xyz, None, 1.0, w.sigma, "fp64")
+    r = np.abs(np.log(g.cpu().numpy() / ray.cpu().numpy()))
+    out = {"workload": f"{w.n_gas} particles (lognormal, i.i.d.), {w.n_src} sources, theta = 1",
+           "ms_per_call": ms, "evals_per_s": w.n_gas / (ms * 1e-3), "pairs": int(offs[-1]),
+           "pairs_integrated_along_ray": int(roots),
+           "abs_ln_ratio_to_ray_integral": {"median": float(np.median(r)), "p90": float(np.percentile(r, 90))}}
+    log(f"[bench] upstream chain: {ms:.1f} ms per call, {int(offs[-1])} pairs")
+    tree.free()
+    grid.free()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -507,6 +542,11 @@ def main():
         log("[bench] H2 photodissociation rates")
         lw_stats = lw_bench()
 
+    up_stats = None
+    if not args.rates_only:
+        log("[bench] upstream-particle chain")
+        up_stats = upstream_bench()
+
     eq_stats = None
     if not args.no_equilibrium and not args.rates_only:
         log("[bench] photoionisation equilibrium (Test 4 setting)")
@@ -548,6 +588,7 @@ def main():
         "equilibrium": eq_stats,
         "k_ion_terms": kion_stats,
         "h2_dissociation": lw_stats,
+        "upstream_chain": up_stats,
         "work_per_target": {"opening_tests": float(c[:, 0].mean()), "entries": float(c[:, 1].mean()),
                             "grid_cells": float(c[:, 2].mean())},
         "source_sha": sha,

@@ -133,6 +133,30 @@ start_status start_compute_dissociation_rates(start_ctx *ctx, const start_tree *
                                               int64_t n_t, const double *tgt_xyz, const int64_t *self_src,
                                               double theta_crit, start_precision prec, void *kdis_out);
 
+/* Gamma of every gas particle (the particles are the targets) with the
+ * optical depths of the upstream-particle chain of section 2.2.1 (eqs. 8-9)
+ * instead of the ray integral, on the same interaction lists: for each
+ * (particle i, list entry alpha) the upstream particle is the neighbour j
+ * (|r_j - r_i| <= 2 h_i, j != i) that is closer to alpha, has alpha in its
+ * own list and is nearest to the ray (largest cos phi, lowest j on ties);
+ *   tau_i = tau_j + sigma (d_i - d_j) (n_HI,i + n_HI,j) / 2,
+ * and pairs without one (list-boundary particles) integrate along the ray
+ * through `grid`.  FP64.  gas_xyz [3][n_gas], gas_h [n_gas] > 0 (SPH
+ * smoothing lengths: 2h is the neighbour radius), gas_nhi [n_gas] >= 0 (the
+ * particles' own n_HI), self_src as start_compute_rates.  gamma_out [n_gas]
+ * double.  offsets_out [n_gas+1] (host or device, may be NULL) receives the
+ * list offsets; parents_out [capacity] (host or device, may be NULL) the
+ * upstream particle of each pair in the order of start_interaction_lists, or
+ * -1; n_roots_out (host, may be NULL) the number of pairs integrated along
+ * the ray.  Synchronous; allocates its work arrays (about 40 bytes per list
+ * entry) for the duration of the call.  More than 2^31 list entries ->
+ * START_ECAPACITY. */
+start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree, const start_grid *grid,
+                                          int64_t n_gas, const double *gas_xyz, const double *gas_h,
+                                          const double *gas_nhi, const int64_t *self_src, double theta_crit,
+                                          double sigma_cm2, double *gamma_out, int64_t *offsets_out,
+                                          int64_t *parents_out, int64_t capacity, int64_t *n_roots_out);
+
 /* One independent rate problem for start_compute_rates_batched. */
 typedef struct {
     const start_tree *tree;

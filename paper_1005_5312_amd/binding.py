@@ -30,7 +30,7 @@ EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_s
            "start_rate_counters", "start_profile_enable", "start_profile_read", "start_equilibrium_update",
            "start_ionization_equilibrium", "start_recombination_emission", "start_total_ionization",
            "start_compute_dissociation_rates", "start_set_tile_targets", "start_autotune_rates",
-           "start_set_graph_replay")
+           "start_set_graph_replay", "start_compute_rates_upstream")
 
 
 class LibraryMissing(RuntimeError):
@@ -108,6 +108,7 @@ def lib():
         "start_compute_dissociation_rates": ([P, P, P, i64, P, P, d, C.c_int, P], C.c_int),
         "start_set_tile_targets": ([P, C.c_int], C.c_int),
         "start_set_graph_replay": ([P, C.c_int], C.c_int),
+        "start_compute_rates_upstream": ([P, P, P, i64, P, P, P, P, d, d, P, P, P, i64, P], C.c_int),
         "start_autotune_rates": ([P, C.c_int, P, C.c_int, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -309,6 +310,38 @@ class Context:
                     "start_compute_dissociation_rates")
         self._leave(cur)
         return out
+
+    def compute_rates_upstream(self, tree: SourceTree, grid: GasGrid, gas_xyz, gas_h, gas_nhi, self_src=None,
+                               theta: float = 1.0, sigma: float = 6.3e-18, structure: bool = False):
+        """Gamma (float64) of every gas particle with the upstream-particle
+        chain optical depths; with structure=True also (offsets [n+1], parents
+        [pairs] in list-export order, number of pairs integrated along the
+        ray) as numpy arrays.  Synchronous."""
+        import torch
+        xyz = _xyz(gas_xyz, self.device)
+        n = xyz.shape[1]
+        h = _vec(gas_h, self.device)
+        nhi = _vec(gas_nhi, self.device)
+        ss = None if self_src is None else _vec(self_src, self.device, torch.int64)
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        offs = np.zeros(n + 1, np.int64)
+        roots = C.c_int64()
+        cur = self._enter(xyz, h, nhi, ss, out)
+        self._check(lib().start_compute_rates_upstream(self._h, tree._h, grid._h, n, _ptr(xyz), _ptr(h), _ptr(nhi),
+                                                       _ptr(ss), float(theta), float(sigma), _ptr(out),
+                                                       offs.ctypes.data_as(C.c_void_p), None, 0, C.byref(roots)),
+                    "start_compute_rates_upstream")
+        par = None
+        if structure:
+            par = np.zeros(max(int(offs[-1]), 1), np.int64)
+            self._check(lib().start_compute_rates_upstream(self._h, tree._h, grid._h, n, _ptr(xyz), _ptr(h),
+                                                           _ptr(nhi), _ptr(ss), float(theta), float(sigma), _ptr(out),
+                                                           None, par.ctypes.data_as(C.c_void_p), par.size,
+                                                           C.byref(roots)),
+                        "start_compute_rates_upstream")
+            par = par[: int(offs[-1])]
+        self._leave(cur)
+        return (out, offs, par, roots.value) if structure else out
 
     def compute_rates_raw(self, tree: SourceTree, grid: GasGrid, xyz, ss, theta, sigma, prec, out):
         """Enqueues on the context stream with prepared device tensors and no

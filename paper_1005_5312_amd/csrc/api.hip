@@ -402,6 +402,139 @@ start_status start_compute_dissociation_rates(start_ctx *ctx, const start_tree *
     return enqueue(ctx, &r, 1, 0);
 }
 
+start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree, const start_grid *grid,
+                                          int64_t n_gas, const double *gas_xyz, const double *gas_h,
+                                          const double *gas_nhi, const int64_t *self_src, double theta_crit,
+                                          double sigma_cm2, double *gamma_out, int64_t *offsets_out,
+                                          int64_t *parents_out, int64_t capacity, int64_t *n_roots_out)
+{
+    if (n_roots_out) *n_roots_out = 0;
+    start_status st = check_rate_args(ctx, tree, grid, n_gas, gas_xyz, theta_crit, sigma_cm2, START_FP64, true);
+    if (st) return st;
+    if (n_gas > 0 && (!gas_h || !gas_nhi || !gamma_out)) return fail(ctx, START_EINVAL, "gas arrays are NULL");
+    hipSetDevice(ctx->c.device);
+    Ctx &c = ctx->c;
+    hipStream_t s = c.stream;
+    if (n_gas == 0) {
+        const int64_t z = 0;
+        if (offsets_out && hipMemcpy(offsets_out, &z, sizeof(z), hipMemcpyDefault) != hipSuccess)
+            return fail(ctx, START_EHIP, "copy failed");
+        return START_OK;
+    }
+    st = start_synchronize(ctx);
+    if (st) return st;
+    // every buffer of the call, freed at the end
+    std::vector<std::pair<void *, size_t>> bufs;
+    auto alloc = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (dmalloc(&c, &p, bytes) != hipSuccess) return nullptr;
+        bufs.push_back({p, bytes});
+        return p;
+    };
+    GasBins bins;
+    bool have_bins = false;
+    auto done = [&](start_status code) {
+        hipStreamSynchronize(s);
+        if (have_bins) free_bins(&c, &bins);
+        for (auto &b : bufs) dfree(&c, b.first, b.second);
+        return code;
+    };
+    auto nomem = [&]() { return done(fail(ctx, c.budget ? START_EBUDGET : START_ENOMEM, "device allocation failed")); };
+    const int64_t n = n_gas;
+    // 1. list sizes and offsets (32-bit: the pairs are counted in unsigned)
+    int64_t *off64 = (int64_t *)alloc((size_t)(n + 1) * sizeof(int64_t));
+    unsigned *off = (unsigned *)alloc((size_t)(n + 1) * sizeof(unsigned));
+    void *scan_tmp = alloc(scan_temp_bytes(n + 1) + (size_t)(n + 1) * sizeof(unsigned));
+    if (!off64 || !off || !scan_tmp) return nomem();
+    RateSpec r = spec_of(tree, grid, n, gas_xyz, self_src, theta_crit, sigma_cm2, START_FP64);
+    r.counts = off64;
+    st = enqueue(ctx, &r, 1, 2);
+    if (st) return done(st);
+    launch_to_u32(&c, n, off64, off);
+    hipMemsetAsync(off + n, 0, sizeof(unsigned), s);
+    exclusive_scan_u32(off, n + 1, scan_tmp, s);
+    unsigned total_u = 0;
+    hipMemcpyAsync(&total_u, off + n, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    st = start_synchronize(ctx);
+    if (st) return done(st);
+    const int64_t E = total_u;
+    // (sums of at most 2^31 fit: a wrapped sum shows as offsets going down)
+    if (E > ((int64_t)1 << 31) - 1) return done(fail(ctx, START_ECAPACITY, "more than 2^31 list entries"));
+    launch_to_i64(&c, n + 1, off, off64);
+    const size_t Eb = (size_t)(E > 0 ? E : 1);
+    uint64_t *keys = (uint64_t *)alloc(Eb * sizeof(uint64_t));
+    unsigned *owner = (unsigned *)alloc(Eb * sizeof(unsigned));
+    int *par = (int *)alloc(Eb * sizeof(int));
+    int *par2 = (int *)alloc(Eb * sizeof(int));
+    double *acc = (double *)alloc(Eb * sizeof(double));
+    double *acc2 = (double *)alloc(Eb * sizeof(double));
+    unsigned *roots = (unsigned *)alloc(Eb * sizeof(unsigned));
+    unsigned *words = (unsigned *)alloc(256);   // [0] root count, [1] "more" flag
+    unsigned *nbc = (unsigned *)alloc((size_t)(n + 1) * sizeof(unsigned));
+    if (!keys || !owner || !par || !par2 || !acc || !acc2 || !roots || !words || !nbc) return nomem();
+    // 2. the lists as sorted keys, and the owner of every pair
+    r.counts = nullptr;
+    r.offsets = off64;
+    r.entries = (int64_t *)keys;
+    st = enqueue(ctx, &r, 1, 4);
+    if (st) return done(st);
+    launch_pair_owner(&c, n, off, owner);
+    // 3. neighbours within 2h (particles binned on the grid's cells)
+    st = bin_gas(&c, tree->t.box, n, gas_xyz, gas_h, gas_nhi, grid->g.grid_log2, &bins);
+    if (st) return done(st == START_ENOMEM && c.budget ? START_EBUDGET : st);
+    have_bins = true;
+    launch_neighbours(&c, bins, n, gas_xyz, gas_h, nbc, nullptr, nullptr);
+    hipMemsetAsync(nbc + n, 0, sizeof(unsigned), s);
+    exclusive_scan_u32(nbc, n + 1, scan_tmp, s);
+    unsigned n_nb = 0;
+    hipMemcpyAsync(&n_nb, nbc + n, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "neighbour count failed"));
+    unsigned *nb = (unsigned *)alloc((size_t)(n_nb > 0 ? n_nb : 1) * sizeof(unsigned));
+    if (!nb) return nomem();
+    launch_neighbours(&c, bins, n, gas_xyz, gas_h, nullptr, nbc, nb);
+    // 4. upstream pair of every pair, its step, and the roots
+    hipMemsetAsync(words, 0, 256, s);
+    launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, off, keys, owner, nbc, nb, sigma_cm2, par, acc, roots,
+                           words);
+    unsigned n_roots = 0;
+    hipMemcpyAsync(&n_roots, words, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "upstream search failed"));
+    if (n_roots_out) *n_roots_out = n_roots;
+    // 5. roots: the column along the ray
+    launch_upstream_roots(&c, &tree->t, &grid->g, n_roots, roots, keys, owner, gas_xyz, n, sigma_cm2, acc);
+    // 6. sums along the chains by pointer jumping
+    for (int round = 0;; ++round) {
+        if (round > 40) return done(fail(ctx, START_EHIP, "upstream chains did not resolve"));
+        hipMemsetAsync(words + 1, 0, sizeof(unsigned), s);
+        launch_jump(&c, E, par, acc, par2, acc2, words + 1);
+        std::swap(par, par2);
+        std::swap(acc, acc2);
+        unsigned more = 0;
+        hipMemcpyAsync(&more, words + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+        if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "pointer jumping failed"));
+        if (!more) break;
+    }
+    // 7. the rates
+    launch_upstream_gamma(&c, &tree->t, n, gas_xyz, off, keys, acc, sigma_cm2, gamma_out);
+    // exports
+    hipError_t e = hipSuccess;
+    if (offsets_out) e = hipMemcpyAsync(offsets_out, off64, (size_t)(n + 1) * sizeof(int64_t), hipMemcpyDefault, s);
+    if (e == hipSuccess && parents_out) {
+        if (E > capacity) return done(fail(ctx, START_ECAPACITY, "parents capacity too small"));
+        int64_t *pp = (int64_t *)alloc(Eb * sizeof(int64_t));
+        if (!pp) return nomem();
+        // the pair-level parent is lost to the jumping; search again
+        hipMemsetAsync(words, 0, 256, s);
+        launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, off, keys, owner, nbc, nb, sigma_cm2, par2, acc2,
+                               roots, words);
+        launch_parent_particle(&c, E, par2, owner, pp);
+        if (E > 0) e = hipMemcpyAsync(parents_out, pp, (size_t)E * sizeof(int64_t), hipMemcpyDefault, s);
+    }
+    if (e != hipSuccess) return done(fail(ctx, START_EHIP, hipGetErrorString(e)));
+    st = start_synchronize(ctx);
+    return done(st);
+}
+
 start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const start_item *items)
 {
     if (!ctx) return START_EINVAL;

@@ -184,6 +184,38 @@ void launch_recomb_terms(Ctx *c, int64_t n, const double *n_h, const double *x, 
 void launch_total_rate(Ctx *c, int64_t n, const double *n_h, const double *x, const void *gamma, int gamma_prec,
                        const double *kself, double *kion);
 
+// ---- upstream-particle chain (upstream.hip, rates.hip) ----
+// A list entry as a sortable key: node << 32 | (bucket member + 1, or 0);
+// the (virtual) source it stands for: the node's centre and luminosity, or
+// the bucket member's position and luminosity.
+__device__ inline double4 source_of_key(const double4 *__restrict__ mom, const double4 *__restrict__ src,
+                                        const int *__restrict__ first, uint64_t key)
+{
+    const int node = (int)(key >> 32);
+    const unsigned m = (unsigned)(key & 0xffffffffu);
+    return m == 0 ? mom[node] : src[first[node] + (int)m - 1];
+}
+// acc[p] = optical depth along the ray of each root pair p (FP64 march).
+void launch_upstream_roots(Ctx *c, const Tree *t, const Grid *g, int64_t n_roots, const unsigned *roots,
+                           const uint64_t *keys, const unsigned *owner, const double *xyz, int64_t n, double sigma,
+                           double *acc);
+
+void launch_to_u32(Ctx *c, int64_t n, const int64_t *in, unsigned *out);
+void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out);
+// Neighbours within 2 h_i: counts (nb_off null) or the lists at nb_off.
+void launch_neighbours(Ctx *c, const GasBins &b, int64_t n, const double *xyz, const double *h, unsigned *count,
+                       const unsigned *nb_off, unsigned *nb);
+void launch_pair_owner(Ctx *c, int64_t n, const unsigned *off, unsigned *owner);
+void launch_upstream_parent(Ctx *c, const Tree *t, int64_t n_pairs, int64_t n, const double *xyz, const double *nhi,
+                            const unsigned *off, const uint64_t *keys, const unsigned *owner, const unsigned *nb_off,
+                            const unsigned *nb, double sigma, int *parent, double *acc, unsigned *roots,
+                            unsigned *n_roots);
+void launch_jump(Ctx *c, int64_t n_pairs, const int *par_in, const double *acc_in, int *par_out, double *acc_out,
+                 unsigned *more);
+void launch_upstream_gamma(Ctx *c, const Tree *t, int64_t n, const double *xyz, const unsigned *off,
+                           const uint64_t *keys, const double *tau, double sigma, double *gamma);
+void launch_parent_particle(Ctx *c, int64_t n_pairs, const int *parent, const unsigned *owner, int64_t *out);
+
 // ---- Morton keys (tree.hip) ----
 void launch_keys(const start_box &box, int64_t n, const double *xyz, const double *lum,
                  uint64_t *keys, unsigned *idx, unsigned *flags, hipStream_t s);

@@ -33,7 +33,7 @@ constexpr int kWave = 64;
 constexpr int kThreads = 256;
 constexpr int kWavesPerBlock = kThreads / kWave;
 
-enum Mode { kRates = 0, kCount = 1, kList = 2, kStats = 3 };
+enum Mode { kRates = 0, kCount = 1, kList = 2, kStats = 3, kKeys = 4 };
 
 // One rate problem: a tree, a grid and a run of targets (the item's segment
 // of the batch's sorted target arrays).  Read by the kernels from a device
@@ -308,10 +308,14 @@ __global__ void __launch_bounds__(kThreads) list_kernel(const Item *__restrict__
         }
     }
     int64_t n_entries = 0;
-    const int64_t out_base = (MODE == kList && valid) ? P.offsets[orig] : 0;
-    auto emit = [&](int64_t code, double L) {
+    const int64_t out_base = ((MODE == kList || MODE == kKeys) && valid) ? P.offsets[orig] : 0;
+    // kList writes the export code (node index, or -(source index)-1);
+    // kKeys writes node << 32 | (bucket member + 1, or 0), which increases
+    // along the walk, so each target's keys come out sorted
+    auto emit = [&](int64_t code, uint64_t key, double L) {
         if (!(L > 0.0)) return;
         if (MODE == kList) P.entries[out_base + n_entries] = code;
+        if (MODE == kKeys) P.entries[out_base + n_entries] = (int64_t)key;
         ++n_entries;
     };
     int resume = 0, node = 0;
@@ -322,21 +326,24 @@ __global__ void __launch_bounds__(kThreads) list_kernel(const Item *__restrict__
         const int kind = g.w >> 8;
         const bool active = valid && node >= resume;
         if (kind == kKindLeaf) {
-            if (active && (int64_t)P.ref[node] != self) emit(-(int64_t)P.ref[node] - 1, P.mom[node].w);
+            if (active && (int64_t)P.ref[node] != self)
+                emit(-(int64_t)P.ref[node] - 1, (uint64_t)node << 32, P.mom[node].w);
             node += 1;
             continue;
         }
         const int sk = P.skip[node];
         const bool acc = active && accept(g, u, P.theta2);
         if (acc) {
-            emit(node, P.mom[node].w);
+            emit(node, (uint64_t)node << 32, P.mom[node].w);
             resume = sk;
         }
         const bool open = active && !acc;
         if (kind == kKindBucket) {
             if (open)
                 for (int q = P.first[node]; q < P.first[node] + P.count[node]; ++q)
-                    if ((int64_t)P.perm[q] != self) emit(-(int64_t)P.perm[q] - 1, P.src[q].w);
+                    if ((int64_t)P.perm[q] != self)
+                        emit(-(int64_t)P.perm[q] - 1, (uint64_t)node << 32 | (uint64_t)(q - P.first[node] + 1),
+                             P.src[q].w);
             node += 1;
             continue;
         }
@@ -908,10 +915,11 @@ void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *s
     radix_sort_pairs(bs.keys, bs.vals, N, bits, bs.radix_tmp, s);
     batch_gather<<<nb, kThreads, 0, s>>>(N, bs.offsets, bs.items, bs.keys, bs.vals, bs.tgt, bs.tgt_orig);
 
-    if (mode == 2 || mode == 3) {
+    if (mode == 2 || mode == 3 || mode == 4) {
         const unsigned lb = (unsigned)((n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
         if (mode == 2) list_kernel<kCount><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
-        else list_kernel<kList><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
+        else if (mode == 3) list_kernel<kList><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
+        else list_kernel<kKeys><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
         return;
     }
     BatchLaunch bl{bs.items, bs.tiles, n_tiles, n64, mode};
@@ -932,6 +940,65 @@ void relaunch_batch(const BatchLaunch &b, hipStream_t s)
         if (b.mode == 1) launch_tiles<START_FP32C, true>(items, b.tiles + b.n64, b.n_tiles - b.n64, s);
         else launch_tiles<START_FP32C, false>(items, b.tiles + b.n64, b.n_tiles - b.n64, s);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Upstream-particle chain: optical depth of the pairs (particle, source) that
+// have no upstream particle, integrated along the ray as in the rate kernel
+// (FP64).  key: node << 32 | (bucket member + 1, or 0).
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ void __launch_bounds__(256) upstream_roots(int64_t n_roots, const unsigned *__restrict__ roots,
+                                                      const uint64_t *__restrict__ keys,
+                                                      const unsigned *__restrict__ owner, const double *__restrict__ xyz,
+                                                      int64_t n, const double4 *__restrict__ mom,
+                                                      const double4 *__restrict__ src, const int *__restrict__ first,
+                                                      const double *__restrict__ grid, int G, double lo0, double lo1,
+                                                      double lo2, double gs, double tau_scale, double *__restrict__ acc)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n_roots) return;
+    const unsigned p = roots[r];
+    const unsigned i = owner[p];
+    const double4 a = source_of_key(mom, src, first, keys[p]);
+    const double lo[3] = {lo0, lo1, lo2};
+    const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
+    const double A[3] = {(a.x - lo[0]) * gs, (a.y - lo[1]) * gs, (a.z - lo[2]) * gs};
+    int tb[3];
+    double fb[3], D[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double B = (x[k] - lo[k]) * gs;
+        int b = (int)floor(B);
+        b = b < 0 ? 0 : (b > G - 1 ? G - 1 : b);
+        tb[k] = b;
+        fb[k] = B - (double)b;
+        D[k] = A[k] - ((double)tb[k] + fb[k]);
+    }
+    const double d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+    if (!(d2 > 0.0)) {
+        acc[p] = 0.0;
+        return;
+    }
+    int nc = 0;
+    const unsigned tcell = (unsigned)((tb[0] * G + tb[1]) * G + tb[2]);
+    const double col = march<double, false>(grid, G, (unsigned)(G * G * G - 1), tcell, fb, D, nc);
+    acc[p] = tau_scale * (col * sqrt(d2));
+}
+
+}  // namespace
+
+void launch_upstream_roots(Ctx *c, const Tree *t, const Grid *g, int64_t n_roots, const unsigned *roots,
+                           const uint64_t *keys, const unsigned *owner, const double *xyz, int64_t n, double sigma,
+                           double *acc)
+{
+    if (n_roots <= 0) return;
+    const double gs = (double)g->G / t->box.size;
+    const double tau_scale = sigma * (t->box.size / g->G * t->box.length_unit_cm);
+    upstream_roots<<<(unsigned)((n_roots + 255) / 256), 256, 0, c->stream>>>(
+        n_roots, roots, keys, owner, xyz, n, t->mom, t->src, t->first, g->val, g->G, t->box.lo[0], t->box.lo[1],
+        t->box.lo[2], gs, tau_scale, acc);
 }
 
 }  // namespace start
