@@ -229,6 +229,16 @@ def batch_bench(n_inst=256, n_p=1 << 14, seed=9, reps=3):
     ctx.synchronize()
     t_single_tuned = (time.perf_counter() - t0) / reps
     n_total = sum(it["tgt_xyz"].shape[1] for it in items)
+    # the same batch in plain FP64 (same lists and rays, FP64 grid and sums)
+    items64 = [dict(it, prec="fp64", out=torch.empty(it["out"].numel(), dtype=torch.float64, device=dev))
+               for it in items]
+    ctx.compute_rates_batched(items64)
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.compute_rates_batched(items64)
+    ctx.synchronize()
+    t_batched64 = (time.perf_counter() - t0) / reps
     for tree, grid, *_ in built:
         tree.free()
         grid.free()
@@ -236,6 +246,7 @@ def batch_bench(n_inst=256, n_p=1 << 14, seed=9, reps=3):
     return {"instances": n_inst, "targets_each": n_p, "batched_ms": t_batched * 1e3,
             "one_call_each_ms": t_single * 1e3, "batched_evals_per_s": n_total / t_batched,
             "one_call_each_evals_per_s": n_total / t_single,
+            "batched_fp64_ms": t_batched64 * 1e3, "batched_fp64_evals_per_s": n_total / t_batched64,
             "autotuned": {"batch_tile_targets": best_batch, "batched_ms": t_batched_tuned * 1e3,
                           "batched_evals_per_s": n_total / t_batched_tuned,
                           "single_tile_targets": best_single, "one_call_each_ms": t_single_tuned * 1e3,
