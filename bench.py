@@ -292,6 +292,28 @@ def equilibrium_bench(n_gas=1 << 21, grid_log2=7, tol=1e-4, max_iter=200):
                      "photoionisations_over_source_rate": ph}
         log(f"[bench] equilibrium {prec}: {it} iterations, {dt * 1e3:.1f} ms")
     tree.free()
+    # with the transfer of recombination photons (every particle an emitter,
+    # the tree rebuilt every iteration), against on the spot, at 2^18 / G = 64
+    e2 = W.make_stromgren(n_gas=1 << 18, grid_log2=6)
+    w2 = e2.work
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xd, _, itd, chd = ctx.diffuse_equilibrium(box, w2.gas_xyz, w2.gas_h, e2.n_h, e2.volume_cm3, w2.src_xyz,
+                                              w2.src_lum, e2.x_init, 6, 1.0, w2.sigma, 4.18e-13, 1.58e-13, "fp32c",
+                                              max_iter, 1e-3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tree2 = ctx.build_source_tree(box, torch.from_numpy(w2.src_xyz).to(dev), torch.from_numpy(w2.src_lum).to(dev))
+    xo, _, ito, _ = ctx.ionization_equilibrium(tree2, w2.gas_xyz, w2.gas_h, e2.n_h, e2.x_init, 6, 1.0, w2.sigma,
+                                               e2.alpha_b, "fp32c", max_iter, 1e-3)
+    tree2.free()
+    rad = lambda x: (3.0 * float(np.sum((1.0 - x.cpu().numpy()) * e2.volume_cm3)) / (4.0 * np.pi)) ** (1 / 3) \
+        / W.KPC_CM  # noqa: E731
+    out["with_recombination_photons"] = {
+        "workload": f"{1 << 18} particles, G = 64, every particle an emitter (alpha_1 = 1.58e-13), FP32C",
+        "iterations": itd, "last_change": chd, "ms_total": dt * 1e3, "ms_per_iteration": dt * 1e3 / itd,
+        "ionised_radius_kpc": rad(xd), "on_the_spot_ionised_radius_kpc": rad(xo), "on_the_spot_iterations": ito}
+    log(f"[bench] equilibrium with recombination photons: {itd} iterations, {dt * 1e3:.1f} ms")
     ctx.close()
     return out
 

@@ -248,6 +248,27 @@ start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree
                                           start_precision prec, int max_iter, double tol, double *x_hi,
                                           void *gamma_out, int *iterations, double *last_change);
 
+/* Photoionisation equilibrium with the transfer of recombination photons
+ * (section 4.1) instead of the on-the-spot approximation: each iteration
+ * makes every gas particle an emitter of alpha_1 n_e n_p V (eq. 19) next to
+ * the n_star stars, builds the source tree of both, grids n_HI = x n_H,
+ * evaluates Gamma of every particle from every other emitter (self
+ * excluded, k_other of eqs. 25-26) and solves
+ *   x Gamma = alpha_eff n_H (1 - x)^2,  alpha_eff = alpha_A - alpha_1 (1 - exp(-tau_self)),
+ * i.e. k_other + k_self = alpha_A n_e n_p with k_self of eq. (30) taking its
+ * optical depth (eq. 28) from the previous iterate.  Stops as
+ * start_ionization_equilibrium.  box: the cube of the particles and stars;
+ * volume_cm3 [n_gas] >= 0 (V of each particle); star_xyz [3][n_star],
+ * star_lum [n_star] (photons/s); alpha_A > alpha_1 >= 0.  Other arguments as
+ * start_ionization_equilibrium.  Synchronous; allocates its tree, grid and
+ * work arrays for the duration of the call. */
+start_status start_diffuse_equilibrium(start_ctx *ctx, const start_box *box, int64_t n_gas, const double *gas_xyz,
+                                       const double *gas_h, const double *n_h, const double *volume_cm3,
+                                       int64_t n_star, const double *star_xyz, const double *star_lum, int grid_log2,
+                                       double theta_crit, double sigma_cm2, double alpha_a, double alpha_1,
+                                       start_precision prec, int max_iter, double tol, double *x_hi, void *gamma_out,
+                                       int *iterations, double *last_change);
+
 /* Whether start_ionization_equilibrium replays its iterations from a
  * captured HIP graph (default on) or launches them one by one.  The results
  * are the same either way (bit for bit). */

@@ -123,3 +123,45 @@ def k_ion_total(gamma_other, n_h, x, k_self_values):
     Gamma the rate per H I atom from every other emitter, eq. A2)."""
     return np.asarray(x, dtype=np.float64) * np.asarray(n_h, dtype=np.float64) * \
         np.asarray(gamma_other, dtype=np.float64) + np.asarray(k_self_values, dtype=np.float64)
+
+
+def effective_recombination(n_h, x, volume_cm3, sigma, alpha_a, alpha_1):
+    """With the transfer of recombination photons every recombination (alpha_A)
+    counts, and a particle's own ground-state photons reionise it at the rate
+    k_self of eq. (30).  Taking k_self's optical depth from the previous
+    iterate, k_ion = alpha_A n_e n_p becomes x n_H Gamma = alpha_eff n_H^2 (1-x)^2
+    with alpha_eff = alpha_A - alpha_1 (1 - exp(-tau_self)), which tends to
+    alpha_B = alpha_A - alpha_1 where the gas is opaque (the statement after
+    eq. 30)."""
+    tau = self_optical_depth(n_h, x, volume_cm3, sigma)
+    return alpha_a - alpha_1 * (-np.expm1(-tau))
+
+
+def diffuse_equilibrium(box, gas_xyz, gas_h, n_h, volume_cm3, star_xyz, star_lum, x_init, grid_log2, theta, sigma,
+                        alpha_a, alpha_1, max_iter=100, tol=1e-4):
+    """Equilibrium with the transfer of recombination photons (section 4.1):
+    every particle emits alpha_1 n_e n_p V (eq. 19) from its position, the
+    stars their own photons; each iteration builds the source tree of the
+    particles and stars, grids n_HI = x n_H, evaluates Gamma of every
+    particle from every other emitter (self excluded, eqs. 25-26) and solves
+    x Gamma = alpha_eff n_H (1 - x)^2 (effective_recombination).  Stops as
+    ionization_equilibrium does.  Returns (x, gamma, iterations, last_change)."""
+    x = np.array(x_init, dtype=np.float64, copy=True)
+    n = x.size
+    n_h = np.asarray(n_h, dtype=np.float64)
+    src = np.ascontiguousarray(np.concatenate([np.asarray(gas_xyz, dtype=np.float64),
+                                               np.asarray(star_xyz, dtype=np.float64).reshape(3, -1)], axis=1))
+    self_src = np.arange(n, dtype=np.int64)
+    change, it, gamma = np.inf, 0, None
+    while it < max_iter:
+        it += 1
+        lum = np.concatenate([recombination_emission(n_h, x, volume_cm3, alpha_1), np.asarray(star_lum, float)])
+        tree = O.Tree(box, src, lum)
+        g = O.grid(box, gas_xyz, gas_h, x * n_h, grid_log2)
+        gamma = O.rates(tree, grid_log2, g, gas_xyz, self_src, theta, sigma)
+        x_new = neutral_fraction(gamma, n_h, effective_recombination(n_h, x, volume_cm3, sigma, alpha_a, alpha_1))
+        change = float(np.max(np.abs(x_new - x))) if n else 0.0
+        x = x_new
+        if change <= tol:
+            break
+    return x, gamma, it, change

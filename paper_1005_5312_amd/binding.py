@@ -30,7 +30,7 @@ EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_s
            "start_rate_counters", "start_profile_enable", "start_profile_read", "start_equilibrium_update",
            "start_ionization_equilibrium", "start_recombination_emission", "start_total_ionization",
            "start_compute_dissociation_rates", "start_set_tile_targets", "start_autotune_rates",
-           "start_set_graph_replay", "start_compute_rates_upstream")
+           "start_set_graph_replay", "start_compute_rates_upstream", "start_diffuse_equilibrium")
 
 
 class LibraryMissing(RuntimeError):
@@ -108,6 +108,8 @@ def lib():
         "start_compute_dissociation_rates": ([P, P, P, i64, P, P, d, C.c_int, P], C.c_int),
         "start_set_tile_targets": ([P, C.c_int], C.c_int),
         "start_set_graph_replay": ([P, C.c_int], C.c_int),
+        "start_diffuse_equilibrium": ([P, P, i64, P, P, P, P, i64, P, P, C.c_int, d, d, d, d, C.c_int, C.c_int, d,
+                                       P, P, P, P], C.c_int),
         "start_compute_rates_upstream": ([P, P, P, i64, P, P, P, P, d, d, P, P, P, i64, P], C.c_int),
         "start_autotune_rates": ([P, C.c_int, P, C.c_int, P, P], C.c_int),
     }
@@ -469,6 +471,35 @@ class Context:
                     "start_total_ionization")
         self._leave(cur)
         return out
+
+    def diffuse_equilibrium(self, box: Box, gas_xyz, gas_h, n_h, volume_cm3, star_xyz, star_lum, x_init,
+                            grid_log2: int, theta: float = 1.0, sigma: float = 6.3e-18, alpha_a: float = 4.18e-13,
+                            alpha_1: float = 1.58e-13, prec="fp64", max_iter: int = 100, tol: float = 1e-4):
+        """Equilibrium with the transfer of recombination photons (see
+        start_diffuse_equilibrium).  Returns (x, gamma, iterations,
+        last_change)."""
+        import torch
+        p = _prec(prec)
+        xyz = _xyz(gas_xyz, self.device)
+        n = xyz.shape[1]
+        h, nh, vol = (_vec(a, self.device) for a in (gas_h, n_h, volume_cm3))
+        x = _vec(x_init, self.device).clone()
+        sxyz = _xyz(star_xyz, self.device)
+        slum = _vec(star_lum, self.device)
+        if h.numel() != n or nh.numel() != n or vol.numel() != n or x.numel() != n or slum.numel() != sxyz.shape[1]:
+            raise ValueError("per-particle and per-star arrays have the wrong lengths")
+        gamma = torch.empty(n, dtype=torch.float64 if p == FP64 else torch.float32, device=self.device)
+        it, ch = C.c_int(), C.c_double()
+        b = box.c()
+        cur = self._enter(xyz, h, nh, vol, x, sxyz, slum, gamma)
+        self._check(lib().start_diffuse_equilibrium(self._h, C.byref(b), n, _ptr(xyz), _ptr(h), _ptr(nh), _ptr(vol),
+                                                    sxyz.shape[1], _ptr(sxyz), _ptr(slum), int(grid_log2),
+                                                    float(theta), float(sigma), float(alpha_a), float(alpha_1), p,
+                                                    int(max_iter), float(tol), _ptr(x), _ptr(gamma), C.byref(it),
+                                                    C.byref(ch)),
+                    "start_diffuse_equilibrium")
+        self._leave(cur)
+        return x, gamma, it.value, ch.value
 
     def ionization_equilibrium(self, tree: SourceTree, gas_xyz, gas_h, n_h, x_init, grid_log2: int,
                                theta: float = 1.0, sigma: float = 6.3e-18, alpha: float = 2.6e-13,

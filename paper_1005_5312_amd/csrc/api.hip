@@ -755,6 +755,124 @@ start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree
     return cleanup(START_OK);
 }
 
+start_status start_diffuse_equilibrium(start_ctx *ctx, const start_box *box, int64_t n_gas, const double *gas_xyz,
+                                       const double *gas_h, const double *n_h, const double *volume_cm3,
+                                       int64_t n_star, const double *star_xyz, const double *star_lum, int grid_log2,
+                                       double theta_crit, double sigma_cm2, double alpha_a, double alpha_1,
+                                       start_precision prec, int max_iter, double tol, double *x_hi, void *gamma_out,
+                                       int *iterations, double *last_change)
+{
+    if (iterations) *iterations = 0;
+    if (last_change) *last_change = 0.0;
+    if (!ctx) return START_EINVAL;
+    start_status st = check_box(ctx, box);
+    if (st) return st;
+    if (n_gas < 0 || n_star < 0) return fail(ctx, START_EINVAL, "n_gas or n_star < 0");
+    if (n_gas + n_star > ((int64_t)1 << 30)) return fail(ctx, START_EINVAL, "too many particles and stars");
+    if (n_gas > 0 && (!gas_xyz || !gas_h || !n_h || !volume_cm3 || !x_hi || !gamma_out))
+        return fail(ctx, START_EINVAL, "equilibrium arrays are NULL");
+    if (n_star > 0 && (!star_xyz || !star_lum)) return fail(ctx, START_EINVAL, "star arrays are NULL");
+    if (!std::isfinite(theta_crit) || !std::isfinite(sigma_cm2) || !std::isfinite(alpha_a) || !std::isfinite(alpha_1) ||
+        !std::isfinite(tol))
+        return fail(ctx, START_ENONFINITE, "theta, sigma, alpha or tol not finite");
+    if (theta_crit < 0.0 || sigma_cm2 < 0.0 || alpha_1 < 0.0 || !(alpha_a > alpha_1) || tol < 0.0)
+        return fail(ctx, START_EINVAL, "need theta, sigma, tol >= 0 and alpha_A > alpha_1 >= 0");
+    if (prec != START_FP64 && prec != START_FP32C) return fail(ctx, START_EINVAL, "unknown precision");
+    if (max_iter < 1) return fail(ctx, START_EINVAL, "max_iter must be >= 1");
+    if (grid_log2 < 1 || grid_log2 > 10) return fail(ctx, START_EINVAL, "grid_log2 must be in [1, 10]");
+    if (n_gas == 0) return START_OK;
+    hipSetDevice(ctx->c.device);
+    st = start_synchronize(ctx);
+    if (st) return st;
+    Ctx &c = ctx->c;
+    hipStream_t s = c.stream;
+    const int64_t n = n_gas, ns = n + n_star;
+    std::vector<std::pair<void *, size_t>> bufs;
+    auto alloc = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (dmalloc(&c, &p, bytes) != hipSuccess) return nullptr;
+        bufs.push_back({p, bytes});
+        return p;
+    };
+    GasBins bins;
+    Grid grid;
+    Tree tree;
+    bool have_bins = false, have_grid = false, have_tree = false;
+    auto free_tree = [&]() {
+        if (have_tree) dfree(&c, tree.keys, tree.bytes);
+        have_tree = false;
+    };
+    auto done = [&](start_status code) {
+        hipStreamSynchronize(s);
+        free_tree();
+        if (have_bins) free_bins(&c, &bins);
+        if (have_grid) dfree(&c, grid.val, grid.bytes);
+        for (auto &b : bufs) dfree(&c, b.first, b.second);
+        return code;
+    };
+    auto nomem = [&]() { return done(fail(ctx, c.budget ? START_EBUDGET : START_ENOMEM, "device allocation failed")); };
+    double *src = (double *)alloc((size_t)ns * 3 * sizeof(double));
+    double *lum = (double *)alloc((size_t)ns * sizeof(double));
+    int64_t *self = (int64_t *)alloc((size_t)n * sizeof(int64_t));
+    double *nhi = (double *)alloc((size_t)n * sizeof(double));
+    unsigned long long *word = (unsigned long long *)alloc(256);
+    if (!src || !lum || !self || !nhi || !word) return nomem();
+    // sources: the particles, then the stars (positions fixed)
+    for (int k = 0; k < 3; ++k) {
+        hipMemcpyAsync(src + (size_t)k * ns, gas_xyz + (size_t)k * n, (size_t)n * sizeof(double),
+                       hipMemcpyDeviceToDevice, s);
+        if (n_star > 0)
+            hipMemcpyAsync(src + (size_t)k * ns + n, star_xyz + (size_t)k * n_star, (size_t)n_star * sizeof(double),
+                           hipMemcpyDeviceToDevice, s);
+    }
+    if (n_star > 0)
+        hipMemcpyAsync(lum + n, star_lum, (size_t)n_star * sizeof(double), hipMemcpyDeviceToDevice, s);
+    launch_iota(&c, n, self);
+    launch_eq_prepare(&c, n, n_h, x_hi, nhi);
+    st = start_synchronize(ctx);
+    if (st) return done(st);
+    c.err.clear();
+    st = bin_gas(&c, *box, n, gas_xyz, gas_h, nhi, grid_log2, &bins);
+    if (st) return done(st == START_ENOMEM && c.budget ? START_EBUDGET : st);
+    have_bins = true;
+    if (alloc_grid(&c, *box, grid_log2, &grid)) return nomem();
+    have_grid = true;
+    start_grid gh;
+    start_tree th;
+    for (int it = 1; it <= max_iter; ++it) {
+        // emitters: alpha_1 n_e n_p V of the current x (eq. 19)
+        launch_recomb_terms(&c, n, n_h, x_hi, volume_cm3, sigma_cm2, alpha_1, lum, nullptr);
+        st = start_synchronize(ctx);
+        if (st) return done(st);
+        free_tree();
+        st = build_tree(&c, *box, ns, src, lum, &tree);
+        if (st) return done(st == START_ENOMEM && c.budget ? START_EBUDGET : st);
+        have_tree = true;
+        make_fp32_tree(&tree, s);
+        fill_grid(&c, bins, it == 1 ? nullptr : nhi, &grid);
+        gh.g = grid;
+        th.t = tree;
+        RateSpec r = spec_of(&th, &gh, n, gas_xyz, self, theta_crit, sigma_cm2, prec);
+        r.gamma = gamma_out;
+        st = enqueue(ctx, &r, 1, 0);
+        if (st) return done(st);
+        launch_clear_word(&c, word);
+        launch_eq_update_diffuse(&c, n, n_h, gamma_out, prec, volume_cm3, sigma_cm2, alpha_a, alpha_1, x_hi, nhi,
+                                 word);
+        unsigned long long bits = 0;
+        hipError_t e = hipMemcpyAsync(&bits, word, sizeof(bits), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return done(fail(ctx, START_EHIP, hipGetErrorString(e)));
+        st = start_synchronize(ctx);
+        if (st) return done(st);
+        double change;
+        std::memcpy(&change, &bits, sizeof(double));
+        if (iterations) *iterations = it;
+        if (last_change) *last_change = change;
+        if (change <= tol) break;
+    }
+    return done(START_OK);
+}
+
 start_status start_set_graph_replay(start_ctx *ctx, int enable)
 {
     if (!ctx) return START_EINVAL;

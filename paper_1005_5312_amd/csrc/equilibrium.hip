@@ -64,6 +64,47 @@ __global__ void __launch_bounds__(kThreads) eq_update(int64_t n, const double *_
     if (threadIdx.x == 0 && m > 0.0) atomicMax(max_change, (unsigned long long)__double_as_longlong(m));
 }
 
+// With the transfer of recombination photons (section 4.1) every
+// recombination counts (alpha_A) and a particle's own ground-state photons
+// reionise it at k_self (eq. 30); with k_self's optical depth (eq. 28) taken
+// from the previous x, k_ion = alpha_A n_e n_p is the balance above with
+// alpha_eff = alpha_A - alpha_1 (1 - exp(-tau_self)), which is alpha_B where
+// the gas is opaque.
+template <typename TG>
+__global__ void __launch_bounds__(kThreads) eq_update_diffuse(int64_t n, const double *__restrict__ n_h,
+                                                              const TG *__restrict__ gamma,
+                                                              const double *__restrict__ vol, double sigma,
+                                                              double alpha_a, double alpha_1, double *__restrict__ x,
+                                                              double *__restrict__ nhi,
+                                                              unsigned long long *max_change, unsigned *flags)
+{
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    double ch = 0.0;
+    if (k < n) {
+        const double nh = n_h[k], g = (double)gamma[k], xo = x[k], v = vol[k];
+        if (!isfinite(nh) || !isfinite(g) || !isfinite(xo) || !isfinite(v) || nh < 0.0 || g < 0.0 || v < 0.0) {
+            atomicOr(flags, kFlagEqInput);
+        } else {
+            const double tau = sigma * (xo * nh) * cbrt(3.0 * v / (4.0 * M_PI));
+            const double alpha = alpha_a - alpha_1 * -expm1(-tau);
+            const double a = alpha * nh;
+            const double den = 2.0 * a + g + sqrt(g * (g + 4.0 * a));
+            const double xn = den > 0.0 ? 2.0 * a / den : 1.0;
+            ch = fabs(xn - xo);
+            x[k] = xn;
+            nhi[k] = xn * nh;
+        }
+    }
+    const double m = block_max(ch);
+    if (threadIdx.x == 0 && m > 0.0) atomicMax(max_change, (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void __launch_bounds__(kThreads) iota64(int64_t n, int64_t *__restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k < n) out[k] = k;
+}
+
 // Checks n_H >= 0 and x in [0, 1], both finite, and writes n_HI = x n_H.
 __global__ void __launch_bounds__(kThreads) eq_prepare(int64_t n, const double *__restrict__ n_h,
                                                        const double *__restrict__ x, double *__restrict__ nhi,
@@ -133,6 +174,24 @@ __global__ void clear_u64(unsigned long long *w) { *w = 0ull; }
 }  // namespace
 
 void launch_clear_word(Ctx *c, unsigned long long *w) { clear_u64<<<1, 1, 0, c->stream>>>(w); }
+
+void launch_iota(Ctx *c, int64_t n, int64_t *out)
+{
+    if (n > 0) iota64<<<blocks_for(n), kThreads, 0, c->stream>>>(n, out);
+}
+
+void launch_eq_update_diffuse(Ctx *c, int64_t n, const double *n_h, const void *gamma, int gamma_prec,
+                              const double *vol, double sigma, double alpha_a, double alpha_1, double *x, double *nhi,
+                              unsigned long long *max_change)
+{
+    if (n <= 0) return;
+    if (gamma_prec == START_FP64)
+        eq_update_diffuse<double><<<blocks_for(n), kThreads, 0, c->stream>>>(
+            n, n_h, (const double *)gamma, vol, sigma, alpha_a, alpha_1, x, nhi, max_change, c->d_flags);
+    else
+        eq_update_diffuse<float><<<blocks_for(n), kThreads, 0, c->stream>>>(
+            n, n_h, (const float *)gamma, vol, sigma, alpha_a, alpha_1, x, nhi, max_change, c->d_flags);
+}
 
 void launch_recomb_terms(Ctx *c, int64_t n, const double *n_h, const double *x, const double *vol, double sigma,
                          double alpha_1, double *lum, double *kself)

@@ -174,6 +174,12 @@ void launch_eq_update(Ctx *c, int64_t n, const double *n_h, const void *gamma, i
                       double *x, double *nhi, unsigned long long *max_change);
 // *w = 0 by a one-thread kernel (graph-safe, unlike a memset node).
 void launch_clear_word(Ctx *c, unsigned long long *w);
+void launch_iota(Ctx *c, int64_t n, int64_t *out);
+// The equilibrium update with the transfer of recombination photons:
+// alpha_eff = alpha_A - alpha_1 (1 - exp(-tau_self(x_old))) per particle.
+void launch_eq_update_diffuse(Ctx *c, int64_t n, const double *n_h, const void *gamma, int gamma_prec,
+                              const double *vol, double sigma, double alpha_a, double alpha_1, double *x, double *nhi,
+                              unsigned long long *max_change);
 // nhi <- x n_H after checking n_H >= 0 and x in [0, 1].
 void launch_eq_prepare(Ctx *c, int64_t n, const double *n_h, const double *x, double *nhi);
 // Recombination emission alpha_1 n_e n_p V and k_self per particle (either

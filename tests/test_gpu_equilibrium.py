@@ -271,3 +271,72 @@ def test_graph_replay_equals_eager_loop(ctx, prec):
         # (the loop also stops early once no x changes at all)
         assert ia == ib and ia <= iters and ca == cb
         assert np.array_equal(xa, xb) and np.array_equal(ga, gb), iters
+
+
+# --- equilibrium with the transfer of recombination photons ---------------
+
+ALPHA_A = 4.18e-13
+
+
+def gpu_diffuse(ctx, e, prec, max_iter, tol, alpha_1=ALPHA_1, theta=1.0):
+    w = e.work
+    x, g, it, ch = ctx.diffuse_equilibrium(H.box_of(w), w.gas_xyz, w.gas_h, e.n_h, e.volume_cm3, w.src_xyz,
+                                           w.src_lum, e.x_init, w.grid_log2, theta, w.sigma, ALPHA_A, alpha_1, prec,
+                                           max_iter, tol)
+    return x.cpu().numpy(), g.cpu().numpy().astype(np.float64), it, ch
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_diffuse_loop_matches_oracle(ctx, prec):
+    e = H.W.make_stromgren(seed=6, n_gas=1 << 13, grid_log2=4)
+    w = e.work
+    x, g, it, ch = gpu_diffuse(ctx, e, prec, 6, 0.0)
+    ob = H.obox_of(w)
+    xo, go, ito, cho = E.diffuse_equilibrium(ob, w.gas_xyz, w.gas_h, e.n_h, e.volume_cm3, w.src_xyz, w.src_lum,
+                                             e.x_init, w.grid_log2, 1.0, w.sigma, ALPHA_A, ALPHA_1, max_iter=6,
+                                             tol=0.0)
+    assert it == ito == 6
+    rel, ab, _ = H.rel_errors(g, go)
+    dx = float(np.max(np.abs(x - xo)))
+    print(f"  diffuse loop {prec}: gamma rel {rel:.2e}, max |dx| {dx:.2e}")
+    tol = H.TOL_FP64 if prec == "fp64" else H.TOL_FP32C
+    assert rel <= tol and ab <= H.ABS_FLOOR and dx <= tol
+
+
+def test_diffuse_loop_without_ground_state_photons_equals_plain_loop(ctx):
+    e = H.W.make_stromgren(seed=6, n_gas=1 << 13, grid_log2=4)
+    w = e.work
+    x, g, it, ch = gpu_diffuse(ctx, e, "fp64", 8, 0.0, alpha_1=0.0)
+    tree = ctx.build_source_tree(H.box_of(w), torch.from_numpy(w.src_xyz).to(ctx.device),
+                                 torch.from_numpy(w.src_lum).to(ctx.device))
+    xo, go, ito, cho = ctx.ionization_equilibrium(tree, w.gas_xyz, w.gas_h, e.n_h, e.x_init, w.grid_log2, 1.0,
+                                                  w.sigma, ALPHA_A, "fp64", 8, 0.0)
+    # (the star's virtual-source centre may round differently inside a
+    # tree of zero-luminosity particles: equal to rounding, not bit for bit)
+    assert it == ito
+    assert np.allclose(x, xo.cpu().numpy(), rtol=1e-12, atol=0)
+    assert np.allclose(g, go.cpu().numpy(), rtol=1e-12, atol=0)
+
+
+def test_diffuse_photons_extend_the_hii_region(ctx):
+    """Test 4 (section 4.2.1): with the transfer of recombination photons the
+    ionised region is more extended than on the spot, and near the source
+    the gas is more neutral (all recombinations count there, alpha_A >
+    alpha_B, while the photons escape); 2^15 particles, G = 32."""
+    e = H.W.make_stromgren(seed=5, n_gas=1 << 15, grid_log2=5)
+    w = e.work
+    xd, gd, itd, chd = gpu_diffuse(ctx, e, "fp32c", 400, 1e-3)
+    tree = ctx.build_source_tree(H.box_of(w), torch.from_numpy(w.src_xyz).to(ctx.device),
+                                 torch.from_numpy(w.src_lum).to(ctx.device))
+    xo, go, ito, cho = ctx.ionization_equilibrium(tree, w.gas_xyz, w.gas_h, e.n_h, e.x_init, w.grid_log2, 1.0,
+                                                  w.sigma, H.W.ALPHA_B, "fp32c", 400, 1e-3)
+    xo = xo.cpu().numpy()
+    rd = E.ionised_volume_radius(xd, e.volume_cm3) / H.KPC
+    ro = E.ionised_volume_radius(xo, e.volume_cm3) / H.KPC
+    r = np.sqrt(((w.gas_xyz - 0.5 * w.box_size) ** 2).sum(axis=0))
+    inner = r < 3.0
+    print(f"  R_eq on the spot {ro:.3f} kpc ({ito} it), with diffuse photons {rd:.3f} kpc ({itd} it); "
+          f"inner x {xo[inner].mean():.2e} vs {xd[inner].mean():.2e}")
+    assert chd <= 1e-3 and cho <= 1e-3
+    assert rd > ro * 1.02
+    assert xd[inner].mean() > xo[inner].mean()

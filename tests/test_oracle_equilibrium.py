@@ -189,3 +189,33 @@ def test_opaque_medium_total_rate_is_alpha_1_ne_np():
     r = kt / (alpha_1 * 0.25) - 1.0
     assert np.all(r >= -1e-15) and np.all(r <= 0.01)
     assert np.mean(np.abs(r) <= 1e-12) >= 0.99
+
+
+# --- equilibrium with the transfer of recombination photons ---------------
+
+def test_effective_recombination_limits():
+    """alpha_eff = alpha_A - alpha_1 (1 - e^-tau): alpha_B where the particle
+    is opaque to its own photons, alpha_A where it is transparent."""
+    aA, a1 = 4.18e-13, 1.58e-13
+    vol = 1e60
+    assert E.effective_recombination(10.0, 0.5, vol, 6.3e-18, aA, a1) == aA - a1
+    assert E.effective_recombination(1e-3, 0.0, vol, 6.3e-18, aA, a1) == aA
+    t = float(E.self_optical_depth(1e-3, 0.5, vol, 6.3e-18))
+    want = aA - a1 * (1 - math.exp(-t))
+    assert abs(float(E.effective_recombination(1e-3, 0.5, vol, 6.3e-18, aA, a1)) - want) <= 1e-15 * want
+
+
+def test_diffuse_loop_without_ground_state_photons_is_the_plain_loop():
+    """alpha_1 = 0: no particle emits and alpha_eff = alpha_A, so the loop is
+    the on-the-spot loop with alpha = alpha_A (the particles sit in the tree
+    with zero luminosity and are left out of the lists): identical x."""
+    e = W.make_stromgren(n_gas=1 << 12, grid_log2=4)
+    w = e.work
+    box = O.make_box(w.box_lo, w.box_size, w.length_unit_cm)
+    xd, gd, itd, chd = E.diffuse_equilibrium(box, w.gas_xyz, w.gas_h, e.n_h, e.volume_cm3, w.src_xyz, w.src_lum,
+                                             e.x_init, 4, 1.0, w.sigma, 4.18e-13, 0.0, max_iter=8, tol=0.0)
+    tree = O.Tree(box, w.src_xyz, w.src_lum)
+    xo, go, ito, cho = E.ionization_equilibrium(box, tree, w.gas_xyz, w.gas_h, e.n_h, e.x_init, 4, 1.0, w.sigma,
+                                                4.18e-13, max_iter=8, tol=0.0)
+    assert itd == ito == 8
+    assert np.array_equal(xd, xo) and np.array_equal(gd, go)
