@@ -974,10 +974,12 @@ size_t start_estimate_bytes(int64_t n_t, int64_t n_s, int64_t n_gas, int grid_lo
     (void)prec;
     if (n_t < 0 || n_s < 0 || n_gas < 0 || grid_log2 < 0 || grid_log2 > 10) return 0;
     const size_t G3 = (size_t)1 << (3 * grid_log2);
+    const int64_t G = (int64_t)1 << grid_log2, pad = (G >= 64 && G <= 512) ? 16 : 0;
+    const size_t span = (size_t)((G - 1) * (G * (G + pad) + pad) + (G - 1) * (G + pad) + G);   // padded grid
     // tree: persistent (keys, perm, sources, 2 n_s nodes) + build temporaries
     const size_t tree = (size_t)n_s * (8 + 4 + 32 + 16) + (size_t)2 * n_s * (16 + 16 + 32 + 16) +
                         radix_temp_bytes(2 * n_s) + (size_t)n_s * 48 + (size_t)2 * n_s * 44 + 65536;
-    const size_t grid = G3 * 12 + (size_t)n_gas * 56 + radix_temp_bytes(n_gas) + G3 * 4 + 65536;
+    const size_t grid = span * 12 + (size_t)n_gas * 56 + radix_temp_bytes(n_gas) + G3 * 4 + 65536;
     const size_t rates = (batch_scratch_bytes(n_t, 1, n_t) * 5) / 4 + 65536;   // up to one tile per target
     return tree + grid + rates;
 }
@@ -1076,7 +1078,13 @@ start_status start_grid_export(start_ctx *ctx, const start_grid *grid, double *v
     hipSetDevice(ctx->c.device);
     hipStreamSynchronize(ctx->c.stream);
     const size_t n = (size_t)grid->g.G * grid->g.G * grid->g.G;
-    hipError_t e = hipMemcpy(values, grid->g.val, n * sizeof(double), hipMemcpyDefault);
+    double *lin = nullptr;
+    if (dmalloc(&ctx->c, (void **)&lin, n * sizeof(double)) != hipSuccess)
+        return fail(ctx, START_ENOMEM, "device allocation failed");
+    launch_grid_unpad(&ctx->c, grid->g, lin);
+    hipError_t e = hipStreamSynchronize(ctx->c.stream);
+    if (e == hipSuccess) e = hipMemcpy(values, lin, n * sizeof(double), hipMemcpyDefault);
+    dfree(&ctx->c, lin, n * sizeof(double));
     return e == hipSuccess ? START_OK : fail(ctx, START_EHIP, hipGetErrorString(e));
 }
 

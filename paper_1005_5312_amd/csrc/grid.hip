@@ -90,7 +90,7 @@ __device__ inline double kernel_w(double r, double h)
 __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double delta, int G, int R,
                                                            double reach, const unsigned *start,
                                                            const double4 *pos_h, const double *ns,
-                                                           double *val, float *valf)
+                                                           double *val, float *valf, int sx, int sy)
 {
     const int64_t lin = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int64_t ncell = (int64_t)G * G * G;
@@ -124,8 +124,17 @@ __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double
         }
     }
     const double v = den > 0.0 ? num / den : 0.0;
-    val[lin] = v;
-    valf[lin] = (float)v;
+    const int64_t e = (int64_t)ia * sx + (int64_t)ib * sy + ic;
+    val[e] = v;
+    valf[e] = (float)v;
+}
+
+__global__ void __launch_bounds__(kThreads) unpad(int G, int sx, int sy, const double *val, double *out)
+{
+    const int64_t lin = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (lin >= (int64_t)G * G * G) return;
+    const int ia = (int)(lin / ((int64_t)G * G)), ib = (int)((lin / G) % G), ic = (int)(lin % G);
+    out[lin] = val[(int64_t)ia * sx + (int64_t)ib * sy + ic];
 }
 
 }  // namespace
@@ -204,13 +213,13 @@ void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g)
     hipStream_t s = c->stream;
     const int64_t ncell = (int64_t)g->G * g->G * g->G;
     if (b.n == 0) {
-        hipMemsetAsync(g->val, 0, ncell * sizeof(double), s);
-        hipMemsetAsync(g->valf, 0, ncell * sizeof(float), s);
+        hipMemsetAsync(g->val, 0, g->span * sizeof(double), s);
+        hipMemsetAsync(g->valf, 0, g->span * sizeof(float), s);
         return;
     }
     if (nhi) gather_values<<<blocks_for(b.n), kThreads, 0, s>>>(b.n, b.idx, nhi, b.ns);
     shepard_gather<<<blocks_for(ncell), kThreads, 0, s>>>(b.box, b.delta, b.G, b.R, b.reach, b.start, b.pos_h,
-                                                           b.ns, g->val, g->valf);
+                                                           b.ns, g->val, g->valf, g->sx, g->sy);
 }
 
 start_status alloc_grid(Ctx *c, const start_box &box, int grid_log2, Grid *g)
@@ -220,13 +229,17 @@ start_status alloc_grid(Ctx *c, const start_box &box, int grid_log2, Grid *g)
     g->grid_log2 = grid_log2;
     const int G = 1 << grid_log2;
     g->G = G;
-    const int64_t ncell = (int64_t)G * G * G;
-    size_t persist = al(ncell * sizeof(double)) + al(ncell * sizeof(float));
+    const int pad = (G >= 64 && G <= 512) ? 16 : 0;
+    g->sy = G + pad;
+    g->sx = G * g->sy + pad;
+    g->span = (int64_t)(G - 1) * g->sx + (int64_t)(G - 1) * g->sy + G;
+    size_t persist = al(g->span * sizeof(double)) + al(g->span * sizeof(float));
     char *pm = nullptr;
     if (dmalloc(c, (void **)&pm, persist) != hipSuccess) return START_ENOMEM;
     g->bytes = persist;
     g->val = (double *)pm;
-    g->valf = (float *)(pm + al(ncell * sizeof(double)));
+    g->valf = (float *)(pm + al(g->span * sizeof(double)));
+    if (pad) hipMemsetAsync(pm, 0, persist, c->stream);   // the padding is never written again
     return START_OK;
 }
 
@@ -250,6 +263,12 @@ start_status build_grid(Ctx *c, const start_box &box, int64_t n, const double *x
         return START_EHIP;
     }
     return START_OK;
+}
+
+void launch_grid_unpad(Ctx *c, const Grid &g, double *out)
+{
+    const int64_t n = (int64_t)g.G * g.G * g.G;
+    unpad<<<blocks_for(n), kThreads, 0, c->stream>>>(g.G, g.sx, g.sy, g.val, out);
 }
 
 }  // namespace start

@@ -57,6 +57,7 @@ struct Item {
     const float *gridf;
     int G;
     int grid_log2;
+    int sx, sy;         // element strides of the grid copies (padded rows and planes)
     double frac_scale;  // 2^-(32 - grid_log2)
     double gs;          // G / size
     double lo[3];
@@ -208,14 +209,14 @@ __device__ inline double load_cell(const double *grid, unsigned idx)
 }
 
 template <typename TV, bool STATS>
-__device__ inline TV march(const TV *__restrict__ grid, int G, unsigned ncell_m1, unsigned idx0, const double fb[3],
-                           const double D[3], int &ncell)
+__device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned last, unsigned idx0,
+                           const double fb[3], const double D[3], int &ncell)
 {
     // Axis k crosses its next plane at tn_k and every 1/|D_k| after it.  In
     // FP64 stepping tn_k by a_k drifts by ~1 ulp per step: over the <= 3G
     // steps of a ray that is ~1e-11 cell, far inside every tolerance.
     constexpr unsigned kScale = sizeof(TV) == 4 ? 4u : 1u;   // offset units per cell
-    const int stride[3] = {G * G, G, 1};
+    const int stride[3] = {sx, sy, 1};
     double a[3], tn[3];
     int ds[3];
 #pragma unroll
@@ -239,7 +240,7 @@ __device__ inline TV march(const TV *__restrict__ grid, int G, unsigned ncell_m1
         ds[k] *= (int)kScale;
     }
     unsigned off = idx0 * kScale;
-    const unsigned off_max = ncell_m1 * kScale;
+    const unsigned off_max = last * kScale;
     double t = 0.0;
     TV sum = TV(0), comp = TV(0);
     auto add = [&](TV v, TV len) {
@@ -428,7 +429,7 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
 
     const int G = P.G;
     const int gl = P.grid_log2;
-    const int ncell_m1 = G * G * G - 1;
+    const int last = (G - 1) * (P.sx + P.sy + 1);   // element of the last cell
     double u[3] = {0.0, 0.0, 0.0};
     unsigned orig = 0;
     int self = -1;   // source indices fit in 31 bits (n_s <= 2^30)
@@ -494,8 +495,9 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
         }
         const double d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
         if (d2 > 0.0) {
-            const T col = march<T, STATS>(PREC == START_FP64 ? (const T *)P.grid : (const T *)P.gridf, G,
-                                          (unsigned)ncell_m1, tcell, fb, D, nc);
+            const unsigned e0 = (unsigned)(tb[0] * P.sx + tb[1] * P.sy + tb[2]);
+            const T col = march<T, STATS>(PREC == START_FP64 ? (const T *)P.grid : (const T *)P.gridf, P.sx, P.sy,
+                                          (unsigned)last, e0, fb, D, nc);
             const T dist = (T)sqrt(d2);                        // grid units
             const T c = col_scale * (col * dist);
             if (P.channel == 0)
@@ -863,9 +865,12 @@ void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *s
             I.gridf = g->valf;
             I.G = g->G;
             I.grid_log2 = g->grid_log2;
+            I.sx = g->sx;
+            I.sy = g->sy;
         } else {
             I.G = 1;
             I.grid_log2 = 0;
+            I.sx = I.sy = 1;
         }
         I.frac_scale = ldexp(1.0, -(32 - I.grid_log2));
         I.gs = (double)I.G / t->box.size;
@@ -954,8 +959,9 @@ __global__ void __launch_bounds__(256) upstream_roots(int64_t n_roots, const uns
                                                       const unsigned *__restrict__ owner, const double *__restrict__ xyz,
                                                       int64_t n, const double4 *__restrict__ mom,
                                                       const double4 *__restrict__ src, const int *__restrict__ first,
-                                                      const double *__restrict__ grid, int G, double lo0, double lo1,
-                                                      double lo2, double gs, double tau_scale, double *__restrict__ acc)
+                                                      const double *__restrict__ grid, int G, int sx, int sy, double lo0,
+                                                      double lo1, double lo2, double gs, double tau_scale,
+                                                      double *__restrict__ acc)
 {
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (r >= n_roots) return;
@@ -982,8 +988,8 @@ __global__ void __launch_bounds__(256) upstream_roots(int64_t n_roots, const uns
         return;
     }
     int nc = 0;
-    const unsigned tcell = (unsigned)((tb[0] * G + tb[1]) * G + tb[2]);
-    const double col = march<double, false>(grid, G, (unsigned)(G * G * G - 1), tcell, fb, D, nc);
+    const unsigned e0 = (unsigned)(tb[0] * sx + tb[1] * sy + tb[2]);
+    const double col = march<double, false>(grid, sx, sy, (unsigned)((G - 1) * (sx + sy + 1)), e0, fb, D, nc);
     acc[p] = tau_scale * (col * sqrt(d2));
 }
 
@@ -997,8 +1003,8 @@ void launch_upstream_roots(Ctx *c, const Tree *t, const Grid *g, int64_t n_roots
     const double gs = (double)g->G / t->box.size;
     const double tau_scale = sigma * (t->box.size / g->G * t->box.length_unit_cm);
     upstream_roots<<<(unsigned)((n_roots + 255) / 256), 256, 0, c->stream>>>(
-        n_roots, roots, keys, owner, xyz, n, t->mom, t->src, t->first, g->val, g->G, t->box.lo[0], t->box.lo[1],
-        t->box.lo[2], gs, tau_scale, acc);
+        n_roots, roots, keys, owner, xyz, n, t->mom, t->src, t->first, g->val, g->G, g->sx, g->sy, t->box.lo[0],
+        t->box.lo[1], t->box.lo[2], gs, tau_scale, acc);
 }
 
 }  // namespace start
