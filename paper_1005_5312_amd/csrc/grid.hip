@@ -56,12 +56,15 @@ __global__ void __launch_bounds__(kThreads) cell_counts(const uint64_t *keys, in
 
 __global__ void __launch_bounds__(kThreads) gather_particles(int64_t n, const unsigned *perm, const double *xyz,
                                                              const double *h, const double *nhi, double4 *pos_h,
-                                                             double *ns)
+                                                             double2 *kern, double *ns)
 {
     const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (k >= n) return;
     const unsigned o = perm[k];
-    pos_h[k] = make_double4(xyz[o], xyz[n + o], xyz[2 * n + o], h[o]);
+    const double hk = h[o];
+    pos_h[k] = make_double4(xyz[o], xyz[n + o], xyz[2 * n + o], hk);
+    // 1/h and the 3-D normalisation 1/(pi h^3) of the kernel, once per particle
+    kern[k] = make_double2(1.0 / hk, 1.0 / (M_PI * hk * hk * hk));
     ns[k] = nhi[o];
 }
 
@@ -73,10 +76,10 @@ __global__ void __launch_bounds__(kThreads) gather_values(int64_t n, const unsig
     ns[k] = nhi[perm[k]];
 }
 
-// M4 cubic spline of section 2.1 with 3-D normalisation 1/(pi h^3).
-__device__ inline double kernel_w(double r, double h)
+// M4 cubic spline of section 2.1 with 3-D normalisation 1/(pi h^3), from
+// q = r / h and the normalisation.
+__device__ inline double kernel_w(double q, double norm)
 {
-    const double q = r / h;
     double f;
     if (q <= 1.0)
         f = 1.0 - 1.5 * q * q + 0.75 * q * q * q;
@@ -84,13 +87,15 @@ __device__ inline double kernel_w(double r, double h)
         f = 0.25 * (2.0 - q) * (2.0 - q) * (2.0 - q);
     else
         f = 0.0;
-    return f / (M_PI * h * h * h);
+    return f * norm;
 }
 
 __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double delta, int G, int R,
                                                            double reach, const unsigned *start,
-                                                           const double4 *pos_h, const double *ns,
-                                                           double *val, float *valf, int sx, int sy)
+                                                           const double4 *__restrict__ pos_h,
+                                                           const double2 *__restrict__ kern,
+                                                           const double *__restrict__ ns, double *val, float *valf,
+                                                           int sx, int sy)
 {
     const int64_t lin = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int64_t ncell = (int64_t)G * G * G;
@@ -103,20 +108,26 @@ __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double
     const int a0 = ia - R < 0 ? 0 : ia - R, a1 = ia + R >= G ? G - 1 : ia + R;
     const int b0 = ib - R < 0 ? 0 : ib - R, b1 = ib + R >= G ? G - 1 : ib + R;
     const int c0 = ic - R < 0 ? 0 : ic - R, c1 = ic + R >= G ? G - 1 : ic + R;
+    const double reach2 = reach * reach;
     for (int a = a0; a <= a1; ++a) {
         const int da = a < ia ? ia - a - 1 : (a > ia ? a - ia - 1 : 0);
         for (int b = b0; b <= b1; ++b) {
             const int db = b < ib ? ib - b - 1 : (b > ib ? b - ib - 1 : 0);
-            // skip rows of cells entirely beyond the largest kernel reach
-            if ((double)(da * da + db * db) * delta * delta > reach * reach) continue;
+            // skip rows of cells entirely beyond the largest kernel reach,
+            // and trim the row to the cells the reach can touch
+            const double dab2 = (double)(da * da + db * db) * delta * delta;
+            if (dab2 > reach2) continue;
+            const int rz = (int)(sqrt(reach2 - dab2) / delta) + 1;
+            const int z0 = ic - rz > c0 ? ic - rz : c0, z1 = ic + rz < c1 ? ic + rz : c1;
             const int64_t row = ((int64_t)a * G + b) * G;
-            const unsigned s0 = start[row + c0], s1 = start[row + c1 + 1];
+            const unsigned s0 = start[row + z0], s1 = start[row + z1 + 1];
             for (unsigned s = s0; s < s1; ++s) {
                 const double4 p = pos_h[s];
                 const double dx = xc - p.x, dy = yc - p.y, dz = zc - p.z;
-                const double r = sqrt(dx * dx + dy * dy + dz * dz);
-                if (r < 2.0 * p.w) {
-                    const double w = kernel_w(r, p.w);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < 4.0 * p.w * p.w) {   // inside the support 2h
+                    const double2 k = kern[s];
+                    const double w = kernel_w(sqrt(r2) * k.x, k.y);
                     num += ns[s] * w;
                     den += w;
                 }
@@ -155,7 +166,7 @@ start_status bin_gas(Ctx *c, const start_box &box, int64_t n, const double *xyz,
     const int64_t nk = n;
     b->bytes = al(radix_temp_bytes(nk)) + al(nk * sizeof(uint64_t)) + al(nk * sizeof(unsigned)) +
                al((ncell + 1) * sizeof(unsigned)) + al(scan_temp_bytes(ncell + 1)) + al(nk * sizeof(double4)) +
-               al(nk * sizeof(double)) + 256;
+               al(nk * sizeof(double2)) + al(nk * sizeof(double)) + 256;
     if (dmalloc(c, (void **)&b->mem, b->bytes) != hipSuccess) {
         b->mem = nullptr;
         return START_ENOMEM;
@@ -168,6 +179,7 @@ start_status bin_gas(Ctx *c, const start_box &box, int64_t n, const double *xyz,
     b->start = (unsigned *)take((ncell + 1) * sizeof(unsigned));
     void *scan_tmp = take(scan_temp_bytes(ncell + 1));
     b->pos_h = (double4 *)take(nk * sizeof(double4));
+    b->kern = (double2 *)take(nk * sizeof(double2));
     b->ns = (double *)take(nk * sizeof(double));
     unsigned long long *hmax = (unsigned long long *)take(256);
 
@@ -180,7 +192,7 @@ start_status bin_gas(Ctx *c, const start_box &box, int64_t n, const double *xyz,
     hipMemsetAsync(b->start, 0, (ncell + 1) * sizeof(unsigned), s);
     cell_counts<<<blocks_for(n), kThreads, 0, s>>>(keys, n, b->start);
     exclusive_scan_u32(b->start, ncell + 1, scan_tmp, s);
-    gather_particles<<<blocks_for(n), kThreads, 0, s>>>(n, b->idx, xyz, h, nhi, b->pos_h, b->ns);
+    gather_particles<<<blocks_for(n), kThreads, 0, s>>>(n, b->idx, xyz, h, nhi, b->pos_h, b->kern, b->ns);
     unsigned flags = 0;
     unsigned long long hbits = 0;
     hipMemcpyAsync(&flags, bflags, sizeof(unsigned), hipMemcpyDeviceToHost, s);
@@ -219,7 +231,7 @@ void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g)
     }
     if (nhi) gather_values<<<blocks_for(b.n), kThreads, 0, s>>>(b.n, b.idx, nhi, b.ns);
     shepard_gather<<<blocks_for(ncell), kThreads, 0, s>>>(b.box, b.delta, b.G, b.R, b.reach, b.start, b.pos_h,
-                                                           b.ns, g->val, g->valf, g->sx, g->sy);
+                                                           b.kern, b.ns, g->val, g->valf, g->sx, g->sy);
 }
 
 start_status alloc_grid(Ctx *c, const start_box &box, int grid_log2, Grid *g)

@@ -104,6 +104,7 @@ struct GasBins {
     unsigned *idx = nullptr;   // binned order -> particle index
     unsigned *start = nullptr; // first binned particle of each cell [G^3 + 1]
     double4 *pos_h = nullptr;  // binned (x, y, z, h)
+    double2 *kern = nullptr;   // binned (1/h, 1/(pi h^3))
     double *ns = nullptr;      // binned n_HI
 };
 
