@@ -6,11 +6,15 @@
 // support 2h) in Shepard-normalised form,
 //     n_c = sum_k n_k W(|x_c - r_k|, h_k) / sum_k W(|x_c - r_k|, h_k),
 // 0 where no kernel reaches, and every ray then integrates the piecewise-
-// constant field exactly.  Particles are counting-sorted into the grid cells
-// (stable, so sums run in a fixed order) and each cell centre gathers from
-// the cells within the largest kernel radius.
+// constant field exactly.  Particles are split into a few classes by their
+// support 2h (chosen from a histogram of 2h to minimise the scan work) and
+// counting-sorted by (class, cell), stable, so sums run in a fixed order;
+// each cell centre gathers, class by class, from the cells within that
+// class's largest support.
 #include "internal.h"
 
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 
 namespace start {
@@ -21,30 +25,73 @@ constexpr int kThreads = 256;
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
+constexpr int kBins = 256;   // reach bins of a quarter cell; the last also holds every larger reach
+
+// Quarter-cell bin of a particle's kernel support 2h: ceil(4 * 2h / delta).
+__device__ inline int reach_bin(double h, double gs)
+{
+    const double u = ceil(8.0 * h * gs);
+    return u < (double)(kBins - 1) ? (int)u : kBins - 1;
+}
+
 __global__ void __launch_bounds__(kThreads) grid_keys(start_box box, double gs, int G, int64_t n,
                                                       const double *xyz, const double *h, const double *nhi,
                                                       uint64_t *keys, unsigned *idx, unsigned *flags,
-                                                      unsigned long long *hmax_bits)
+                                                      unsigned *hist, unsigned long long *hmax_bits)
+{
+    __shared__ unsigned lh[kBins];
+    __shared__ double wmax[kThreads / 64];
+    for (int t = threadIdx.x; t < kBins; t += kThreads) lh[t] = 0;
+    __syncthreads();
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    double reach = 0.0;
+    if (k < n) {
+        unsigned bad = 0;
+        int c[3];
+        for (int a = 0; a < 3; ++a) {
+            const double x = xyz[(int64_t)a * n + k];
+            if (!isfinite(x)) bad |= kFlagNonFinite;
+            else if (x < box.lo[a] || x > box.lo[a] + box.size) bad |= kFlagOutOfBox;
+            double g = isfinite(x) ? (x - box.lo[a]) * gs : 0.0;
+            int v = (int)floor(g);
+            c[a] = v < 0 ? 0 : (v >= G ? G - 1 : v);
+        }
+        const double hk = h[k], nk = nhi[k];
+        if (!isfinite(hk) || !isfinite(nk)) bad |= kFlagNonFinite;
+        else if (!(hk > 0.0) || nk < 0.0) bad |= kFlagNegative;
+        if (bad) {
+            atomicOr(flags, bad);
+        } else {
+            reach = 2.0 * hk;
+            atomicAdd(&lh[reach_bin(hk, gs)], 1u);
+        }
+        keys[k] = ((uint64_t)c[0] * G + c[1]) * G + c[2];
+        idx[k] = (unsigned)k;
+    }
+    // largest reach of the block, one atomic per block (positive doubles
+    // order like their bit patterns)
+    for (int o = 32; o > 0; o >>= 1) reach = fmax(reach, __shfl_xor(reach, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = reach;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wmax[0];
+        for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, wmax[w]);
+        if (m > 0.0) atomicMax(hmax_bits, (unsigned long long)__double_as_longlong(m));
+    }
+    for (int t = threadIdx.x; t < kBins; t += kThreads)
+        if (lh[t]) atomicAdd(&hist[t], lh[t]);
+}
+
+// Class-major keys: class * G^3 + cell; top.{x,y,z} are the last bins of
+// classes 0..2 (kBins where the class is unused).
+__global__ void __launch_bounds__(kThreads) class_keys(int64_t n, const double *h, double gs, int64_t ncell,
+                                                       int4 top, uint64_t *keys)
 {
     const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (k >= n) return;
-    unsigned bad = 0;
-    int c[3];
-    for (int a = 0; a < 3; ++a) {
-        const double x = xyz[(int64_t)a * n + k];
-        if (!isfinite(x)) bad |= kFlagNonFinite;
-        else if (x < box.lo[a] || x > box.lo[a] + box.size) bad |= kFlagOutOfBox;
-        double g = isfinite(x) ? (x - box.lo[a]) * gs : 0.0;
-        int v = (int)floor(g);
-        c[a] = v < 0 ? 0 : (v >= G ? G - 1 : v);
-    }
-    const double hk = h[k], nk = nhi[k];
-    if (!isfinite(hk) || !isfinite(nk)) bad |= kFlagNonFinite;
-    else if (!(hk > 0.0) || nk < 0.0) bad |= kFlagNegative;
-    if (bad) atomicOr(flags, bad);
-    else atomicMax(hmax_bits, (unsigned long long)__double_as_longlong(2.0 * hk));
-    keys[k] = ((uint64_t)c[0] * G + c[1]) * G + c[2];
-    idx[k] = (unsigned)k;
+    const int bin = reach_bin(h[k], gs);
+    const int cls = (bin > top.x) + (bin > top.y) + (bin > top.z);
+    keys[k] += (uint64_t)cls * (uint64_t)ncell;
 }
 
 __global__ void __launch_bounds__(kThreads) cell_counts(const uint64_t *keys, int64_t n, unsigned *start)
@@ -90,8 +137,14 @@ __device__ inline double kernel_w(double q, double norm)
     return f * norm;
 }
 
-__global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double delta, int G, int R,
-                                                           double reach, const unsigned *start,
+// One cell centre per thread.  Per reach class, the rows of cells within the
+// class reach are scanned: a particle in cell (a, b, c) is at least
+// (|a - ia| - 1/2)_+ cells from the centre along x (likewise y, z), so the
+// stencil is the set of cells whose nearest point to the centre lies within
+// the reach; the row geometry runs in float on a widened reach, so the
+// stencil can only grow.  The kernel support test itself is exact (FP64).
+__global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double delta, int G, ReachClasses cls,
+                                                           const unsigned *__restrict__ start,
                                                            const double4 *__restrict__ pos_h,
                                                            const double2 *__restrict__ kern,
                                                            const double *__restrict__ ns, double *val, float *valf,
@@ -105,31 +158,34 @@ __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double
     const double yc = box.lo[1] + ((double)ib + 0.5) * delta;
     const double zc = box.lo[2] + ((double)ic + 0.5) * delta;
     double num = 0.0, den = 0.0;
-    const int a0 = ia - R < 0 ? 0 : ia - R, a1 = ia + R >= G ? G - 1 : ia + R;
-    const int b0 = ib - R < 0 ? 0 : ib - R, b1 = ib + R >= G ? G - 1 : ib + R;
-    const int c0 = ic - R < 0 ? 0 : ic - R, c1 = ic + R >= G ? G - 1 : ic + R;
-    const double reach2 = reach * reach;
-    for (int a = a0; a <= a1; ++a) {
-        const int da = a < ia ? ia - a - 1 : (a > ia ? a - ia - 1 : 0);
-        for (int b = b0; b <= b1; ++b) {
-            const int db = b < ib ? ib - b - 1 : (b > ib ? b - ib - 1 : 0);
-            // skip rows of cells entirely beyond the largest kernel reach,
-            // and trim the row to the cells the reach can touch
-            const double dab2 = (double)(da * da + db * db) * delta * delta;
-            if (dab2 > reach2) continue;
-            const int rz = (int)(sqrt(reach2 - dab2) / delta) + 1;
-            const int z0 = ic - rz > c0 ? ic - rz : c0, z1 = ic + rz < c1 ? ic + rz : c1;
-            const int64_t row = ((int64_t)a * G + b) * G;
-            const unsigned s0 = start[row + z0], s1 = start[row + z1 + 1];
-            for (unsigned s = s0; s < s1; ++s) {
-                const double4 p = pos_h[s];
-                const double dx = xc - p.x, dy = yc - p.y, dz = zc - p.z;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < 4.0 * p.w * p.w) {   // inside the support 2h
-                    const double2 k = kern[s];
-                    const double w = kernel_w(sqrt(r2) * k.x, k.y);
-                    num += ns[s] * w;
-                    den += w;
+    for (int k = 0; k < cls.K; ++k) {
+        const unsigned *st = start + k * ncell;
+        const float q2 = cls.q2[k];
+        const int R = cls.R[k];
+        const int a0 = ia - R < 0 ? 0 : ia - R, a1 = ia + R >= G ? G - 1 : ia + R;
+        for (int a = a0; a <= a1; ++a) {
+            const float fa = a == ia ? 0.0f : (float)(a < ia ? ia - a : a - ia) - 0.5f;
+            const float ra = q2 - fa * fa;
+            if (ra < 0.0f) continue;
+            const int rb = (int)(sqrtf(ra) + 0.5f);
+            const int b0 = ib - rb < 0 ? 0 : ib - rb, b1 = ib + rb >= G ? G - 1 : ib + rb;
+            for (int b = b0; b <= b1; ++b) {
+                const float fb = b == ib ? 0.0f : (float)(b < ib ? ib - b : b - ib) - 0.5f;
+                const float rem = ra - fb * fb;
+                const int rz = (int)(sqrtf(rem > 0.0f ? rem : 0.0f) + 0.5f);
+                const int z0 = ic - rz < 0 ? 0 : ic - rz, z1 = ic + rz >= G ? G - 1 : ic + rz;
+                const int64_t row = ((int64_t)a * G + b) * G;
+                const unsigned s0 = st[row + z0], s1 = st[row + z1 + 1];
+                for (unsigned s = s0; s < s1; ++s) {
+                    const double4 p = pos_h[s];
+                    const double dx = xc - p.x, dy = yc - p.y, dz = zc - p.z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 < 4.0 * p.w * p.w) {   // inside the support 2h
+                        const double2 kk = kern[s];
+                        const double w = kernel_w(sqrt(r2) * kk.x, kk.y);
+                        num += ns[s] * w;
+                        den += w;
+                    }
                 }
             }
         }
@@ -150,6 +206,71 @@ __global__ void __launch_bounds__(kThreads) unpad(int G, int sx, int sy, const d
 
 }  // namespace
 
+// Splits the non-empty reach bins into at most kmax classes of neighbouring
+// bins, minimising an estimate of the gather work per cell centre: for each
+// class, the particles it holds per cell times the cells its stencil scans
+// (a ball of radius reach + half a cell), plus a fixed cost per row of cells.
+// reach_cells is the largest reach in cells; it bounds the last class.
+static ReachClasses choose_classes(const unsigned *hist, int64_t n, int64_t ncell, double reach_cells, int kmax,
+                                   int4 *top)
+{
+    constexpr double kRowCost = 3.0;   // one row's set-up, in particle tests
+    std::vector<int> bin;
+    std::vector<double> pre(1, 0.0);
+    for (int u = 0; u < kBins; ++u)
+        if (hist[u]) {
+            bin.push_back(u);
+            pre.push_back(pre.back() + hist[u]);
+        }
+    const int m = (int)bin.size();
+    ReachClasses c;
+    *top = make_int4(kBins, kBins, kBins, 0);
+    if (m == 0) return c;   // no particle: one empty class
+    auto radius = [&](int j) {   // reach in cells of a class ending at bin j
+        return bin[j] == kBins - 1 ? reach_cells : std::min(0.25 * bin[j], reach_cells);
+    };
+    auto cost = [&](int i, int j) {
+        const double r = radius(j) + 0.5, rows = M_PI * r * r;
+        return (pre[j + 1] - pre[i]) / (double)ncell * (4.0 / 3.0 * M_PI * r * r * r + rows) + kRowCost * rows;
+    };
+    const double inf = 1e300;
+    // best[k][j]: k classes over the first j bins; from[k][j]: first bin of the last class
+    std::vector<std::vector<double>> best(kmax + 1, std::vector<double>(m + 1, inf));
+    std::vector<std::vector<int>> from(kmax + 1, std::vector<int>(m + 1, 0));
+    best[0][0] = 0.0;
+    for (int k = 1; k <= kmax; ++k)
+        for (int j = 1; j <= m; ++j)
+            for (int i = k - 1; i < j; ++i)
+                if (best[k - 1][i] < inf) {
+                    const double v = best[k - 1][i] + cost(i, j - 1);
+                    if (v < best[k][j]) {
+                        best[k][j] = v;
+                        from[k][j] = i;
+                    }
+                }
+    int K = 1;
+    for (int k = 2; k <= kmax && k <= m; ++k)
+        if (best[k][m] < best[K][m]) K = k;
+    int last[kMaxReachClasses];
+    for (int k = K, j = m; k > 0; --k) {
+        last[k - 1] = j - 1;
+        j = from[k][j];
+    }
+    c.K = K;
+    int t[3] = {kBins, kBins, kBins};
+    for (int k = 0; k < K; ++k) {
+        const double r = radius(last[k]);
+        // a margin far above the rounding of the binning and of the float
+        // stencil arithmetic; it only ever adds cells to the scan
+        c.q2[k] = (float)(r * r * (1.0 + 1e-4) + 1e-4);
+        c.R[k] = (int)floor(0.5 + sqrt((double)c.q2[k]));
+        if (k < 3 && k < K - 1) t[k] = bin[last[k]];
+    }
+    *top = make_int4(t[0], t[1], t[2], 0);
+    (void)n;
+    return c;
+}
+
 start_status bin_gas(Ctx *c, const start_box &box, int64_t n, const double *xyz, const double *h,
                      const double *nhi, int grid_log2, GasBins *b)
 {
@@ -165,8 +286,8 @@ start_status bin_gas(Ctx *c, const start_box &box, int64_t n, const double *xyz,
     if (n == 0) return START_OK;
     const int64_t nk = n;
     b->bytes = al(radix_temp_bytes(nk)) + al(nk * sizeof(uint64_t)) + al(nk * sizeof(unsigned)) +
-               al((ncell + 1) * sizeof(unsigned)) + al(scan_temp_bytes(ncell + 1)) + al(nk * sizeof(double4)) +
-               al(nk * sizeof(double2)) + al(nk * sizeof(double)) + 256;
+               al(nk * sizeof(double4)) + al(nk * sizeof(double2)) + al(nk * sizeof(double)) +
+               al(kBins * sizeof(unsigned)) + 256;
     if (dmalloc(c, (void **)&b->mem, b->bytes) != hipSuccess) {
         b->mem = nullptr;
         return START_ENOMEM;
@@ -176,26 +297,23 @@ start_status bin_gas(Ctx *c, const start_box &box, int64_t n, const double *xyz,
     void *radix_tmp = take(radix_temp_bytes(nk));
     uint64_t *keys = (uint64_t *)take(nk * sizeof(uint64_t));
     b->idx = (unsigned *)take(nk * sizeof(unsigned));
-    b->start = (unsigned *)take((ncell + 1) * sizeof(unsigned));
-    void *scan_tmp = take(scan_temp_bytes(ncell + 1));
     b->pos_h = (double4 *)take(nk * sizeof(double4));
     b->kern = (double2 *)take(nk * sizeof(double2));
     b->ns = (double *)take(nk * sizeof(double));
+    unsigned *hist = (unsigned *)take(kBins * sizeof(unsigned));
     unsigned long long *hmax = (unsigned long long *)take(256);
 
     const double gs = (double)G / box.size;
     unsigned *bflags = c->d_flags + 1;   // build validation word (not the rate calls' one)
     hipMemsetAsync(bflags, 0, sizeof(unsigned), s);
+    hipMemsetAsync(hist, 0, kBins * sizeof(unsigned), s);
     hipMemsetAsync(hmax, 0, sizeof(unsigned long long), s);
-    grid_keys<<<blocks_for(n), kThreads, 0, s>>>(box, gs, G, n, xyz, h, nhi, keys, b->idx, bflags, hmax);
-    radix_sort_pairs(keys, b->idx, n, 3 * grid_log2, radix_tmp, s);
-    hipMemsetAsync(b->start, 0, (ncell + 1) * sizeof(unsigned), s);
-    cell_counts<<<blocks_for(n), kThreads, 0, s>>>(keys, n, b->start);
-    exclusive_scan_u32(b->start, ncell + 1, scan_tmp, s);
-    gather_particles<<<blocks_for(n), kThreads, 0, s>>>(n, b->idx, xyz, h, nhi, b->pos_h, b->kern, b->ns);
+    grid_keys<<<blocks_for(n), kThreads, 0, s>>>(box, gs, G, n, xyz, h, nhi, keys, b->idx, bflags, hist, hmax);
     unsigned flags = 0;
     unsigned long long hbits = 0;
+    unsigned hh[kBins];
     hipMemcpyAsync(&flags, bflags, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(hh, hist, sizeof(hh), hipMemcpyDeviceToHost, s);
     hipMemcpyAsync(&hbits, hmax, sizeof(hbits), hipMemcpyDeviceToHost, s);
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess || flags) {
@@ -207,17 +325,35 @@ start_status bin_gas(Ctx *c, const start_box &box, int64_t n, const double *xyz,
         return START_EINVAL;
     }
     std::memcpy(&b->reach, &hbits, sizeof(double));
-    // a particle can reach a centre only from cells within ceil(reach/delta)
-    int R = (int)ceil(b->reach / b->delta);
-    b->R = R > G ? G : R;
+    int4 top;
+    b->cls = choose_classes(hh, n, ncell, b->reach / b->delta, grid_log2 >= 10 ? 2 : kMaxReachClasses, &top);
+    const int K = b->cls.K;
+    // per (class, cell) starts, allocated once the number of classes is known
+    const int64_t nstart = K * ncell + 1;
+    b->bytes2 = al(nstart * sizeof(unsigned)) + al(scan_temp_bytes(nstart));
+    if (dmalloc(c, (void **)&b->mem2, b->bytes2) != hipSuccess) {
+        b->mem2 = nullptr;
+        free_bins(c, b);
+        c->err = "allocation failed";
+        return START_ENOMEM;
+    }
+    b->start = (unsigned *)b->mem2;
+    void *scan_tmp = b->mem2 + al(nstart * sizeof(unsigned));
+    if (K > 1) class_keys<<<blocks_for(n), kThreads, 0, s>>>(n, h, gs, ncell, top, keys);
+    radix_sort_pairs(keys, b->idx, n, 3 * grid_log2 + (K > 2 ? 2 : K - 1), radix_tmp, s);
+    hipMemsetAsync(b->start, 0, nstart * sizeof(unsigned), s);
+    cell_counts<<<blocks_for(n), kThreads, 0, s>>>(keys, n, b->start);
+    exclusive_scan_u32(b->start, nstart, scan_tmp, s);
+    gather_particles<<<blocks_for(n), kThreads, 0, s>>>(n, b->idx, xyz, h, nhi, b->pos_h, b->kern, b->ns);
     return START_OK;
 }
 
 void free_bins(Ctx *c, GasBins *b)
 {
     dfree(c, b->mem, b->bytes);
-    b->mem = nullptr;
-    b->bytes = 0;
+    dfree(c, b->mem2, b->bytes2);
+    b->mem = b->mem2 = nullptr;
+    b->bytes = b->bytes2 = 0;
 }
 
 void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g)
@@ -230,8 +366,8 @@ void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g)
         return;
     }
     if (nhi) gather_values<<<blocks_for(b.n), kThreads, 0, s>>>(b.n, b.idx, nhi, b.ns);
-    shepard_gather<<<blocks_for(ncell), kThreads, 0, s>>>(b.box, b.delta, b.G, b.R, b.reach, b.start, b.pos_h,
-                                                           b.kern, b.ns, g->val, g->valf, g->sx, g->sy);
+    shepard_gather<<<blocks_for(ncell), kThreads, 0, s>>>(b.box, b.delta, b.G, b.cls, b.start, b.pos_h, b.kern,
+                                                           b.ns, g->val, g->valf, g->sx, g->sy);
 }
 
 start_status alloc_grid(Ctx *c, const start_box &box, int grid_log2, Grid *g)

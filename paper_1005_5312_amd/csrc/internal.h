@@ -92,17 +92,29 @@ struct Grid {
 
 // Gas particles counting-sorted into the cells of a G^3 grid, kept so that
 // the grid can be refilled for new n_HI values at the same positions.
+// The particles are split into at most kMaxReachClasses classes by their
+// kernel support 2h, so that each cell centre scans, per class, only the
+// cells that class can reach; the binned order is class-major, then cell.
+constexpr int kMaxReachClasses = 4;
+struct ReachClasses {
+    int K = 1;
+    int R[kMaxReachClasses] = {};      // loop half-width in cells
+    float q2[kMaxReachClasses] = {};   // (reach / delta)^2 with a small safety margin
+};
+
 struct GasBins {
     start_box box;
     int64_t n = 0;
     int G = 1;
-    int R = 0;                 // gather radius in cells
     double reach = 0.0;        // largest kernel support 2h
     double delta = 0.0;        // cell side
-    char *mem = nullptr;
+    ReachClasses cls;
+    char *mem = nullptr;       // particle arrays
     size_t bytes = 0;
+    char *mem2 = nullptr;      // starts
+    size_t bytes2 = 0;
     unsigned *idx = nullptr;   // binned order -> particle index
-    unsigned *start = nullptr; // first binned particle of each cell [G^3 + 1]
+    unsigned *start = nullptr; // first binned particle of each (class, cell) [K G^3 + 1]
     double4 *pos_h = nullptr;  // binned (x, y, z, h)
     double2 *kern = nullptr;   // binned (1/h, 1/(pi h^3))
     double *ns = nullptr;      // binned n_HI

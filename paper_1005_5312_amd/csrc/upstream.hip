@@ -27,7 +27,7 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / k
 template <bool FILL>
 __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const double *__restrict__ xyz,
                                                        const double *__restrict__ h, start_box box, double delta,
-                                                       int G, const unsigned *__restrict__ start,
+                                                       int G, int K, const unsigned *__restrict__ start,
                                                        const double4 *__restrict__ pos_h,
                                                        const unsigned *__restrict__ idx, unsigned *__restrict__ count,
                                                        const unsigned *__restrict__ nb_off, unsigned *__restrict__ nb)
@@ -47,9 +47,11 @@ __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const double *
     }
     unsigned c = 0;
     const unsigned base = FILL ? nb_off[i] : 0u;
+    const int64_t ncell = (int64_t)G * G * G;
+    for (int k = 0; k < K; ++k)   // every reach class of the binning
     for (int a = lo[0]; a <= hi[0]; ++a)
         for (int b = lo[1]; b <= hi[1]; ++b) {
-            const int64_t row = ((int64_t)a * G + b) * G;
+            const int64_t row = k * ncell + ((int64_t)a * G + b) * G;
             const unsigned s0 = start[row + lo[2]], s1 = start[row + hi[2] + 1];
             for (unsigned s = s0; s < s1; ++s) {
                 const unsigned j = idx[s];
@@ -212,10 +214,10 @@ void launch_neighbours(Ctx *c, const GasBins &b, int64_t n, const double *xyz, c
 {
     if (n <= 0) return;
     if (!nb_off)
-        neighbours<false><<<blocks_for(n), kThreads, 0, c->stream>>>(n, xyz, h, b.box, b.delta, b.G, b.start, b.pos_h,
+        neighbours<false><<<blocks_for(n), kThreads, 0, c->stream>>>(n, xyz, h, b.box, b.delta, b.G, b.cls.K, b.start, b.pos_h,
                                                                      b.idx, count, nullptr, nullptr);
     else
-        neighbours<true><<<blocks_for(n), kThreads, 0, c->stream>>>(n, xyz, h, b.box, b.delta, b.G, b.start, b.pos_h,
+        neighbours<true><<<blocks_for(n), kThreads, 0, c->stream>>>(n, xyz, h, b.box, b.delta, b.G, b.cls.K, b.start, b.pos_h,
                                                                     b.idx, nullptr, nb_off, nb);
 }
 

@@ -169,6 +169,37 @@ def test_grid_parity(ctx, name):
     assert np.max(np.abs(got[nz] / want[nz] - 1)) <= 1e-12
 
 
+@pytest.mark.parametrize("case", ["log_h", "bin_edges"])
+def test_grid_parity_wide_smoothing_lengths(ctx, case):
+    """Smoothing lengths spread over a factor ~20 (several reach classes of
+    the binning), and particles on cell faces with 2h on the quarter-cell
+    class edges: every cell still sees every particle whose support reaches
+    it (same zero pattern, rel 1e-12)."""
+    rng = np.random.default_rng(61)
+    G = 32
+    size = 6.6
+    delta = size / G
+    n = 700                 # sparse enough to leave cells uncovered
+    if case == "log_h":
+        xyz = rng.random((3, n)) * size
+        h = delta * np.exp(rng.uniform(np.log(0.15), np.log(3.0), n))
+    else:
+        # positions on cell faces and corners, 2h = k/4 cells exactly
+        xyz = rng.integers(0, G + 1, (3, n)) * delta
+        h = 0.5 * delta * rng.integers(1, 17, n) / 4.0
+    nhi = 10 ** rng.uniform(-5, -2, n)
+    print(f"[case] grid {case} G={G}", flush=True)
+    box = O.make_box([0.0, 0.0, 0.0], size, 3.0856775814913673e21)
+    from paper_1005_5312_amd import Box
+    grid = ctx.build_gas_grid(Box((0.0, 0.0, 0.0), size, 3.0856775814913673e21), dev(xyz), dev(h), dev(nhi), 5)
+    got = ctx.grid_export(grid)
+    want = O.grid(box, xyz, h, nhi, 5)
+    assert np.array_equal(got == 0, want == 0)
+    nz = want != 0
+    assert 0.5 < nz.mean() < 0.95
+    assert np.max(np.abs(got[nz] / want[nz] - 1)) <= 1e-12
+
+
 # --------------------------------------------------------------- rates ---
 
 @pytest.mark.parametrize("theta", [0.0, 0.5, 1.0])
