@@ -79,14 +79,19 @@ typedef struct start_grid start_grid;
 /* Context on `device`.  hip_stream: a hipStream_t to run on, or NULL for a
  * stream of its own.  hbm_budget_bytes: cap on the device memory the library
  * allocates through this context (0 = no cap); allocations beyond it fail
- * with START_EBUDGET. */
+ * with START_EBUDGET.  Device memory that the library releases (a freed tree
+ * or grid, the temporaries of a call) stays with the context, up to 8 GiB,
+ * and is reused for later requests of the same size; it goes back to the
+ * device when a new allocation needs the room (budget or device memory
+ * short) and at start_ctx_destroy. */
 start_status start_ctx_create(int device, void *hip_stream, size_t hbm_budget_bytes, start_ctx **out);
 void start_ctx_destroy(start_ctx *ctx);
 /* Message of the last failing call on ctx; valid until the next call. */
 const char *start_last_error(const start_ctx *ctx);
 /* Waits for the context stream and reports device-side input errors. */
 start_status start_synchronize(start_ctx *ctx);
-/* Device memory currently held by trees, grids and scratch of ctx. */
+/* Device memory currently held by trees, grids and scratch of ctx (the
+ * released blocks kept for reuse not included). */
 size_t start_bytes_in_use(const start_ctx *ctx);
 
 /* Octree over n_s sources (section 2.2.2, eqs. 14-15).  src_xyz [3][n_s],

@@ -13,13 +13,41 @@ start_status build_grid(Ctx *c, const start_box &box, int64_t n, const double *x
                         const double *nhi, int grid_log2, Grid *g);
 void make_fp32_tree(Tree *t, hipStream_t s);
 
+// Freed blocks stay with the context and are handed out again for a request
+// of the same size: the builds ask for the same sizes at every step, and a
+// hipMalloc / hipFree pair costs ~0.3 ms (hipFree waits for the device).  All
+// work of a context runs on its one stream, so a reused block is only touched
+// after the work that used it before.  The pool is returned to the device
+// when an allocation would fail without it, and when the context ends.
+void release_pool(Ctx *c)
+{
+    for (auto &b : c->pool) hipFree(b.first);
+    c->pool.clear();
+    c->pooled = 0;
+}
+
 hipError_t dmalloc(Ctx *c, void **p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
     if (c->budget && c->in_use + bytes > c->budget) return hipErrorOutOfMemory;
+    for (size_t i = c->pool.size(); i-- > 0;)
+        if (c->pool[i].second == bytes) {
+            *p = c->pool[i].first;
+            c->pool.erase(c->pool.begin() + (std::ptrdiff_t)i);
+            c->pooled -= bytes;
+            c->in_use += bytes;
+            return hipSuccess;
+        }
+    if (c->budget && c->in_use + c->pooled + bytes > c->budget) release_pool(c);
     hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess && !c->pool.empty()) {
+        (void)hipGetLastError();
+        release_pool(c);
+        e = hipMalloc(p, bytes);
+    }
     if (e == hipSuccess) c->in_use += bytes;
+    else *p = nullptr;
     return e;
 }
 
@@ -27,8 +55,15 @@ void dfree(Ctx *c, void *p, size_t bytes)
 {
     if (!p) return;
     if (bytes == 0) bytes = 256;
-    hipFree(p);
     c->in_use -= bytes < c->in_use ? bytes : c->in_use;
+    c->pool.emplace_back(p, bytes);
+    c->pooled += bytes;
+    // keep the pool bounded: the oldest blocks go back first
+    while (c->pooled > kPoolMaxBytes && !c->pool.empty()) {
+        hipFree(c->pool.front().first);
+        c->pooled -= c->pool.front().second;
+        c->pool.erase(c->pool.begin());
+    }
 }
 
 }  // namespace start
@@ -254,6 +289,7 @@ void start_ctx_destroy(start_ctx *ctx)
     hipSetDevice(ctx->c.device);
     hipStreamSynchronize(ctx->c.stream);
     dfree(&ctx->c, ctx->c.scratch, ctx->c.scratch_bytes);
+    release_pool(&ctx->c);
     for (hipEvent_t ev : ctx->c.ev_pool) hipEventDestroy(ev);
     if (ctx->c.stage_ev) hipEventDestroy(ctx->c.stage_ev);
     if (ctx->c.host_stage) hipHostFree(ctx->c.host_stage);

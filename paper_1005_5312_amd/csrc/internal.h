@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/start.h"
@@ -22,6 +23,8 @@ constexpr unsigned kFlagOutOfBox = 2u;
 constexpr unsigned kFlagNegative = 4u;
 constexpr unsigned kFlagBadSelf = 8u;
 constexpr unsigned kFlagEqInput = 16u;    // equilibrium: n_H, Gamma or x out of range
+
+constexpr size_t kPoolMaxBytes = (size_t)8 << 30;
 
 struct Ctx {
     int device = 0;
@@ -47,6 +50,10 @@ struct Ctx {
     // replay repeated kernel sequences (the equilibrium iterations) from a
     // captured HIP graph
     bool graphs = true;
+    // freed device blocks kept for reuse (dmalloc / dfree), at most
+    // kPoolMaxBytes in total
+    std::vector<std::pair<void *, size_t>> pool;
+    size_t pooled = 0;
     // walk-kernel timing (start_profile_enable)
     bool profile = false;
     std::vector<hipEvent_t> ev_pool;   // pairs (start, stop)
@@ -133,6 +140,7 @@ void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g);
 // ---- memory helpers (count against the context budget) ----
 hipError_t dmalloc(Ctx *c, void **p, size_t bytes);
 void dfree(Ctx *c, void *p, size_t bytes);
+void release_pool(Ctx *c);
 
 // ---- primitives (sort.hip) ----
 // Exclusive scan of n unsigned ints in place; returns total through *d_total
