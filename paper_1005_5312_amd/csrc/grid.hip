@@ -137,12 +137,16 @@ __device__ inline double kernel_w(double q, double norm)
     return f * norm;
 }
 
-// One cell centre per thread.  Per reach class, the rows of cells within the
-// class reach are scanned: a particle in cell (a, b, c) is at least
-// (|a - ia| - 1/2)_+ cells from the centre along x (likewise y, z), so the
-// stencil is the set of cells whose nearest point to the centre lies within
-// the reach; the row geometry runs in float on a widened reach, so the
-// stencil can only grow.  The kernel support test itself is exact (FP64).
+constexpr int kCellsZ = 4;   // cell centres per thread, consecutive along z
+
+// kCellsZ consecutive cell centres of one z row per thread: they share x and
+// y, so every particle is loaded once for all of them.  Per reach class, the
+// rows of cells within the class reach are scanned: a particle in cell
+// (a, b, c) is at least (|a - ia| - 1/2)_+ cells from a centre in cell ia
+// along x (likewise y, z), so the stencil is the set of cells whose nearest
+// point lies within the reach; the row geometry runs in float on a widened
+// reach, so the stencil can only grow.  The support test itself is exact
+// (FP64), and every centre sums its particles in (class, row, binned) order.
 __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double delta, int G, ReachClasses cls,
                                                            const unsigned *__restrict__ start,
                                                            const double4 *__restrict__ pos_h,
@@ -150,14 +154,21 @@ __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double
                                                            const double *__restrict__ ns, double *val, float *valf,
                                                            int sx, int sy)
 {
+    const int GZ = (G + kCellsZ - 1) / kCellsZ;   // thread groups per z row
     const int64_t lin = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int64_t ncell = (int64_t)G * G * G;
-    if (lin >= ncell) return;
-    const int ia = (int)(lin / ((int64_t)G * G)), ib = (int)((lin / G) % G), ic = (int)(lin % G);
+    if (lin >= (int64_t)G * G * GZ) return;
+    const int ia = (int)(lin / ((int64_t)G * GZ)), ib = (int)((lin / GZ) % G);
+    const int ic0 = (int)(lin % GZ) * kCellsZ;
+    const int nz = G - ic0 < kCellsZ ? G - ic0 : kCellsZ;
     const double xc = box.lo[0] + ((double)ia + 0.5) * delta;
     const double yc = box.lo[1] + ((double)ib + 0.5) * delta;
-    const double zc = box.lo[2] + ((double)ic + 0.5) * delta;
-    double num = 0.0, den = 0.0;
+    double zc[kCellsZ], num[kCellsZ], den[kCellsZ];
+    for (int j = 0; j < kCellsZ; ++j) {
+        zc[j] = box.lo[2] + ((double)(ic0 + j) + 0.5) * delta;
+        num[j] = 0.0;
+        den[j] = 0.0;
+    }
     for (int k = 0; k < cls.K; ++k) {
         const unsigned *st = start + k * ncell;
         const float q2 = cls.q2[k];
@@ -173,27 +184,42 @@ __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double
                 const float fb = b == ib ? 0.0f : (float)(b < ib ? ib - b : b - ib) - 0.5f;
                 const float rem = ra - fb * fb;
                 const int rz = (int)(sqrtf(rem > 0.0f ? rem : 0.0f) + 0.5f);
-                const int z0 = ic - rz < 0 ? 0 : ic - rz, z1 = ic + rz >= G ? G - 1 : ic + rz;
+                const int z0 = ic0 - rz < 0 ? 0 : ic0 - rz;
+                const int z1 = ic0 + nz - 1 + rz >= G ? G - 1 : ic0 + nz - 1 + rz;
                 const int64_t row = ((int64_t)a * G + b) * G;
                 const unsigned s0 = st[row + z0], s1 = st[row + z1 + 1];
                 for (unsigned s = s0; s < s1; ++s) {
                     const double4 p = pos_h[s];
-                    const double dx = xc - p.x, dy = yc - p.y, dz = zc - p.z;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 < 4.0 * p.w * p.w) {   // inside the support 2h
-                        const double2 kk = kern[s];
-                        const double w = kernel_w(sqrt(r2) * kk.x, kk.y);
-                        num += ns[s] * w;
-                        den += w;
+                    const double dx = xc - p.x, dy = yc - p.y;
+                    const double dxy2 = dx * dx + dy * dy, h2 = 4.0 * p.w * p.w;
+                    if (!(dxy2 < h2)) continue;
+                    double2 kk = make_double2(0.0, 0.0);
+                    double nk = 0.0;
+                    bool loaded = false;
+                    for (int j = 0; j < kCellsZ; ++j) {
+                        const double dz = zc[j] - p.z;
+                        const double r2 = dxy2 + dz * dz;
+                        if (j < nz && r2 < h2) {   // inside the support 2h
+                            if (!loaded) {
+                                kk = kern[s];
+                                nk = ns[s];
+                                loaded = true;
+                            }
+                            const double w = kernel_w(sqrt(r2) * kk.x, kk.y);
+                            num[j] += nk * w;
+                            den[j] += w;
+                        }
                     }
                 }
             }
         }
     }
-    const double v = den > 0.0 ? num / den : 0.0;
-    const int64_t e = (int64_t)ia * sx + (int64_t)ib * sy + ic;
-    val[e] = v;
-    valf[e] = (float)v;
+    for (int j = 0; j < nz; ++j) {
+        const double v = den[j] > 0.0 ? num[j] / den[j] : 0.0;
+        const int64_t e = (int64_t)ia * sx + (int64_t)ib * sy + ic0 + j;
+        val[e] = v;
+        valf[e] = (float)v;
+    }
 }
 
 __global__ void __launch_bounds__(kThreads) unpad(int G, int sx, int sy, const double *val, double *out)
@@ -359,15 +385,15 @@ void free_bins(Ctx *c, GasBins *b)
 void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g)
 {
     hipStream_t s = c->stream;
-    const int64_t ncell = (int64_t)g->G * g->G * g->G;
     if (b.n == 0) {
         hipMemsetAsync(g->val, 0, g->span * sizeof(double), s);
         hipMemsetAsync(g->valf, 0, g->span * sizeof(float), s);
         return;
     }
     if (nhi) gather_values<<<blocks_for(b.n), kThreads, 0, s>>>(b.n, b.idx, nhi, b.ns);
-    shepard_gather<<<blocks_for(ncell), kThreads, 0, s>>>(b.box, b.delta, b.G, b.cls, b.start, b.pos_h, b.kern,
-                                                           b.ns, g->val, g->valf, g->sx, g->sy);
+    const int64_t groups = (int64_t)g->G * g->G * ((g->G + kCellsZ - 1) / kCellsZ);
+    shepard_gather<<<blocks_for(groups), kThreads, 0, s>>>(b.box, b.delta, b.G, b.cls, b.start, b.pos_h, b.kern,
+                                                            b.ns, g->val, g->valf, g->sx, g->sy);
 }
 
 start_status alloc_grid(Ctx *c, const start_box &box, int grid_log2, Grid *g)

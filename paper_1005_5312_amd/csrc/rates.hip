@@ -17,9 +17,10 @@
 // their rays are nearly parallel and read the same grid lines.
 //
 // Precision: START_FP64 marches and accumulates in FP64.  START_FP32C keeps
-// the FP64 opening test (exact lists) and marches in FP32 from the target
-// towards the source, with crossings computed from the cell index rather
-// than accumulated, and Kahan-compensated sums for tau and Gamma.
+// the FP64 opening test (exact lists) and the FP64 ray geometry, reads the
+// FP32 copy of the grid (half the bytes), accumulates each column in FP64
+// (one FMA per cell, no dearer than a compensated FP32 sum) and sums the
+// terms of Gamma with Kahan compensation in FP32.
 #include "internal.h"
 
 #include <cstring>
@@ -137,18 +138,22 @@ __device__ inline int lanes_below(uint64_t m)
 // to ~6e-8 of the ray length (1e-5 cell over 128 cells), which times the
 // optical depth of a dense cell (~200 per cell for the 200x clumps) is above
 // the 2e-4 target.  The marching is from the target, so crossings next to it
-// come first and exactly.  TV is the type of the grid values and of the sum:
-// FP32 with Kahan compensation, or FP64.  Returns sum n_c dt.
+// come first and exactly.  TV is the type of the grid values (FP32 or
+// FP64); the sum is FP64 in both cases.  Returns sum n_c dt.
 //
 // The step is branch-free: the next crossing is the minimum m of the three
 // plane parameters, every axis whose parameter equals m moves to its next
 // plane (two at once where the ray passes exactly through an edge, which
 // only skips a chord of zero length), and the cell offset moves by the
-// strides of those axes.  Each value is loaded one step ahead of its use.
-// FP32 cells are addressed by 32-bit byte offset from the grid base (below
-// 2^32 for G <= 1024), which the hardware adds to the base in the load
-// itself.  The hot loop is VALU- and L1-bound: one gather per step and lane,
-// about 25 VALU instructions per step.
+// strides of those axes.  The cell sequence depends on the geometry only,
+// so the loads run ahead of the sum: FP64 values one cell ahead, FP32 values
+// three cells ahead (three gathers in flight per lane hide more of the L1 /
+// L2 latency; the FP64 kernel and the counter pass have no registers to
+// spare for it).  FP32 cells
+// are addressed by 32-bit byte offset from the grid base (below 2^32 for
+// G <= 1024), which the hardware adds to the base in the load itself.  The
+// hot loop is L1- and latency-bound: one gather per step and lane, about 22
+// VALU instructions per step.
 //
 // The loop ends: each step moves at least one axis whose parameter is below
 // 1, by a_k >= 1 / (2 G) (|D| is below 2G for points in the box; the step is
@@ -241,24 +246,14 @@ __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned
     }
     unsigned off = idx0 * kScale;
     const unsigned off_max = last * kScale;
-    double t = 0.0;
-    TV sum = TV(0), comp = TV(0);
-    auto add = [&](TV v, TV len) {
-        if (sizeof(TV) == 4) {
-            // Kahan-compensated FP32 sum
-            const TV y = fma(v, len, -comp);
-            const TV s2 = sum + y;
-            comp = (s2 - sum) - y;
-            sum = s2;
-        } else {
-            sum = fma(v, len, sum);
-        }
-        if (STATS) ncell += len > TV(0) ? 1 : 0;
+    double t = 0.0, sum = 0.0;
+    auto add = [&](TV v, double len) {
+        sum = fma((double)v, len, sum);
+        if (STATS) ncell += len > 0.0 ? 1 : 0;
     };
-    TV v = load_cell(grid, off);
     double m = min3(tn[0], tn[1], tn[2]);
-    auto step = [&]() {
-        add(v, (TV)(m - t));
+    // leave the current cell (t = m) for the next one and load its value
+    auto advance = [&](TV &vnext) {
         t = m;
         const bool s0 = tn[0] == m, s1 = tn[1] == m, s2 = tn[2] == m;
         tn[0] = fma(s0 ? 1.0 : 0.0, a[0], tn[0]);
@@ -266,18 +261,38 @@ __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned
         tn[2] = fma(s2 ? 1.0 : 0.0, a[2], tn[2]);
         off += (s0 ? (unsigned)ds[0] : 0u) + (s1 ? (unsigned)ds[1] : 0u) + (s2 ? (unsigned)ds[2] : 0u);
         off = off > off_max ? off_max : off;   // also catches a step below 0
-        v = load_cell(grid, off);
+        vnext = load_cell(grid, off);
         m = min3(tn[0], tn[1], tn[2]);
     };
-    // two steps per turn (no register copies between them)
-    for (;;) {
-        if (!(m < 1.0)) break;
-        step();
-        if (!(m < 1.0)) break;
-        step();
+    if constexpr (sizeof(TV) == 4 && !STATS) {
+        // Three registers take the cells in turn; a cell's value is added
+        // when the march leaves the cell two places after it, so the loads
+        // of three cells are in flight.  Cells before the first hold 0.
+        TV vA = load_cell(grid, off), vB = TV(0), vC = TV(0);
+        double lA = 0.0, lB = 0.0, lC = 0.0;
+        for (;;) {
+            if (!(m < 1.0)) { add(vB, lB); add(vC, lC); add(vA, 1.0 - t); break; }
+            add(vB, lB); lA = m - t; advance(vB);
+            if (!(m < 1.0)) { add(vC, lC); add(vA, lA); add(vB, 1.0 - t); break; }
+            add(vC, lC); lB = m - t; advance(vC);
+            if (!(m < 1.0)) { add(vA, lA); add(vB, lB); add(vC, 1.0 - t); break; }
+            add(vA, lA); lC = m - t; advance(vA);
+        }
+        return (TV)sum;
+    } else {
+        TV v = load_cell(grid, off);
+        // two steps per turn (no register copies between them)
+        for (;;) {
+            if (!(m < 1.0)) break;
+            add(v, m - t);
+            advance(v);
+            if (!(m < 1.0)) break;
+            add(v, m - t);
+            advance(v);
+        }
+        add(v, 1.0 - t);
+        return sum;
     }
-    add(v, (TV)(1.0 - t));
-    return sum;
 }
 
 // ---------------------------------------------------------------------------
