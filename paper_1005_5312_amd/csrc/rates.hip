@@ -160,7 +160,8 @@ __device__ inline int lanes_below(uint64_t m)
 // exact since a_k is far above the spacing of doubles below 1), so after at
 // most 2G + 2 steps per axis every parameter is >= 1.  A NaN parameter is
 // never the minimum (v_min_f64 returns the other operand), an all-NaN state
-// exits at once, and +inf never steps.  Positions reaching the kernel are
+// exits at once, and +inf never steps (the FP32 march's t = min(m, 1)
+// reaches 1 at the same step, and at once for NaN).  Positions reaching the kernel are
 // finite and inside the box (checked on entry), so no extra step counter is
 // kept: one costs 4-8% here, as it changes how the loop is scheduled.
 // ---------------------------------------------------------------------------
@@ -266,18 +267,46 @@ __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned
     };
     if constexpr (sizeof(TV) == 4 && !STATS) {
         // Three registers take the cells in turn; a cell's value is added
-        // when the march leaves the cell two places after it, so the loads
-        // of three cells are in flight.  Cells before the first hold 0.
-        TV vA = load_cell(grid, off), vB = TV(0), vC = TV(0);
+        // when the march leaves the cell two places after it, so three loads
+        // are in flight.  The march runs in whole turns of three steps with
+        // the crossing parameter clamped to 1: once a lane has reached the
+        // source its further steps have length 0 and add nothing, so a turn
+        // has no exits inside it, and every turn (the first too: the two
+        // pending registers start as loads of the first cell, added with
+        // length 0) enters with the same three loads in flight, so no wait
+        // for all of them.  Each step is kept in place by a scheduling
+        // barrier so that its load is issued within it.
+        TV vB = load_cell(grid, off);
+        TV vC = load_cell(grid, off);
+        TV vA = load_cell(grid, off);
         double lA = 0.0, lB = 0.0, lC = 0.0;
+        auto leave = [&](double &len, TV &vnext) {
+            const double mc = vmin(m, 1.0);   // a NaN m gives 1: the lane ends
+            len = mc - t;
+            t = mc;
+            const bool s0 = tn[0] == m, s1 = tn[1] == m, s2 = tn[2] == m;
+            tn[0] = fma(s0 ? 1.0 : 0.0, a[0], tn[0]);
+            tn[1] = fma(s1 ? 1.0 : 0.0, a[1], tn[1]);
+            tn[2] = fma(s2 ? 1.0 : 0.0, a[2], tn[2]);
+            off += (s0 ? (unsigned)ds[0] : 0u) + (s1 ? (unsigned)ds[1] : 0u) + (s2 ? (unsigned)ds[2] : 0u);
+            off = off > off_max ? off_max : off;   // also catches a step below 0
+            vnext = load_cell(grid, off);
+            m = min3(tn[0], tn[1], tn[2]);
+        };
         for (;;) {
-            if (!(m < 1.0)) { add(vB, lB); add(vC, lC); add(vA, 1.0 - t); break; }
-            add(vB, lB); lA = m - t; advance(vB);
-            if (!(m < 1.0)) { add(vC, lC); add(vA, lA); add(vB, 1.0 - t); break; }
-            add(vC, lC); lB = m - t; advance(vC);
-            if (!(m < 1.0)) { add(vA, lA); add(vB, lB); add(vC, 1.0 - t); break; }
-            add(vA, lA); lC = m - t; advance(vA);
+            add(vB, lB);
+            leave(lA, vB);
+            __builtin_amdgcn_sched_barrier(0);
+            add(vC, lC);
+            leave(lB, vC);
+            __builtin_amdgcn_sched_barrier(0);
+            add(vA, lA);
+            leave(lC, vA);
+            __builtin_amdgcn_sched_barrier(0);
+            if (!(t < 1.0)) break;
         }
+        add(vB, lB);
+        add(vC, lC);
         return (TV)sum;
     } else {
         TV v = load_cell(grid, off);
@@ -412,7 +441,7 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
 
 template <int PREC, bool STATS>
 __global__ void __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(PREC == START_FP64 ? 5 : 6))) rates_kernel(const Item *__restrict__ items,
+__attribute__((amdgpu_waves_per_eu(PREC == START_FP64 ? 5 : 7))) rates_kernel(const Item *__restrict__ items,
                                                          const int4 *__restrict__ tiles, int n_tiles)
 {
     using T = typename std::conditional<PREC == START_FP64, double, float>::type;
