@@ -111,6 +111,16 @@ start_status start_tree_free(start_ctx *ctx, start_tree *tree);
 start_status start_build_gas_grid(start_ctx *ctx, const start_box *box, int64_t n_gas, const double *gas_xyz,
                                   const double *gas_h, const double *gas_nhi, int grid_log2, start_grid **out);
 start_status start_grid_free(start_ctx *ctx, start_grid *grid);
+/* The tree and the grid of one scene in one call: the same results as
+ * start_build_source_tree and start_build_gas_grid with these arguments,
+ * with the two builds running at the same time (the grid on a second stream
+ * of the context, driven from a second host thread).  Synchronous; all
+ * input pointers must stay valid until it returns.  On any failure both
+ * outputs are NULL, nothing is left allocated, and the status and message
+ * are those of the failing build (the tree's if both fail). */
+start_status start_build_scene(start_ctx *ctx, const start_box *box, int64_t n_s, const double *src_xyz,
+                               const double *src_lum, int64_t n_gas, const double *gas_xyz, const double *gas_h,
+                               const double *gas_nhi, int grid_log2, start_tree **tree_out, start_grid **grid_out);
 /* G of a grid (host). */
 int start_grid_size(const start_grid *grid);
 

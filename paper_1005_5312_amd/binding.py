@@ -25,6 +25,7 @@ STATUS_NAMES = {OK: "START_OK", EINVAL: "START_EINVAL", ENOMEM: "START_ENOMEM", 
 # every symbol include/start.h declares
 EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_synchronize",
            "start_bytes_in_use", "start_build_source_tree", "start_tree_free", "start_build_gas_grid",
+           "start_build_scene",
            "start_grid_free", "start_grid_size", "start_compute_rates", "start_compute_rates_batched",
            "start_estimate_bytes", "start_tree_export", "start_interaction_lists", "start_grid_export",
            "start_rate_counters", "start_profile_enable", "start_profile_read", "start_equilibrium_update",
@@ -89,6 +90,7 @@ def lib():
         "start_build_source_tree": ([P, P, i64, P, P, P], C.c_int),
         "start_tree_free": ([P, P], C.c_int),
         "start_build_gas_grid": ([P, P, i64, P, P, P, C.c_int, P], C.c_int),
+        "start_build_scene": ([P, P, i64, P, P, i64, P, P, P, C.c_int, P, P], C.c_int),
         "start_grid_free": ([P, P], C.c_int),
         "start_grid_size": ([P], C.c_int),
         "start_compute_rates": ([P, P, P, i64, P, P, d, d, C.c_int, P], C.c_int),
@@ -250,6 +252,28 @@ class Context:
                                                int(grid_log2), C.byref(h)), "start_build_gas_grid")
         self._leave(cur)
         return GasGrid(self, h, box)
+
+    def build_scene(self, box: Box, src_xyz, src_lum, gas_xyz, gas_h, gas_nhi, grid_log2: int = 0):
+        """(SourceTree, GasGrid) of one scene, the two builds run at the same
+        time (start_build_scene)."""
+        sx = _xyz(src_xyz, self.device)
+        sl = _vec(src_lum, self.device)
+        gx = _xyz(gas_xyz, self.device)
+        gh = _vec(gas_h, self.device)
+        gn = _vec(gas_nhi, self.device)
+        ns, ng = sx.shape[1], gx.shape[1]
+        if sl.numel() != ns:
+            raise ValueError("src_lum length does not match src_xyz")
+        if gh.numel() != ng or gn.numel() != ng:
+            raise ValueError("gas_h / gas_nhi length does not match gas_xyz")
+        ht, hg = C.c_void_p(), C.c_void_p()
+        b = box.c()
+        cur = self._enter(sx, sl, gx, gh, gn)
+        self._check(lib().start_build_scene(self._h, C.byref(b), ns, _ptr(sx), _ptr(sl), ng, _ptr(gx), _ptr(gh),
+                                            _ptr(gn), int(grid_log2), C.byref(ht), C.byref(hg)),
+                    "start_build_scene")
+        self._leave(cur)
+        return SourceTree(self, ht, box, ns), GasGrid(self, hg, box)
 
     def _enter(self, *tensors):
         """Orders the context stream after the caller's current stream and

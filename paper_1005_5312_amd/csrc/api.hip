@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -15,21 +16,33 @@ void make_fp32_tree(Tree *t, hipStream_t s);
 
 // Freed blocks stay with the context and are handed out again for a request
 // of the same size: the builds ask for the same sizes at every step, and a
-// hipMalloc / hipFree pair costs ~0.3 ms (hipFree waits for the device).  All
-// work of a context runs on its one stream, so a reused block is only touched
-// after the work that used it before.  The pool is returned to the device
-// when an allocation would fail without it, and when the context ends.
-void release_pool(Ctx *c)
+// hipMalloc / hipFree pair costs ~0.3 ms (hipFree waits for the device).  A
+// block is released only once the work that used it is done or is ordered
+// before any later use: the work of a context runs on its stream, and the
+// second stream of start_build_scene only starts after the first is idle and
+// releases blocks only after waiting for its own work.  The pool is returned
+// to the device when an allocation would fail without it, and when the
+// context ends.  A helper context allocates through its owner.
+static void release_pool_locked(Ctx *c)
 {
     for (auto &b : c->pool) hipFree(b.first);
     c->pool.clear();
     c->pooled = 0;
 }
 
+void release_pool(Ctx *c)
+{
+    if (c->mem_owner) c = c->mem_owner;
+    std::lock_guard<std::mutex> lock(c->mem_mu);
+    release_pool_locked(c);
+}
+
 hipError_t dmalloc(Ctx *c, void **p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
+    if (c->mem_owner) c = c->mem_owner;
+    std::lock_guard<std::mutex> lock(c->mem_mu);
     if (c->budget && c->in_use + bytes > c->budget) return hipErrorOutOfMemory;
     for (size_t i = c->pool.size(); i-- > 0;)
         if (c->pool[i].second == bytes) {
@@ -39,11 +52,11 @@ hipError_t dmalloc(Ctx *c, void **p, size_t bytes)
             c->in_use += bytes;
             return hipSuccess;
         }
-    if (c->budget && c->in_use + c->pooled + bytes > c->budget) release_pool(c);
+    if (c->budget && c->in_use + c->pooled + bytes > c->budget) release_pool_locked(c);
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess && !c->pool.empty()) {
         (void)hipGetLastError();
-        release_pool(c);
+        release_pool_locked(c);
         e = hipMalloc(p, bytes);
     }
     if (e == hipSuccess) c->in_use += bytes;
@@ -55,6 +68,8 @@ void dfree(Ctx *c, void *p, size_t bytes)
 {
     if (!p) return;
     if (bytes == 0) bytes = 256;
+    if (c->mem_owner) c = c->mem_owner;
+    std::lock_guard<std::mutex> lock(c->mem_mu);
     c->in_use -= bytes < c->in_use ? bytes : c->in_use;
     c->pool.emplace_back(p, bytes);
     c->pooled += bytes;
@@ -290,6 +305,8 @@ void start_ctx_destroy(start_ctx *ctx)
     hipStreamSynchronize(ctx->c.stream);
     dfree(&ctx->c, ctx->c.scratch, ctx->c.scratch_bytes);
     release_pool(&ctx->c);
+    if (ctx->c.stream2) hipStreamDestroy(ctx->c.stream2);
+    if (ctx->c.ev2) hipEventDestroy(ctx->c.ev2);
     for (hipEvent_t ev : ctx->c.ev_pool) hipEventDestroy(ev);
     if (ctx->c.stage_ev) hipEventDestroy(ctx->c.stage_ev);
     if (ctx->c.host_stage) hipHostFree(ctx->c.host_stage);
@@ -365,21 +382,31 @@ start_status start_tree_free(start_ctx *ctx, start_tree *tree)
     return START_OK;
 }
 
-start_status start_build_gas_grid(start_ctx *ctx, const start_box *box, int64_t n_gas, const double *gas_xyz,
-                                  const double *gas_h, const double *gas_nhi, int grid_log2, start_grid **out)
+// Host-side checks of the grid build's arguments; resolves grid_log2 = 0.
+static start_status check_grid_args(start_ctx *ctx, const start_box *box, int64_t n_gas, const double *gas_xyz,
+                                    const double *gas_h, const double *gas_nhi, int *grid_log2)
 {
-    if (!ctx || !out) return START_EINVAL;
-    *out = nullptr;
     start_status st = check_box(ctx, box);
     if (st) return st;
     if (n_gas < 0) return fail(ctx, START_EINVAL, "n_gas < 0");
     if (n_gas > ((int64_t)1 << 31) - 1) return fail(ctx, START_EINVAL, "n_gas too large");
     if (n_gas > 0 && (!gas_xyz || !gas_h || !gas_nhi)) return fail(ctx, START_EINVAL, "gas arrays are NULL");
-    if (grid_log2 == 0) {
-        grid_log2 = 1;
-        while (grid_log2 < 10 && (double)(1 << grid_log2) < std::cbrt((double)n_gas) - 1e-9) ++grid_log2;
+    if (*grid_log2 == 0) {
+        int gl = 1;
+        while (gl < 10 && (double)(1 << gl) < std::cbrt((double)n_gas) - 1e-9) ++gl;
+        *grid_log2 = gl;
     }
-    if (grid_log2 < 1 || grid_log2 > 10) return fail(ctx, START_EINVAL, "grid_log2 must be in [1, 10]");
+    if (*grid_log2 < 1 || *grid_log2 > 10) return fail(ctx, START_EINVAL, "grid_log2 must be in [1, 10]");
+    return START_OK;
+}
+
+start_status start_build_gas_grid(start_ctx *ctx, const start_box *box, int64_t n_gas, const double *gas_xyz,
+                                  const double *gas_h, const double *gas_nhi, int grid_log2, start_grid **out)
+{
+    if (!ctx || !out) return START_EINVAL;
+    *out = nullptr;
+    start_status st = check_grid_args(ctx, box, n_gas, gas_xyz, gas_h, gas_nhi, &grid_log2);
+    if (st) return st;
     hipSetDevice(ctx->c.device);
     st = start_synchronize(ctx);
     if (st) return st;
@@ -393,6 +420,87 @@ start_status start_build_gas_grid(start_ctx *ctx, const start_box *box, int64_t 
         return st;
     }
     *out = g;
+    return START_OK;
+}
+
+start_status start_build_scene(start_ctx *ctx, const start_box *box, int64_t n_s, const double *src_xyz,
+                               const double *src_lum, int64_t n_gas, const double *gas_xyz, const double *gas_h,
+                               const double *gas_nhi, int grid_log2, start_tree **tree_out, start_grid **grid_out)
+{
+    if (!ctx || !tree_out || !grid_out) return START_EINVAL;
+    *tree_out = nullptr;
+    *grid_out = nullptr;
+    start_status st = check_box(ctx, box);
+    if (st) return st;
+    if (n_s < 0) return fail(ctx, START_EINVAL, "n_s < 0");
+    if (n_s > ((int64_t)1 << 30)) return fail(ctx, START_EINVAL, "n_s too large");
+    if (n_s > 0 && (!src_xyz || !src_lum)) return fail(ctx, START_EINVAL, "source arrays are NULL");
+    st = check_grid_args(ctx, box, n_gas, gas_xyz, gas_h, gas_nhi, &grid_log2);
+    if (st) return st;
+    Ctx &c = ctx->c;
+    hipSetDevice(c.device);
+    st = start_synchronize(ctx);   // also: every pooled block is idle from here on
+    if (st) return st;
+    if (!c.stream2) {
+        if (hipStreamCreateWithFlags(&c.stream2, hipStreamNonBlocking) != hipSuccess) {
+            c.stream2 = nullptr;
+            return fail(ctx, START_EHIP, "second stream");
+        }
+        if (hipEventCreateWithFlags(&c.ev2, hipEventDisableTiming) != hipSuccess) {
+            c.ev2 = nullptr;
+            return fail(ctx, START_EHIP, "second stream event");
+        }
+    }
+    // the grid's stream starts after all work before it on the context's
+    hipEventRecord(c.ev2, c.stream);
+    hipStreamWaitEvent(c.stream2, c.ev2, 0);
+    start_tree *t = new (std::nothrow) start_tree;
+    start_grid *g = new (std::nothrow) start_grid;
+    if (!t || !g) {
+        delete t;
+        delete g;
+        return START_ENOMEM;
+    }
+    // the grid is built from a second host thread on the second stream, by
+    // a helper context with its own validation word that allocates through
+    // this one; build_grid waits for its stream before it returns
+    Ctx side;
+    side.device = c.device;
+    side.stream = c.stream2;
+    side.d_flags = c.d_flags + 2;
+    side.mem_owner = &c;
+    start_status gst = START_OK;
+    std::thread worker([&]() {
+        hipSetDevice(side.device);
+        gst = build_grid(&side, *box, n_gas, gas_xyz, gas_h, gas_nhi, grid_log2, &g->g);
+    });
+    start_status tst = build_tree(&c, *box, n_s, src_xyz, src_lum, &t->t);
+    bool have_tree = tst == START_OK;
+    if (have_tree) {
+        make_fp32_tree(&t->t, c.stream);
+        hipError_t e = hipStreamSynchronize(c.stream);
+        if (e != hipSuccess) {
+            c.err = hipGetErrorString(e);
+            tst = START_EHIP;
+        }
+    }
+    worker.join();
+    if (tst == START_ENOMEM && c.budget) tst = START_EBUDGET;
+    if (gst == START_ENOMEM && c.budget) gst = START_EBUDGET;
+    if (tst || gst) {
+        if (have_tree) dfree(&c, t->t.keys, t->t.bytes);
+        if (!gst) dfree(&c, g->g.val, g->g.bytes);
+        delete t;
+        delete g;
+        if (tst) {
+            if (c.err.empty()) c.err = "tree build failed";
+            return tst;
+        }
+        c.err = side.err.empty() ? "grid build failed" : side.err;
+        return gst;
+    }
+    *tree_out = t;
+    *grid_out = g;
     return START_OK;
 }
 

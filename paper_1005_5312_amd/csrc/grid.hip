@@ -425,6 +425,7 @@ start_status build_grid(Ctx *c, const start_box &box, int64_t n, const double *x
     GasBins b;
     st = bin_gas(c, box, n, xyz, h, nhi, grid_log2, &b);
     if (st) {
+        hipStreamSynchronize(c->stream);   // the padding clear may still run
         dfree(c, g->val, g->bytes);
         return st;
     }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -51,9 +52,16 @@ struct Ctx {
     // captured HIP graph
     bool graphs = true;
     // freed device blocks kept for reuse (dmalloc / dfree), at most
-    // kPoolMaxBytes in total
+    // kPoolMaxBytes in total; guarded by mem_mu
     std::vector<std::pair<void *, size_t>> pool;
     size_t pooled = 0;
+    std::mutex mem_mu;
+    // a helper context (the second build of start_build_scene) allocates
+    // through its owner: one budget, one pool
+    Ctx *mem_owner = nullptr;
+    // second stream and its event, for the concurrent scene builds
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev2 = nullptr;
     // walk-kernel timing (start_profile_enable)
     bool profile = false;
     std::vector<hipEvent_t> ev_pool;   // pairs (start, stop)

@@ -1,0 +1,103 @@
+"""The two-stream scene build (start_build_scene) against the separate tree
+and grid builds: the same tree and grid bit for bit, the same rates, no
+memory left behind on failures, and the failing build's status."""
+import numpy as np
+import pytest
+
+from paper_1005_5312_amd import binding as B
+from tests import gpu_common as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("name", ["small", "clumpy"])
+def test_scene_equals_separate_builds(ctx, name):
+    w = H.workload(name)
+    print(f"[case] scene {name}", flush=True)
+    box = H.box_of(w)
+    args = (dev(w.src_xyz), dev(w.src_lum), dev(w.gas_xyz), dev(w.gas_h), dev(w.gas_nhi))
+    t1 = ctx.build_source_tree(box, args[0], args[1])
+    g1 = ctx.build_gas_grid(box, args[2], args[3], args[4], w.grid_log2)
+    t2, g2 = ctx.build_scene(box, *args, w.grid_log2)
+    e1, e2 = ctx.tree_export(t1), ctx.tree_export(t2)
+    assert sorted(e1) == sorted(e2)
+    for k in e1:
+        assert np.array_equal(e1[k], e2[k]), k
+    assert np.array_equal(ctx.grid_export(g1), ctx.grid_export(g2))
+    tgt = dev(w.tgt_xyz)
+    ss = None if w.self_src is None else dev(w.self_src)
+    for prec in ("fp32c", "fp64"):
+        a = ctx.compute_rates(t1, g1, tgt, ss, 1.0, w.sigma, prec).cpu().numpy()
+        b = ctx.compute_rates(t2, g2, tgt, ss, 1.0, w.sigma, prec).cpu().numpy()
+        assert np.array_equal(a, b), prec
+    for o in (t1, g1, t2, g2):
+        o.free()
+
+
+def test_scene_repeated_builds_release_memory(ctx):
+    """Ten builds in a row (blocks handed back and forth between the two
+    build threads through the context's pool): same grid every time, and the
+    memory held returns to where it was."""
+    w = H.workload("clumpy")
+    box = H.box_of(w)
+    args = (dev(w.src_xyz), dev(w.src_lum), dev(w.gas_xyz), dev(w.gas_h), dev(w.gas_nhi))
+    base = ctx.bytes_in_use()
+    ref = None
+    for _ in range(10):
+        t, g = ctx.build_scene(box, *args, w.grid_log2)
+        v = ctx.grid_export(g)
+        if ref is None:
+            ref = v
+        assert np.array_equal(v, ref)
+        t.free()
+        g.free()
+        assert ctx.bytes_in_use() == base
+
+
+@pytest.mark.parametrize("bad,code", [("gas_out_of_box", B.EOUTOFBOX), ("src_nonfinite", B.ENONFINITE),
+                                      ("both", B.ENONFINITE), ("gas_h_negative", B.EINVAL)])
+def test_scene_failures(ctx, bad, code):
+    w = H.workload("small")
+    box = H.box_of(w)
+    sx, sl = w.src_xyz.copy(), w.src_lum.copy()
+    gx, gh = w.gas_xyz.copy(), w.gas_h.copy()
+    if bad in ("gas_out_of_box", "both"):
+        gx[0, 5] = w.box_lo[0] + 2 * w.box_size
+    if bad in ("src_nonfinite", "both"):
+        sx[1, 3] = np.nan
+    if bad == "gas_h_negative":
+        gh[7] = -1.0
+    base = ctx.bytes_in_use()
+    with pytest.raises(B.StartError) as ei:
+        ctx.build_scene(box, dev(sx), dev(sl), dev(gx), dev(gh), dev(w.gas_nhi), w.grid_log2)
+    assert ei.value.code == code
+    assert ctx.bytes_in_use() == base
+    # the context stays usable
+    t, g = ctx.build_scene(box, dev(w.src_xyz), dev(w.src_lum), dev(w.gas_xyz), dev(w.gas_h), dev(w.gas_nhi),
+                           w.grid_log2)
+    t.free()
+    g.free()
+
+
+def test_scene_budget():
+    w = H.workload("small")
+    box = H.box_of(w)
+    with B.Context(0, hbm_budget=1 << 16) as c:
+        with pytest.raises(B.StartError) as ei:
+            c.build_scene(box, dev(w.src_xyz), dev(w.src_lum), dev(w.gas_xyz), dev(w.gas_h), dev(w.gas_nhi),
+                          w.grid_log2)
+        assert ei.value.code == B.EBUDGET
+        assert c.bytes_in_use() == 0
