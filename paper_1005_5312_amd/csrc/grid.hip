@@ -124,17 +124,13 @@ __global__ void __launch_bounds__(kThreads) gather_values(int64_t n, const unsig
 }
 
 // M4 cubic spline of section 2.1 with 3-D normalisation 1/(pi h^3), from
-// q = r / h and the normalisation.
+// q = r / h and the normalisation, without branches: 0.25 (2 - q)^3 less
+// (1 - q)^3 below q = 1 is the inner polynomial 1 - 1.5 q^2 + 0.75 q^3, and
+// both cubes vanish from q = 2 on.
 __device__ inline double kernel_w(double q, double norm)
 {
-    double f;
-    if (q <= 1.0)
-        f = 1.0 - 1.5 * q * q + 0.75 * q * q * q;
-    else if (q <= 2.0)
-        f = 0.25 * (2.0 - q) * (2.0 - q) * (2.0 - q);
-    else
-        f = 0.0;
-    return f * norm;
+    const double t2 = fmax(2.0 - q, 0.0), t1 = fmax(1.0 - q, 0.0);
+    return (0.25 * (t2 * t2 * t2) - t1 * t1 * t1) * norm;
 }
 
 constexpr int kCellsZ = 4;   // cell centres per thread, consecutive along z
@@ -193,22 +189,17 @@ __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double
                     const double dx = xc - p.x, dy = yc - p.y;
                     const double dxy2 = dx * dx + dy * dy, h2 = 4.0 * p.w * p.w;
                     if (!(dxy2 < h2)) continue;
-                    double2 kk = make_double2(0.0, 0.0);
-                    double nk = 0.0;
-                    bool loaded = false;
+                    // the four centres without branches: a centre outside
+                    // the support 2h (or past the row's end) adds 0
+                    const double2 kk = kern[s];
+                    const double nk = ns[s];
+#pragma unroll
                     for (int j = 0; j < kCellsZ; ++j) {
                         const double dz = zc[j] - p.z;
                         const double r2 = dxy2 + dz * dz;
-                        if (j < nz && r2 < h2) {   // inside the support 2h
-                            if (!loaded) {
-                                kk = kern[s];
-                                nk = ns[s];
-                                loaded = true;
-                            }
-                            const double w = kernel_w(sqrt(r2) * kk.x, kk.y);
-                            num[j] += nk * w;
-                            den[j] += w;
-                        }
+                        const double w = (j < nz && r2 < h2) ? kernel_w(sqrt(r2) * kk.x, kk.y) : 0.0;
+                        num[j] = fma(nk, w, num[j]);
+                        den[j] += w;
                     }
                 }
             }
