@@ -428,6 +428,57 @@ def upstream_bench(reps=3):
     return out
 
 
+def theta_sweep_bench(thetas=(0.0, 0.3, 0.5, 0.8, 1.0), reps=3):
+    """The clumpy medium (2^18 particles, 1024 sources with L = 10^U[47,50])
+    over the opening angle: time per rate call in both precisions and the
+    error against theta = 0, where every source is summed on its own (the
+    exact sum over sources on the same grid), as median / p99 / max of the
+    relative difference over all 2^18 particles."""
+    import torch
+    import paper_1005_5312_amd as S
+    from paper_1005_5312_amd import workloads as W
+    w = W.make_clumpy()
+    ctx = S.Context(0)
+    dev = torch.device("cuda", 0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    box = S.Box(tuple(float(v) for v in w.box_lo), float(w.box_size), float(w.length_unit_cm))
+    tree, grid = ctx.build_scene(box, d(w.src_xyz), d(w.src_lum), d(w.gas_xyz), d(w.gas_h), d(w.gas_nhi),
+                                 w.grid_log2)
+    tgt = d(w.tgt_xyz)
+    outs = {"fp64": torch.empty(w.n_tgt, dtype=torch.float64, device=dev),
+            "fp32c": torch.empty(w.n_tgt, dtype=torch.float32, device=dev)}
+    ref = None
+    rows = []
+    for theta in thetas:
+        row = {"theta": theta}
+        for prec in ("fp64", "fp32c"):
+            out = outs[prec]
+            ctx.compute_rates_raw(tree, grid, tgt, None, theta, w.sigma, prec, out)
+            ctx.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.compute_rates_raw(tree, grid, tgt, None, theta, w.sigma, prec, out)
+            ctx.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            g = out.cpu().numpy().astype(np.float64)
+            if ref is None:
+                ref = g.copy()          # theta = 0, FP64: the exact sum over sources
+            rel = np.abs(g - ref) / ref
+            row[prec] = {"ms_per_call": ms, "evals_per_s": w.n_tgt / (ms * 1e-3),
+                         "rel_err_vs_theta0_fp64": {"median": float(np.median(rel)),
+                                                     "p99": float(np.percentile(rel, 99)),
+                                                     "max": float(rel.max())}}
+        log(f"[bench] theta {theta}: fp64 {row['fp64']['ms_per_call']:.2f} ms, fp32c "
+            f"{row['fp32c']['ms_per_call']:.2f} ms, fp32c median rel err vs theta 0 "
+            f"{row['fp32c']['rel_err_vs_theta0_fp64']['median']:.2e}")
+        rows.append(row)
+    tree.free()
+    grid.free()
+    ctx.close()
+    return {"workload": f"{w.n_gas} particles (lognormal), {w.n_src} sources, G = {1 << w.grid_log2}",
+            "sweep": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -585,6 +636,11 @@ def main():
         log("[bench] upstream-particle chain")
         up_stats = upstream_bench()
 
+    sweep_stats = None
+    if not args.rates_only:
+        log("[bench] opening-angle sweep on the clumpy medium")
+        sweep_stats = theta_sweep_bench()
+
     eq_stats = None
     if not args.no_equilibrium and not args.rates_only:
         log("[bench] photoionisation equilibrium (Test 4 setting)")
@@ -625,6 +681,7 @@ def main():
         "serve": serve_stats,
         "batched": batch_stats,
         "equilibrium": eq_stats,
+        "theta_sweep": sweep_stats,
         "k_ion_terms": kion_stats,
         "h2_dissociation": lw_stats,
         "upstream_chain": up_stats,

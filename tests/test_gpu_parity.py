@@ -117,7 +117,7 @@ def test_lists_bit_exact_small(ctx, theta):
     assert np.array_equal(H.gpu_entries_as_cells(ent, geo), oent)
 
 
-@pytest.mark.parametrize("theta", [0.3, 1.0])
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.8, 1.0])
 def test_lists_bit_exact_clumpy_subset(ctx, theta):
     w = H.workload("clumpy")
     print(f"[case] lists clumpy theta={theta}", flush=True)
@@ -218,7 +218,7 @@ def test_rates_small(ctx, theta, prec):
     assert ab <= H.ABS_FLOOR
 
 
-@pytest.mark.parametrize("theta", [0.3, 1.0])
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.8, 1.0])
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_rates_clumpy_sampled(ctx, theta, prec):
     w = H.workload("clumpy")
@@ -228,14 +228,36 @@ def test_rates_clumpy_sampled(ctx, theta, prec):
     ctx.synchronize()
     idx = H.W.sample_indices(w.n_tgt, 1500, seed=7)
     ot = O.Tree(H.obox_of(w), w.src_xyz, w.src_lum)
-    og = ctx.grid_export(grid)   # the oracle grid equals this to 1e-12 (test_grid_parity)
     want = O.rates(ot, w.grid_log2, O.grid(H.obox_of(w), w.gas_xyz, w.gas_h, w.gas_nhi, w.grid_log2),
                    w.tgt_xyz[:, idx], None, theta, w.sigma)
-    del og
     rel, ab, nbig = H.rel_errors(got.cpu().numpy()[idx], want)
     print(f"  max rel {rel:.3e} over {nbig}, max abs below floor {ab:.3e}")
     assert rel <= (H.TOL_FP64 if prec == "fp64" else H.TOL_FP32C)
     assert ab <= H.ABS_FLOOR
+
+
+def test_theta_sweep_error_grows_with_theta(ctx):
+    """Clumpy medium, all 2^18 particles: theta = 0 sums every source on its
+    own and matches the oracle's exact sum on sampled particles; the error
+    of the tree approximation against it grows with theta."""
+    w = H.workload("clumpy")
+    print("[case] theta sweep clumpy", flush=True)
+    tree, grid = build(ctx, w)
+    tgt = dev(w.tgt_xyz)
+    g0 = ctx.compute_rates(tree, grid, tgt, None, 0.0, w.sigma, "fp64").cpu().numpy()
+    idx = H.W.sample_indices(w.n_tgt, 400, seed=3)
+    want = O.rates(O.Tree(H.obox_of(w), w.src_xyz, w.src_lum), w.grid_log2,
+                   O.grid(H.obox_of(w), w.gas_xyz, w.gas_h, w.gas_nhi, w.grid_log2), w.tgt_xyz[:, idx], None, 0.0,
+                   w.sigma)
+    rel, ab, _ = H.rel_errors(g0[idx], want)
+    assert rel <= H.TOL_FP64 and ab <= H.ABS_FLOOR
+    med = []
+    for theta in (0.3, 0.5, 0.8, 1.0):
+        g = ctx.compute_rates(tree, grid, tgt, None, theta, w.sigma, "fp32c").cpu().numpy().astype(np.float64)
+        e = np.abs(g / g0 - 1)
+        med.append(float(np.median(e)))
+        print(f"  theta {theta}: median rel err vs theta 0 {med[-1]:.2e}, p99 {np.percentile(e, 99):.2e}")
+    assert all(a < b for a, b in zip(med, med[1:]))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
