@@ -146,14 +146,14 @@ __device__ inline int lanes_below(uint64_t m)
 // plane (two at once where the ray passes exactly through an edge, which
 // only skips a chord of zero length), and the cell offset moves by the
 // strides of those axes.  The cell sequence depends on the geometry only,
-// so the loads run ahead of the sum: FP64 values one cell ahead, FP32 values
-// three cells ahead (three gathers in flight per lane hide more of the L1 /
-// L2 latency; the FP64 kernel and the counter pass have no registers to
-// spare for it).  FP32 cells
-// are addressed by 32-bit byte offset from the grid base (below 2^32 for
-// G <= 1024), which the hardware adds to the base in the load itself.  The
-// hot loop is L1- and latency-bound: one gather per step and lane, about 22
-// VALU instructions per step.
+// so the loads run ahead of the sum: three cells ahead in the rate kernels
+// (three gathers in flight per lane hide most of the L1 / L2 latency: 7%
+// faster in FP32 and 16% in FP64 than one), one ahead in the counter pass,
+// which has no registers to spare.  FP32 cells are addressed by 32-bit byte
+// offset from the grid base (below 2^32 for G <= 1024), which the hardware
+// adds to the base in the load itself.  The hot loop is L1- and
+// latency-bound: one gather per step and lane, about 22 VALU instructions
+// per step.
 //
 // The loop ends: each step moves at least one axis whose parameter is below
 // 1, by a_k >= 1 / (2 G) (|D| is below 2G for points in the box; the step is
@@ -265,7 +265,7 @@ __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned
         vnext = load_cell(grid, off);
         m = min3(tn[0], tn[1], tn[2]);
     };
-    if constexpr (sizeof(TV) == 4 && !STATS) {
+    if constexpr (!STATS) {
         // Three registers take the cells in turn; a cell's value is added
         // when the march leaves the cell two places after it, so three loads
         // are in flight.  The march runs in whole turns of three steps with
@@ -309,6 +309,7 @@ __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned
         add(vC, lC);
         return (TV)sum;
     } else {
+        // the counter pass: one load ahead
         TV v = load_cell(grid, off);
         // two steps per turn (no register copies between them)
         for (;;) {
