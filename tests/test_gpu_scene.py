@@ -101,3 +101,34 @@ def test_scene_budget():
                           w.grid_log2)
         assert ei.value.code == B.EBUDGET
         assert c.bytes_in_use() == 0
+
+
+@pytest.mark.parametrize("case", ["no_sources", "no_gas", "both_empty", "auto_grid"])
+def test_scene_edge_cases(ctx, case):
+    """Empty source or gas sets and the automatic grid size go through the
+    scene build exactly as through the separate builds."""
+    w = H.workload("small")
+    box = H.box_of(w)
+    sx, sl = w.src_xyz, w.src_lum
+    gx, gh, gn = w.gas_xyz, w.gas_h, w.gas_nhi
+    gl = w.grid_log2
+    if case in ("no_sources", "both_empty"):
+        sx, sl = np.zeros((3, 0)), np.zeros(0)
+    if case in ("no_gas", "both_empty"):
+        gx, gh, gn = np.zeros((3, 0)), np.zeros(0), np.zeros(0)
+    if case == "auto_grid":
+        gl = 0
+    print(f"[case] scene edge {case}", flush=True)
+    t1 = ctx.build_source_tree(box, dev(sx), dev(sl))
+    g1 = ctx.build_gas_grid(box, dev(gx), dev(gh), dev(gn), gl)
+    t2, g2 = ctx.build_scene(box, dev(sx), dev(sl), dev(gx), dev(gh), dev(gn), gl)
+    assert g1.G == g2.G
+    assert np.array_equal(ctx.grid_export(g1), ctx.grid_export(g2))
+    tgt = dev(w.tgt_xyz[:, :300])
+    a = ctx.compute_rates(t1, g1, tgt, None, 1.0, w.sigma, "fp64").cpu().numpy()
+    b = ctx.compute_rates(t2, g2, tgt, None, 1.0, w.sigma, "fp64").cpu().numpy()
+    assert np.array_equal(a, b)
+    if sx.shape[1] == 0:
+        assert not b.any()
+    for o in (t1, g1, t2, g2):
+        o.free()
