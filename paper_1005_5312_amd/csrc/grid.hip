@@ -133,6 +133,18 @@ __device__ inline double kernel_w(double q, double norm)
     return (0.25 * (t2 * t2 * t2) - t1 * t1 * t1) * norm;
 }
 
+// sqrt(x) for 0 <= x (finite): the hardware reciprocal square root and one
+// Newton step on the root, ~1e-15 relative (the library sqrt rounds
+// correctly but takes ~4x the instructions).  Below 1e-200 the result is
+// ~1e-100 instead of x^(1/2): kernel weights are then W(0) either way.
+__device__ inline double sqrt_nr(double x)
+{
+    const double xm = fmax(x, 1e-200);
+    const double y = __builtin_amdgcn_rsq(xm);
+    const double r = xm * y;
+    return fma(0.5 * y, fma(-r, r, xm), r);
+}
+
 constexpr int kCellsZ = 4;   // cell centres per thread, consecutive along z
 
 // kCellsZ consecutive cell centres of one z row per thread: they share x and
@@ -197,7 +209,7 @@ __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double
                     for (int j = 0; j < kCellsZ; ++j) {
                         const double dz = zc[j] - p.z;
                         const double r2 = dxy2 + dz * dz;
-                        const double w = (j < nz && r2 < h2) ? kernel_w(sqrt(r2) * kk.x, kk.y) : 0.0;
+                        const double w = (j < nz && r2 < h2) ? kernel_w(sqrt_nr(r2) * kk.x, kk.y) : 0.0;
                         num[j] = fma(nk, w, num[j]);
                         den[j] += w;
                     }
