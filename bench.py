@@ -428,6 +428,84 @@ def upstream_bench(reps=3):
     return out
 
 
+def _rel_stats(got, ref, floor=1e-30):
+    """Relative-error statistics above the Gamma floor, and the largest
+    absolute difference below it."""
+    big = ref >= floor
+    rel = np.abs(got[big] - ref[big]) / ref[big]
+    small = np.abs(got[~big] - ref[~big])
+    return {"n_above_floor": int(big.sum()), "median": float(np.median(rel)) if rel.size else 0.0,
+            "p99": float(np.percentile(rel, 99)) if rel.size else 0.0,
+            "p99_9": float(np.percentile(rel, 99.9)) if rel.size else 0.0,
+            "max": float(rel.max()) if rel.size else 0.0,
+            "max_abs_below_floor": float(small.max()) if small.size else 0.0}
+
+
+def tree_error_bench(ctx, w, tree, grid, n_sample=1024, seed=23):
+    """The tree approximation on the bench workload: theta = 1 in both
+    precisions against theta = 0 (every source on its own: the exact sum
+    over sources on the same grid), on a seeded sample of targets."""
+    import torch
+    from paper_1005_5312_amd import workloads as W
+    dev = torch.device("cuda", 0)
+    idx = W.sample_indices(w.n_tgt, n_sample, seed)
+    tgt = torch.from_numpy(np.ascontiguousarray(w.tgt_xyz[:, idx])).to(dev)
+    ss = None if w.self_src is None else torch.from_numpy(np.ascontiguousarray(w.self_src[idx])).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g0 = ctx.compute_rates(tree, grid, tgt, ss, 0.0, w.sigma, "fp64").cpu().numpy()
+    ms0 = (time.perf_counter() - t0) * 1e3
+    g64 = ctx.compute_rates(tree, grid, tgt, ss, 1.0, w.sigma, "fp64").cpu().numpy()
+    g32 = ctx.compute_rates(tree, grid, tgt, ss, 1.0, w.sigma, "fp32c").cpu().numpy().astype(np.float64)
+    log(f"[bench] theta 1 vs theta 0 on {n_sample} targets: fp64 median rel "
+        f"{_rel_stats(g64, g0)['median']:.2e}")
+    return {"sample_targets": n_sample, "theta0_ms": ms0, "fp64_theta1_vs_theta0": _rel_stats(g64, g0),
+            "fp32c_theta1_vs_theta0": _rel_stats(g32, g0)}
+
+
+def shadow_bench(reps=3):
+    """The shadowing configuration (2^21 emitting particles, a 1e50/s star,
+    16 dense neutral clumps, theta = 1, G = 128): rate-call time in both
+    precisions and the FP32C error against FP64 over every particle, in the
+    clumps and outside them."""
+    import torch
+    import paper_1005_5312_amd as S
+    from paper_1005_5312_amd import workloads as W
+    w = W.make_shadow()
+    ctx = S.Context(0)
+    dev = torch.device("cuda", 0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    box = S.Box(tuple(float(v) for v in w.box_lo), float(w.box_size), float(w.length_unit_cm))
+    tree, grid = ctx.build_scene(box, d(w.src_xyz), d(w.src_lum), d(w.gas_xyz), d(w.gas_h), d(w.gas_nhi),
+                                 w.grid_log2)
+    tgt, ss = d(w.tgt_xyz), d(w.self_src)
+    res = {}
+    outs = {"fp64": torch.empty(w.n_tgt, dtype=torch.float64, device=dev),
+            "fp32c": torch.empty(w.n_tgt, dtype=torch.float32, device=dev)}
+    for prec, out in outs.items():
+        ctx.compute_rates_raw(tree, grid, tgt, ss, 1.0, w.sigma, prec, out)
+        ctx.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.compute_rates_raw(tree, grid, tgt, ss, 1.0, w.sigma, prec, out)
+        ctx.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res[prec] = {"ms_per_call": ms, "evals_per_s": w.n_tgt / (ms * 1e-3)}
+    g64 = outs["fp64"].cpu().numpy()
+    g32 = outs["fp32c"].cpu().numpy().astype(np.float64)
+    clump = w.gas_nhi > 0.01
+    res["fp32c_vs_fp64_all"] = _rel_stats(g32, g64)
+    res["fp32c_vs_fp64_in_clumps"] = _rel_stats(g32[clump], g64[clump])
+    res["fp32c_vs_fp64_outside"] = _rel_stats(g32[~clump], g64[~clump])
+    res["workload"] = WORKLOAD_TEXT["shadow"]
+    log(f"[bench] shadow: fp32c {res['fp32c']['ms_per_call']:.1f} ms, fp64 {res['fp64']['ms_per_call']:.1f} ms, "
+        f"fp32c vs fp64 max rel {res['fp32c_vs_fp64_all']['max']:.2e}")
+    tree.free()
+    grid.free()
+    ctx.close()
+    return res
+
+
 def theta_sweep_bench(thetas=(0.0, 0.3, 0.5, 0.8, 1.0), reps=3):
     """The clumpy medium (2^18 particles, 1024 sources with L = 10^U[47,50])
     over the opening angle: time per rate call in both precisions and the
@@ -494,6 +572,7 @@ def main():
     ap.add_argument("--serve-rates", default="10,100,1000", help="Poisson arrival rates swept (requests/s)")
     ap.add_argument("--serve-requests", type=int, default=100, help="requests per arrival rate")
     ap.add_argument("--no-equilibrium", action="store_true", help="skip the equilibrium-loop measurement")
+    ap.add_argument("--no-shadow", action="store_true", help="skip the 2^21-particle shadowing measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -641,6 +720,16 @@ def main():
         log("[bench] opening-angle sweep on the clumpy medium")
         sweep_stats = theta_sweep_bench()
 
+    tree_err = None
+    if not args.rates_only:
+        log("[bench] tree approximation against theta = 0 on sampled targets")
+        tree_err = tree_error_bench(ctx, w, tree, grid)
+
+    shadow_stats = None
+    if not args.rates_only and not args.no_shadow:
+        log("[bench] shadowing configuration (2^21 particles)")
+        shadow_stats = shadow_bench()
+
     eq_stats = None
     if not args.no_equilibrium and not args.rates_only:
         log("[bench] photoionisation equilibrium (Test 4 setting)")
@@ -682,6 +771,8 @@ def main():
         "batched": batch_stats,
         "equilibrium": eq_stats,
         "theta_sweep": sweep_stats,
+        "tree_error": tree_err,
+        "shadow": shadow_stats,
         "k_ion_terms": kion_stats,
         "h2_dissociation": lw_stats,
         "upstream_chain": up_stats,
