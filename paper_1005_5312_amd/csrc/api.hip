@@ -471,8 +471,14 @@ start_status start_build_scene(start_ctx *ctx, const start_box *box, int64_t n_s
     side.mem_owner = &c;
     start_status gst = START_OK;
     std::thread worker([&]() {
-        hipSetDevice(side.device);
-        gst = build_grid(&side, *box, n_gas, gas_xyz, gas_h, gas_nhi, grid_log2, &g->g);
+        // no exception may leave the thread (it would end the process)
+        try {
+            hipSetDevice(side.device);
+            gst = build_grid(&side, *box, n_gas, gas_xyz, gas_h, gas_nhi, grid_log2, &g->g);
+        } catch (...) {
+            side.err = "grid build: host allocation failed";
+            gst = START_ENOMEM;
+        }
     });
     start_status tst = build_tree(&c, *box, n_s, src_xyz, src_lum, &t->t);
     bool have_tree = tst == START_OK;
