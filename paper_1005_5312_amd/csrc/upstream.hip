@@ -93,6 +93,7 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
     if (p >= n_pairs) return;
     const unsigned i = owner[p];
     const uint64_t key = keys[p];
+    const unsigned li = off[i], ni = off[i + 1] - li, rank = (unsigned)(p - li);   // alpha's place in i's list
     const double4 a = source_of_key(mom, src, first, key);
     const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
     const double di = dist3(x, a);
@@ -101,14 +102,41 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
     double bc = 0.0, bd = 0.0;
     for (unsigned t = nb_off[i]; t < nb_off[i + 1]; ++t) {
         const unsigned j = nb[t];
-        // alpha in j's list (keys ascending)
-        unsigned lo = off[j], hi = off[j + 1];
+        // alpha in j's list (keys ascending).  Neighbours' lists are nearly
+        // the same, so the search starts at alpha's place in i's list,
+        // scaled to j's length, and gallops to a bracket before bisecting:
+        // the same lower bound as a plain bisection of the whole list, with
+        // a few nearby loads instead of ~log2(length) scattered ones.
+        const unsigned lj = off[j], nj = off[j + 1] - lj;
+        if (nj == 0) continue;
+        const uint64_t *kj = keys + lj;
+        unsigned g = ni > 0 ? (unsigned)(((uint64_t)rank * nj) / ni) : 0u;
+        g = g < nj ? g : nj - 1;
+        unsigned lo, hi;
+        if (kj[g] < key) {          // the lower bound is above g
+            lo = g + 1;
+            unsigned b = 1;
+            while (g + b < nj && kj[g + b] < key) {
+                lo = g + b + 1;
+                b <<= 1;
+            }
+            hi = g + b < nj ? g + b : nj;
+        } else {                    // the lower bound is at most g
+            hi = g;
+            unsigned b = 1;
+            while (b <= g && kj[g - b] >= key) {
+                hi = g - b;
+                b <<= 1;
+            }
+            lo = b <= g ? g - b + 1 : 0u;
+        }
         while (lo < hi) {
             const unsigned mid = (lo + hi) >> 1;
-            if (keys[mid] < key) lo = mid + 1;
+            if (kj[mid] < key) lo = mid + 1;
             else hi = mid;
         }
-        if (lo >= off[j + 1] || keys[lo] != key) continue;
+        if (lo >= nj || kj[lo] != key) continue;
+        lo += lj;
         const double y[3] = {xyz[j], xyz[n + j], xyz[2 * n + j]};
         const double dj = dist3(y, a);
         if (!(dj < di)) continue;
