@@ -5,7 +5,8 @@
 //   1. per-tile digit histogram (LDS atomics),
 //   2. exclusive scan of the digit-major [256][tiles] count table,
 //   3. stable scatter: ranks inside a wave come from 8 ballots that match
-//      equal digits; waves and rounds are ordered through LDS counters.
+//      equal digits; waves and rounds are ordered through LDS counters; the
+//      tile is staged in LDS in digit order and written out run by run.
 #include "internal.h"
 
 namespace start {
@@ -89,18 +90,31 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const uint64_t *ke
                                                               uint64_t *keys_out, unsigned *vals_out, int64_t n,
                                                               int shift, const unsigned *offsets, int64_t ntiles)
 {
-    __shared__ unsigned base[256];
+    __shared__ unsigned base[256];      // global start of each digit's run of this tile
+    __shared__ unsigned loc[256];       // start of each digit inside the tile
     __shared__ unsigned running[256];
     __shared__ unsigned wave_cnt[kWaves][256];
+    __shared__ unsigned scan_lds[kSortThreads];
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ unsigned sval[kSortTile];
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int w = t >> 6;
-    base[t] = offsets[(int64_t)t * ntiles + blockIdx.x];
+    const int64_t tile = blockIdx.x;
+    // the tile's count of digit t, from the scanned digit-major count table
+    const unsigned b0 = offsets[(int64_t)t * ntiles + tile];
+    unsigned b1;
+    if (tile + 1 < ntiles) b1 = offsets[(int64_t)t * ntiles + tile + 1];
+    else b1 = t + 1 < 256 ? offsets[(int64_t)(t + 1) * ntiles] : (unsigned)n;
+    base[t] = b0;
+    unsigned tile_total;
+    loc[t] = block_exclusive_scan(b1 - b0, scan_lds, &tile_total);
     running[t] = 0;
     for (int k = 0; k < kWaves; ++k) wave_cnt[k][t] = 0;
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+    const int64_t tile0 = tile * kSortTile;
+    // 1. stable rank of every item inside the tile, digit-major: staged in LDS
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t i = tile0 + (int64_t)r * kSortThreads + t;
         const bool valid = i < n;
@@ -123,9 +137,9 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const uint64_t *ke
         if (valid) {
             unsigned pre = running[d];
             for (int k = 0; k < w; ++k) pre += wave_cnt[k][d];
-            const unsigned dst = base[d] + pre + rank;
-            keys_out[dst] = key;
-            vals_out[dst] = val;
+            const unsigned at = loc[d] + pre + rank;
+            skey[at] = key;
+            sval[at] = val;
         }
         __syncthreads();
         unsigned add = 0;
@@ -135,6 +149,15 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter(const uint64_t *ke
         }
         running[t] += add;
         __syncthreads();
+    }
+    // 2. out in tile order: neighbouring threads write neighbouring places of
+    // one digit's run (coalesced), instead of up to 256 runs per wave
+    for (unsigned i = t; i < tile_total; i += kSortThreads) {
+        const uint64_t key = skey[i];
+        const unsigned d = (unsigned)(key >> shift) & 0xFFu;
+        const unsigned dst = base[d] + (i - loc[d]);
+        keys_out[dst] = key;
+        vals_out[dst] = sval[i];
     }
 }
 
