@@ -214,21 +214,31 @@ __global__ void __launch_bounds__(kThreads) gather_sources(int64_t n, const unsi
 
 // Bottom-up sums S = sum L_j r_j and L = sum L_j (eqs. 14-15) for the nodes of
 // one level; children are visited in depth-first order.
-__global__ void __launch_bounds__(kThreads) moments_level(int64_t m, int level, const int4 *geo, const int *skip,
-                                                          const int *first, const int *count,
-                                                          const double4 *src, double4 *msum)
+// One byte per node for the level passes: its level, or 0xFF for a leaf
+// (each pass then reads 1 byte per node instead of the 16-byte record).
+__global__ void __launch_bounds__(kThreads) node_levels(int64_t m, const int4 *geo, unsigned char *lvl)
 {
     const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (p >= m) return;
-    const int4 g = geo[p];
-    const int kind = g.w >> 8;
-    if (kind == kKindLeaf) {
+    const int w = geo[p].w;
+    lvl[p] = (w >> 8) == kKindLeaf ? (unsigned char)0xFF : (unsigned char)(w & 0xFF);
+}
+
+__global__ void __launch_bounds__(kThreads) moments_level(int64_t m, int level, const unsigned char *lvl,
+                                                          const int4 *geo, const int *skip, const int *first,
+                                                          const int *count, const double4 *src, double4 *msum)
+{
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= m) return;
+    const unsigned char lp = lvl[p];
+    if (lp == 0xFF) {
         if (level != 0) return;   // leaves are filled once, in the first launch
         const double4 s = src[first[p]];
         msum[p] = make_double4(s.w * s.x, s.w * s.y, s.w * s.z, s.w);
         return;
     }
-    if ((g.w & 0xFF) != kMaxLevel - level) return;
+    if ((int)lp != kMaxLevel - level) return;
+    const int kind = geo[p].w >> 8;
     double sx = 0.0, sy = 0.0, sz = 0.0, L = 0.0;
     if (kind == kKindBucket) {
         for (int q = first[p]; q < first[p] + count[p]; ++q) {
@@ -319,7 +329,7 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     size_t tmp_bytes = al(radix_temp_bytes(max_items)) + 6 * al(n * sizeof(int)) + 2 * al(n * sizeof(unsigned)) +
                        al((n + 1) * sizeof(unsigned)) + al(max_items * sizeof(uint64_t)) +
                        al(max_items * sizeof(unsigned)) + al(scan_temp_bytes(n + 1)) + al(max_items * sizeof(double4)) +
-                       256;
+                       al(max_items) + 256;
     char *tm = nullptr;
     if (dmalloc(c, (void **)&tm, tmp_bytes) != hipSuccess) {
         dfree(c, pm, persist);
@@ -340,6 +350,7 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     unsigned *item_code = (unsigned *)take(max_items * sizeof(unsigned));
     void *scan_tmp = take(scan_temp_bytes(n + 1));
     double4 *msum = (double4 *)take(max_items * sizeof(double4));
+    unsigned char *lvl = (unsigned char *)take(max_items);
     unsigned *counts_host_dev = (unsigned *)take(256);
 
     unsigned *bflags = c->d_flags + 1;   // build validation word (not the rate calls' one)
@@ -396,8 +407,10 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     exclusive_scan_u32(first_count, n + 1, scan_tmp, s);   // pos_start[i] = items with first < i
     fill_nodes<<<blocks_for(m), kThreads, 0, s>>>(ni, m, t->keys, t->perm, blo, bhi, bdelta, item_code, first_count,
                                                   t->geo, t->skip, t->first, t->count, t->ref);
+    node_levels<<<blocks_for(m), kThreads, 0, s>>>(m, t->geo, lvl);
     for (int lv = 0; lv <= kMaxLevel; ++lv)
-        moments_level<<<blocks_for(m), kThreads, 0, s>>>(m, lv, t->geo, t->skip, t->first, t->count, t->src, msum);
+        moments_level<<<blocks_for(m), kThreads, 0, s>>>(m, lv, lvl, t->geo, t->skip, t->first, t->count, t->src,
+                                                         msum);
     moments_finish<<<blocks_for(m), kThreads, 0, s>>>(m, t->geo, t->first, t->src, msum, t->mom);
     e = hipStreamSynchronize(s);
     dfree(c, tm, tmp_bytes);
