@@ -147,6 +147,9 @@ __device__ inline double sqrt_nr(double x)
 
 constexpr int kCellsZ = 4;   // cell centres per thread, consecutive along z
 
+enum ShepardMode { kGather = 0, kCountPairs = 1, kFillPairs = 2 };
+constexpr unsigned long long kMaxPairs = 1ull << 29;   // recorded pairs: at most 6 GiB
+
 // kCellsZ consecutive cell centres of one z row per thread: they share x and
 // y, so every particle is loaded once for all of them.  Per reach class, the
 // rows of cells within the class reach are scanned: a particle in cell
@@ -155,12 +158,23 @@ constexpr int kCellsZ = 4;   // cell centres per thread, consecutive along z
 // point lies within the reach; the row geometry runs in float on a widened
 // reach, so the stencil can only grow.  The support test itself is exact
 // (FP64), and every centre sums its particles in (class, row, binned) order.
+// kCountPairs counts the (centre, particle) pairs inside the support per
+// centre; kFillPairs also records them with their weights, in summation
+// order, and the weight sums (for refills with new n_HI at the same
+// positions, refill_pairs).  The pairs of 64 consecutive cells are stored
+// interleaved (pair q of the group's cell l at q * 64 + l, the group padded
+// to its longest list), so that a wave refilling those cells reads
+// consecutive addresses at every step.
+template <int MODE>
 __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double delta, int G, ReachClasses cls,
                                                            const unsigned *__restrict__ start,
                                                            const double4 *__restrict__ pos_h,
                                                            const double2 *__restrict__ kern,
                                                            const double *__restrict__ ns, double *val, float *valf,
-                                                           int sx, int sy)
+                                                           int sx, int sy, unsigned *__restrict__ pcount,
+                                                           const unsigned *__restrict__ pstart,
+                                                           unsigned *__restrict__ pidx, double *__restrict__ pw,
+                                                           double *__restrict__ pden)
 {
     const int GZ = (G + kCellsZ - 1) / kCellsZ;   // thread groups per z row
     const int64_t lin = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -169,13 +183,16 @@ __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double
     const int ia = (int)(lin / ((int64_t)G * GZ)), ib = (int)((lin / GZ) % G);
     const int ic0 = (int)(lin % GZ) * kCellsZ;
     const int nz = G - ic0 < kCellsZ ? G - ic0 : kCellsZ;
+    const int64_t cell0 = ((int64_t)ia * G + ib) * G + ic0;   // unpadded index of the first centre
     const double xc = box.lo[0] + ((double)ia + 0.5) * delta;
     const double yc = box.lo[1] + ((double)ib + 0.5) * delta;
     double zc[kCellsZ], num[kCellsZ], den[kCellsZ];
+    unsigned cnt[kCellsZ];
     for (int j = 0; j < kCellsZ; ++j) {
         zc[j] = box.lo[2] + ((double)(ic0 + j) + 0.5) * delta;
         num[j] = 0.0;
         den[j] = 0.0;
+        cnt[j] = 0u;
     }
     for (int k = 0; k < cls.K; ++k) {
         const unsigned *st = start + k * ncell;
@@ -201,6 +218,14 @@ __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double
                     const double dx = xc - p.x, dy = yc - p.y;
                     const double dxy2 = dx * dx + dy * dy, h2 = 4.0 * p.w * p.w;
                     if (!(dxy2 < h2)) continue;
+                    if (MODE == kCountPairs) {
+#pragma unroll
+                        for (int j = 0; j < kCellsZ; ++j) {
+                            const double dz = zc[j] - p.z;
+                            cnt[j] += (j < nz && dxy2 + dz * dz < h2) ? 1u : 0u;
+                        }
+                        continue;
+                    }
                     // the four centres without branches: a centre outside
                     // the support 2h (or past the row's end) adds 0
                     const double2 kk = kern[s];
@@ -209,20 +234,90 @@ __global__ void __launch_bounds__(kThreads) shepard_gather(start_box box, double
                     for (int j = 0; j < kCellsZ; ++j) {
                         const double dz = zc[j] - p.z;
                         const double r2 = dxy2 + dz * dz;
-                        const double w = (j < nz && r2 < h2) ? kernel_w(sqrt_nr(r2) * kk.x, kk.y) : 0.0;
+                        const bool in = j < nz && r2 < h2;
+                        const double w = in ? kernel_w(sqrt_nr(r2) * kk.x, kk.y) : 0.0;
                         num[j] = fma(nk, w, num[j]);
                         den[j] += w;
+                        if (MODE == kFillPairs && in) {
+                            // pair q of cell c: group c / 64, place q * 64 + c % 64
+                            const int64_t c = cell0 + j;
+                            const int64_t at = (int64_t)pstart[c >> 6] + (int64_t)cnt[j] * 64 + (c & 63);
+                            pidx[at] = s;
+                            pw[at] = w;
+                            ++cnt[j];
+                        }
                     }
                 }
             }
         }
     }
     for (int j = 0; j < nz; ++j) {
+        if (MODE == kCountPairs) {
+            pcount[cell0 + j] = cnt[j];
+            continue;
+        }
+        if (MODE == kFillPairs) pden[cell0 + j] = den[j];
         const double v = den[j] > 0.0 ? num[j] / den[j] : 0.0;
         const int64_t e = (int64_t)ia * sx + (int64_t)ib * sy + ic0 + j;
         val[e] = v;
         valf[e] = (float)v;
     }
+}
+
+// Sum of n counts into a 64-bit total (the count scan is 32-bit).
+__global__ void __launch_bounds__(kThreads) sum_counts(int64_t n, const unsigned *cnt, unsigned long long *total)
+{
+    __shared__ unsigned long long part[kThreads / 64];
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    unsigned long long v = i < n ? cnt[i] : 0ull;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kThreads / 64; ++w) t += part[w];
+        if (t) atomicAdd(total, t);
+    }
+}
+
+// The grid from the recorded pairs: the same sums in the same order as
+// shepard_gather, so the same values bit for bit, reading each cell's pairs
+// instead of searching the stencil.
+__global__ void __launch_bounds__(kThreads) refill_pairs(int G, const unsigned *__restrict__ pcount,
+                                                         const unsigned *__restrict__ gstart,
+                                                         const unsigned *__restrict__ pidx,
+                                                         const double *__restrict__ pw,
+                                                         const double *__restrict__ pden,
+                                                         const double *__restrict__ ns, double *val, float *valf,
+                                                         int sx, int sy)
+{
+    const int64_t lin = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (lin >= (int64_t)G * G * G) return;
+    const int ia = (int)(lin / ((int64_t)G * G)), ib = (int)((lin / G) % G), ic = (int)(lin % G);
+    const int64_t base = (int64_t)gstart[lin >> 6] + (lin & 63);
+    const unsigned nq = pcount[lin];
+    double num = 0.0;
+    for (unsigned q = 0; q < nq; ++q) {
+        const int64_t at = base + (int64_t)q * 64;
+        num = fma(ns[pidx[at]], pw[at], num);
+    }
+    const double den = pden[lin];
+    const double v = den > 0.0 ? num / den : 0.0;
+    const int64_t e = (int64_t)ia * sx + (int64_t)ib * sy + ic;
+    val[e] = v;
+    valf[e] = (float)v;
+}
+
+// Size of each group of 64 cells in the interleaved pair arrays: 64 times
+// its longest list.
+__global__ void __launch_bounds__(kThreads) group_sizes(int64_t ncell, int64_t ngroups, const unsigned *pcount,
+                                                        unsigned *gsize)
+{
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= ngroups) return;
+    unsigned m = 0;
+    for (int64_t c = g * 64; c < g * 64 + 64 && c < ncell; ++c) m = pcount[c] > m ? pcount[c] : m;
+    gsize[g] = 64u * m;
 }
 
 __global__ void __launch_bounds__(kThreads) unpad(int G, int sx, int sy, const double *val, double *out)
@@ -381,8 +476,12 @@ void free_bins(Ctx *c, GasBins *b)
 {
     dfree(c, b->mem, b->bytes);
     dfree(c, b->mem2, b->bytes2);
-    b->mem = b->mem2 = nullptr;
-    b->bytes = b->bytes2 = 0;
+    dfree(c, b->mem3, b->bytes3);
+    dfree(c, b->mem4, b->bytes4);
+    b->mem = b->mem2 = b->mem3 = b->mem4 = nullptr;
+    b->bytes = b->bytes2 = b->bytes3 = b->bytes4 = 0;
+    b->pcount = b->pstart = b->pidx = nullptr;
+    b->pw = b->pden = nullptr;
 }
 
 void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g)
@@ -394,9 +493,86 @@ void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g)
         return;
     }
     if (nhi) gather_values<<<blocks_for(b.n), kThreads, 0, s>>>(b.n, b.idx, nhi, b.ns);
+    if (b.pidx) {
+        const int64_t ncell = (int64_t)g->G * g->G * g->G;
+        refill_pairs<<<blocks_for(ncell), kThreads, 0, s>>>(g->G, b.pcount, b.pstart, b.pidx, b.pw, b.pden, b.ns,
+                                                            g->val, g->valf, g->sx, g->sy);
+        return;
+    }
     const int64_t groups = (int64_t)g->G * g->G * ((g->G + kCellsZ - 1) / kCellsZ);
-    shepard_gather<<<blocks_for(groups), kThreads, 0, s>>>(b.box, b.delta, b.G, b.cls, b.start, b.pos_h, b.kern,
-                                                            b.ns, g->val, g->valf, g->sx, g->sy);
+    shepard_gather<kGather><<<blocks_for(groups), kThreads, 0, s>>>(
+        b.box, b.delta, b.G, b.cls, b.start, b.pos_h, b.kern, b.ns, g->val, g->valf, g->sx, g->sy, nullptr, nullptr,
+        nullptr, nullptr, nullptr);
+}
+
+start_status record_pairs(Ctx *c, GasBins *b, Grid *g)
+{
+    if (b->n == 0 || b->pidx) return START_OK;
+    hipStream_t s = c->stream;
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const int64_t ncell = (int64_t)b->G * b->G * b->G;
+    const int64_t ngroups = (ncell + 63) / 64;
+    const int64_t groups = (int64_t)b->G * b->G * ((b->G + kCellsZ - 1) / kCellsZ);
+    // 1. pairs per centre, the padded group sizes and their starts
+    b->bytes3 = al(ncell * sizeof(unsigned)) + al((ngroups + 1) * sizeof(unsigned)) +
+                al(scan_temp_bytes(ngroups + 1)) + al(ncell * sizeof(double)) + 256;
+    if (dmalloc(c, (void **)&b->mem3, b->bytes3) != hipSuccess) {
+        b->mem3 = nullptr;
+        b->bytes3 = 0;
+        return START_ENOMEM;
+    }
+    char *q = b->mem3;
+    auto take = [&](size_t v) { char *r = q; q += al(v); return r; };
+    b->pcount = (unsigned *)take(ncell * sizeof(unsigned));
+    b->pstart = (unsigned *)take((ngroups + 1) * sizeof(unsigned));
+    void *scan_tmp = take(scan_temp_bytes(ngroups + 1));
+    b->pden = (double *)take(ncell * sizeof(double));
+    unsigned long long *d_total = (unsigned long long *)take(256);
+    auto drop = [&]() {
+        dfree(c, b->mem3, b->bytes3);
+        b->mem3 = nullptr;
+        b->bytes3 = 0;
+        b->pcount = b->pstart = nullptr;
+        b->pden = nullptr;
+    };
+    hipMemsetAsync(b->pstart + ngroups, 0, sizeof(unsigned), s);
+    hipMemsetAsync(d_total, 0, sizeof(unsigned long long), s);
+    shepard_gather<kCountPairs><<<blocks_for(groups), kThreads, 0, s>>>(
+        b->box, b->delta, b->G, b->cls, b->start, b->pos_h, b->kern, b->ns, nullptr, nullptr, 0, 0, b->pcount,
+        nullptr, nullptr, nullptr, nullptr);
+    group_sizes<<<blocks_for(ngroups), kThreads, 0, s>>>(ncell, ngroups, b->pcount, b->pstart);
+    sum_counts<<<blocks_for(ngroups), kThreads, 0, s>>>(ngroups, b->pstart, d_total);
+    unsigned long long total64 = 0;
+    hipMemcpyAsync(&total64, d_total, sizeof(total64), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        drop();
+        return START_EHIP;
+    }
+    // the starts are 32-bit, and the pairs (12 B each) must stay modest
+    if (total64 > kMaxPairs) {
+        drop();
+        return START_ENOMEM;
+    }
+    exclusive_scan_u32(b->pstart, ngroups + 1, scan_tmp, s);
+    // 2. the pairs themselves (particle, weight), with the weight sums
+    const size_t np = total64 > 0 ? (size_t)total64 : 1;
+    b->bytes4 = al(np * sizeof(unsigned)) + al(np * sizeof(double));
+    if (dmalloc(c, (void **)&b->mem4, b->bytes4) != hipSuccess) {
+        b->mem4 = nullptr;
+        b->bytes4 = 0;
+        hipStreamSynchronize(s);   // the scan may still run
+        drop();
+        return START_ENOMEM;
+    }
+    unsigned *pidx = (unsigned *)b->mem4;
+    b->pw = (double *)(b->mem4 + al(np * sizeof(unsigned)));
+    shepard_gather<kFillPairs><<<blocks_for(groups), kThreads, 0, s>>>(
+        b->box, b->delta, b->G, b->cls, b->start, b->pos_h, b->kern, b->ns, g->val, g->valf, g->sx, g->sy, nullptr,
+        b->pstart, pidx, b->pw, b->pden);
+    b->pidx = pidx;
+    b->n_pairs = (int64_t)total64;
+    if (hipStreamSynchronize(s) != hipSuccess) return START_EHIP;
+    return START_OK;
 }
 
 start_status alloc_grid(Ctx *c, const start_box &box, int grid_log2, Grid *g)

@@ -133,6 +133,17 @@ struct GasBins {
     double4 *pos_h = nullptr;  // binned (x, y, z, h)
     double2 *kern = nullptr;   // binned (1/h, 1/(pi h^3))
     double *ns = nullptr;      // binned n_HI
+    // optional (record_pairs): every (cell centre, particle) pair inside the
+    // support, in summation order, for refills at the same positions
+    char *mem3 = nullptr, *mem4 = nullptr;
+    size_t bytes3 = 0, bytes4 = 0;
+    unsigned *pcount = nullptr;  // pairs of each cell [G^3] (unpadded order)
+    unsigned *pstart = nullptr;  // first pair of each group of 64 cells [G^3 / 64 + 1]; a group's
+                                 // pairs are interleaved: pair q of its cell l at q * 64 + l
+    unsigned *pidx = nullptr;    // binned particle of each pair
+    double *pw = nullptr;        // kernel weight of each pair
+    double *pden = nullptr;      // weight sum of each cell
+    int64_t n_pairs = 0;
 };
 
 // ---- gas grid (grid.hip) ----
@@ -144,6 +155,10 @@ void free_bins(Ctx *c, GasBins *b);
 // Enqueues the grid values from the binned particles; nhi (particle order,
 // not validated) replaces the binned n_HI first when non-null.
 void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g);
+// Records the pairs (and fills g from the binned n_HI) so that later
+// fill_grid calls read them instead of searching the stencil; synchronises.
+// START_ENOMEM leaves the bins as they were (fill_grid then gathers).
+start_status record_pairs(Ctx *c, GasBins *b, Grid *g);
 
 // ---- memory helpers (count against the context budget) ----
 hipError_t dmalloc(Ctx *c, void **p, size_t bytes);
