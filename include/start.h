@@ -289,6 +289,15 @@ start_status start_diffuse_equilibrium(start_ctx *ctx, const start_box *box, int
  * are the same either way (bit for bit). */
 start_status start_set_graph_replay(start_ctx *ctx, int enable);
 
+/* Whether the equilibrium loops (start_ionization_equilibrium,
+ * start_diffuse_equilibrium) record, after their first iteration, every
+ * (grid cell, gas particle) pair inside the kernel support with its weight
+ * (12 bytes per pair, ~32 pairs per cell at one particle per cell) and
+ * refill the grid from them (default on), or search the stencil at every
+ * refill.  The grids, and so all results, are the same either way (bit for
+ * bit); the recording is skipped by itself when its memory is not there. */
+start_status start_set_grid_pairs(start_ctx *ctx, int enable);
+
 /* ---- transfer of recombination photons (section 4.1) ---- */
 
 /* Per particle, with n_e = n_p = (1 - x) n_H:

@@ -31,7 +31,8 @@ EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_s
            "start_rate_counters", "start_profile_enable", "start_profile_read", "start_equilibrium_update",
            "start_ionization_equilibrium", "start_recombination_emission", "start_total_ionization",
            "start_compute_dissociation_rates", "start_set_tile_targets", "start_autotune_rates",
-           "start_set_graph_replay", "start_compute_rates_upstream", "start_diffuse_equilibrium")
+           "start_set_graph_replay", "start_compute_rates_upstream", "start_diffuse_equilibrium",
+           "start_set_grid_pairs")
 
 
 class LibraryMissing(RuntimeError):
@@ -110,6 +111,7 @@ def lib():
         "start_compute_dissociation_rates": ([P, P, P, i64, P, P, d, C.c_int, P], C.c_int),
         "start_set_tile_targets": ([P, C.c_int], C.c_int),
         "start_set_graph_replay": ([P, C.c_int], C.c_int),
+        "start_set_grid_pairs": ([P, C.c_int], C.c_int),
         "start_diffuse_equilibrium": ([P, P, i64, P, P, P, P, i64, P, P, C.c_int, d, d, d, d, C.c_int, C.c_int, d,
                                        P, P, P, P], C.c_int),
         "start_compute_rates_upstream": ([P, P, P, i64, P, P, P, P, d, d, P, P, P, i64, P], C.c_int),
@@ -407,6 +409,11 @@ class Context:
         """Replay the equilibrium iterations from a captured HIP graph (default)
         or launch them one by one."""
         self._check(lib().start_set_graph_replay(self._h, 1 if enable else 0), "start_set_graph_replay")
+
+    def set_grid_pairs(self, enable: bool):
+        """Refill the equilibrium loops' grids from recorded (cell, particle)
+        pairs (default) or search the stencil at every refill."""
+        self._check(lib().start_set_grid_pairs(self._h, 1 if enable else 0), "start_set_grid_pairs")
 
     def set_tile_targets(self, tile_targets: int):
         """Targets per wavefront of the rate kernels (1..64), or 0 for the

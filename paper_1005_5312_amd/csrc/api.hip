@@ -895,7 +895,7 @@ start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree
             drop_graph();
             return cleanup(st);
         }
-        if (it == 1) {
+        if (it == 1 && c.grid_pairs) {
             // later refills read the recorded (centre, particle) pairs; without
             // the memory for them they search the stencil as before
             const start_status pst = record_pairs(&c, &bins, &grid);
@@ -1023,7 +1023,7 @@ start_status start_diffuse_equilibrium(start_ctx *ctx, const start_box *box, int
         if (e != hipSuccess) return done(fail(ctx, START_EHIP, hipGetErrorString(e)));
         st = start_synchronize(ctx);
         if (st) return done(st);
-        if (it == 1) {
+        if (it == 1 && c.grid_pairs) {
             const start_status pst = record_pairs(&c, &bins, &grid);   // as in the on-the-spot loop
             if (pst != START_OK && pst != START_ENOMEM) return done(fail(ctx, pst, "grid pair recording failed"));
         }
@@ -1040,6 +1040,13 @@ start_status start_set_graph_replay(start_ctx *ctx, int enable)
 {
     if (!ctx) return START_EINVAL;
     ctx->c.graphs = enable != 0;
+    return START_OK;
+}
+
+start_status start_set_grid_pairs(start_ctx *ctx, int enable)
+{
+    if (!ctx) return START_EINVAL;
+    ctx->c.grid_pairs = enable != 0;
     return START_OK;
 }
 

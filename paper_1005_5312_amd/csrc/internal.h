@@ -51,6 +51,8 @@ struct Ctx {
     // replay repeated kernel sequences (the equilibrium iterations) from a
     // captured HIP graph
     bool graphs = true;
+    // refill the equilibrium loops' grids from recorded (cell, particle) pairs
+    bool grid_pairs = true;
     // freed device blocks kept for reuse (dmalloc / dfree), at most
     // kPoolMaxBytes in total; guarded by mem_mu
     std::vector<std::pair<void *, size_t>> pool;

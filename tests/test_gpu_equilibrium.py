@@ -273,6 +273,33 @@ def test_graph_replay_equals_eager_loop(ctx, prec):
         assert np.array_equal(xa, xb) and np.array_equal(ga, gb), iters
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_recorded_pairs_equal_stencil_search(ctx, prec):
+    """Grids refilled from the recorded (cell, particle) pairs equal those of
+    the stencil search bit for bit: x, Gamma and the iteration count of the
+    loops agree exactly with the recording on and off, on the small medium,
+    the Stromgren sphere and with recombination photons."""
+    for name in ("small", "stromgren"):
+        w, nh, x0, theta = loop_case(name)
+        outs = {}
+        for pairs in (False, True):
+            ctx.set_grid_pairs(pairs)
+            outs[pairs] = gpu_loop(ctx, w, nh, x0, theta, prec, 6, 0.0)
+        ctx.set_grid_pairs(True)
+        (xa, ga, ia, ca), (xb, gb, ib, cb) = outs[False], outs[True]
+        assert ia == ib and ca == cb, name
+        assert np.array_equal(xa, xb) and np.array_equal(ga, gb), name
+    e = H.W.make_stromgren(n_gas=1 << 14, grid_log2=5)
+    outs = {}
+    for pairs in (False, True):
+        ctx.set_grid_pairs(pairs)
+        outs[pairs] = gpu_diffuse(ctx, e, prec, 5, 0.0)
+    ctx.set_grid_pairs(True)
+    (xa, ga, ia, ca), (xb, gb, ib, cb) = outs[False], outs[True]
+    assert ia == ib and ca == cb
+    assert np.array_equal(xa, xb) and np.array_equal(ga, gb)
+
+
 # --- equilibrium with the transfer of recombination photons ---------------
 
 ALPHA_A = 4.18e-13
