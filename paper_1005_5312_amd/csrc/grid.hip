@@ -45,6 +45,7 @@ __global__ void __launch_bounds__(kThreads) grid_keys(start_box box, double gs, 
     __syncthreads();
     const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     double reach = 0.0;
+    int bin = -1;   // reach bin of a valid particle
     if (k < n) {
         unsigned bad = 0;
         int c[3];
@@ -63,10 +64,22 @@ __global__ void __launch_bounds__(kThreads) grid_keys(start_box box, double gs, 
             atomicOr(flags, bad);
         } else {
             reach = 2.0 * hk;
-            atomicAdd(&lh[reach_bin(hk, gs)], 1u);
+            bin = reach_bin(hk, gs);
         }
         keys[k] = ((uint64_t)c[0] * G + c[1]) * G + c[2];
         idx[k] = (unsigned)k;
+    }
+    // histogram: one LDS atomic per distinct bin of the wave (most particles
+    // share one or two bins, and same-address atomics serialise)
+    for (;;) {
+        const uint64_t left = __ballot(bin >= 0);
+        if (!left) break;
+        const int b = __shfl(bin, __ffsll((unsigned long long)left) - 1, 64);
+        const uint64_t same = __ballot(bin == b);
+        if (bin == b) {
+            if ((__lane_id() == __ffsll((unsigned long long)same) - 1)) atomicAdd(&lh[b], (unsigned)__popcll(same));
+            bin = -1;
+        }
     }
     // largest reach of the block, one atomic per block (positive doubles
     // order like their bit patterns)
@@ -101,13 +114,24 @@ __global__ void __launch_bounds__(kThreads) cell_counts(const uint64_t *keys, in
     atomicAdd(&start[keys[k]], 1u);
 }
 
-__global__ void __launch_bounds__(kThreads) gather_particles(int64_t n, const unsigned *perm, const double *xyz,
-                                                             const double *h, const double *nhi, double4 *pos_h,
-                                                             double2 *kern, double *ns)
+__global__ void __launch_bounds__(kThreads) invert_perm(int64_t n, const unsigned *perm, unsigned *inv)
 {
     const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (k >= n) return;
-    const unsigned o = perm[k];
+    inv[perm[k]] = (unsigned)k;
+}
+
+// The binned particle arrays, written from the particles in input order
+// (reads in order, each particle's three records written to its binned
+// place; gathering through the permutation instead reads five scattered
+// doubles per particle).
+__global__ void __launch_bounds__(kThreads) scatter_particles(int64_t n, const unsigned *inv, const double *xyz,
+                                                              const double *h, const double *nhi, double4 *pos_h,
+                                                              double2 *kern, double *ns)
+{
+    const int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (o >= n) return;
+    const unsigned k = inv[o];
     const double hk = h[o];
     pos_h[k] = make_double4(xyz[o], xyz[n + o], xyz[2 * n + o], hk);
     // 1/h and the 3-D normalisation 1/(pi h^3) of the kernel, once per particle
@@ -468,7 +492,9 @@ start_status bin_gas(Ctx *c, const start_box &box, int64_t n, const double *xyz,
     hipMemsetAsync(b->start, 0, nstart * sizeof(unsigned), s);
     cell_counts<<<blocks_for(n), kThreads, 0, s>>>(keys, n, b->start);
     exclusive_scan_u32(b->start, nstart, scan_tmp, s);
-    gather_particles<<<blocks_for(n), kThreads, 0, s>>>(n, b->idx, xyz, h, nhi, b->pos_h, b->kern, b->ns);
+    unsigned *inv = (unsigned *)keys;   // the keys are no longer needed
+    invert_perm<<<blocks_for(n), kThreads, 0, s>>>(n, b->idx, inv);
+    scatter_particles<<<blocks_for(n), kThreads, 0, s>>>(n, inv, xyz, h, nhi, b->pos_h, b->kern, b->ns);
     return START_OK;
 }
 
