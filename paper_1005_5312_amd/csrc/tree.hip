@@ -203,13 +203,22 @@ __global__ void __launch_bounds__(kThreads) fill_nodes(int n, int64_t m, const u
     ref[p] = r;
 }
 
-__global__ void __launch_bounds__(kThreads) gather_sources(int64_t n, const unsigned *perm, const double *xyz,
-                                                           const double *lum, double4 *src)
+__global__ void __launch_bounds__(kThreads) invert_order(int64_t n, const unsigned *perm, unsigned *inv)
 {
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (j >= n) return;
-    const unsigned o = perm[j];
-    src[j] = make_double4(xyz[o], xyz[n + o], xyz[2 * n + o], lum[o]);
+    inv[perm[j]] = (unsigned)j;
+}
+
+// The sorted sources, written from the input in order through the inverse
+// permutation (a gather through the permutation reads four scattered
+// doubles per source).
+__global__ void __launch_bounds__(kThreads) scatter_sources(int64_t n, const unsigned *inv, const double *xyz,
+                                                            const double *lum, double4 *src)
+{
+    const int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (o >= n) return;
+    src[inv[o]] = make_double4(xyz[o], xyz[n + o], xyz[2 * n + o], lum[o]);
 }
 
 // Bottom-up sums S = sum L_j r_j and L = sum L_j (eqs. 14-15) for the nodes of
@@ -357,7 +366,8 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     hipMemsetAsync(bflags, 0, sizeof(unsigned), s);
     launch_keys(box, n, xyz, lum, t->keys, t->perm, bflags, s);
     radix_sort_pairs(t->keys, t->perm, n, 63, radix_tmp, s);
-    gather_sources<<<blocks_for(n), kThreads, 0, s>>>(n, t->perm, xyz, lum, t->src);
+    invert_order<<<blocks_for(n), kThreads, 0, s>>>(n, t->perm, pos_int);   // pos_int is free until the scans
+    scatter_sources<<<blocks_for(n), kThreads, 0, s>>>(n, pos_int, xyz, lum, t->src);
 
     unsigned n_int = 0, n_leaf = 0;
     if (n > 1) {
