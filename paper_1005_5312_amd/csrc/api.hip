@@ -895,7 +895,9 @@ start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree
             drop_graph();
             return cleanup(st);
         }
-        if (it == 1 && c.grid_pairs) {
+        double change;
+        std::memcpy(&change, &bits, sizeof(double));
+        if (it == 1 && it < max_iter && !(change <= tol) && c.grid_pairs) {
             // later refills read the recorded (centre, particle) pairs; without
             // the memory for them they search the stencil as before
             const start_status pst = record_pairs(&c, &bins, &grid);
@@ -904,8 +906,6 @@ start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree
                 return cleanup(fail(ctx, pst, "grid pair recording failed"));
             }
         }
-        double change;
-        std::memcpy(&change, &bits, sizeof(double));
         if (iterations) *iterations = it;
         if (last_change) *last_change = change;
         if (change <= tol) break;
@@ -1023,12 +1023,12 @@ start_status start_diffuse_equilibrium(start_ctx *ctx, const start_box *box, int
         if (e != hipSuccess) return done(fail(ctx, START_EHIP, hipGetErrorString(e)));
         st = start_synchronize(ctx);
         if (st) return done(st);
-        if (it == 1 && c.grid_pairs) {
+        double change;
+        std::memcpy(&change, &bits, sizeof(double));
+        if (it == 1 && it < max_iter && !(change <= tol) && c.grid_pairs) {
             const start_status pst = record_pairs(&c, &bins, &grid);   // as in the on-the-spot loop
             if (pst != START_OK && pst != START_ENOMEM) return done(fail(ctx, pst, "grid pair recording failed"));
         }
-        double change;
-        std::memcpy(&change, &bits, sizeof(double));
         if (iterations) *iterations = it;
         if (last_change) *last_change = change;
         if (change <= tol) break;
