@@ -9,7 +9,7 @@ marches that produces Gamma for every particle.  value = particles / step time.
 Also measured in the same run: the rate call alone with tree and grid
 resident (FP32C and FP64), the walk kernel's duration from HIP events on the
 library's stream (roofline against HBM bandwidth with the algorithmic byte
-model), and the CPU FP64 checker on a bounded sample (cpu_baseline).
+model), and the CPU FP64 oracle on a bounded sample (cpu_baseline).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload diffuse]
 """
@@ -84,7 +84,7 @@ def traffic_from_profiles(workload, prec, sha):
 
 
 def cpu_baseline(w, sample, seed=17):
-    """The CPU FP64 checker on this host: tree and grid built in full, rates
+    """The CPU FP64 oracle on this host: tree and grid built in full, rates
     on a seeded sample of targets, whole step extrapolated linearly in the
     number of targets."""
     from oracle import oracle as O
@@ -102,7 +102,7 @@ def cpu_baseline(w, sample, seed=17):
     t3 = time.perf_counter()
     step = (t1 - t0) + (t2 - t1) + (t3 - t2) * w.n_tgt / len(idx)
     return {"value": w.n_tgt / step, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 checker, {threads} threads: full tree ({t1 - t0:.2f} s) and grid ({t2 - t1:.2f} s), "
+            "sample": f"FP64 oracle, {threads} threads: full tree ({t1 - t0:.2f} s) and grid ({t2 - t1:.2f} s), "
                       f"rates for {len(idx)} of {w.n_tgt} targets ({t3 - t2:.2f} s); step time extrapolated "
                       f"to all targets = {step:.1f} s",
             "rates_only_evals_per_s": len(idx) / (t3 - t2)}

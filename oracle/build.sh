@@ -1,5 +1,5 @@
 #!/bin/sh
-# Builds the CPU checker library (test infrastructure only).
+# Builds the CPU oracle library (test infrastructure only).
 set -e
 cd "$(dirname "$0")"
 gcc -std=c11 -D_GNU_SOURCE -O2 -ffp-contract=off -fno-fast-math -fopenmp -fPIC -shared \

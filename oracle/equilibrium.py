@@ -1,8 +1,8 @@
-"""Photoionisation equilibrium on top of the rate checker.
+"""Photoionisation equilibrium on top of the rate oracle.
 
 TEST INFRASTRUCTURE ONLY: the plain CPU FP64 definition that the HIP
 library's equilibrium update and equilibrium loop are compared against.  It
-shares no code with the HIP library; it calls only the checker in oracle.py.
+shares no code with the HIP library; it calls only the oracle in oracle.py.
 
 Physics (pure hydrogen, static gas, fixed temperature):
 

@@ -1,4 +1,4 @@
-"""ctypes loader for the CPU FP64 checker (liboracle.so).
+"""ctypes loader for the CPU FP64 oracle (liboracle.so).
 
 TEST INFRASTRUCTURE ONLY: used by tests, the smoke check and the CPU-baseline
 leg of the benchmark to produce the values the HIP library must reproduce.

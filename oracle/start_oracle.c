@@ -1,6 +1,6 @@
 /*
  * start_oracle.c -- CPU FP64 reference for the photoionization-rate path of
- * START (Hasegawa & Umemura 2010).  TEST INFRASTRUCTURE ONLY: the checker the
+ * START (Hasegawa & Umemura 2010).  TEST INFRASTRUCTURE ONLY: the oracle the
  * HIP library is compared against.  It shares no code with that library.
  *
  * What it computes, in the paper's order:

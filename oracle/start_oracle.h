@@ -3,7 +3,7 @@
  * START (Hasegawa & Umemura 2010, "START: smoothed particle hydrodynamics
  * with tree-based accelerated radiative transfer", MNRAS 407, 2632).
  *
- * TEST INFRASTRUCTURE ONLY.  This is the checker that the HIP library is
+ * TEST INFRASTRUCTURE ONLY.  This is the oracle that the HIP library is
  * compared against.  It is plain, slow and written to be read against the
  * paper: recursive geometric subdivision of the source cube (section 2.2.2),
  * the opening test of eqs. (12)-(13), virtual sources of eqs. (14)-(15),

@@ -93,7 +93,7 @@ struct Item {
 
 // Eq. (12): l^2 <= theta^2 d^2 in normalised units, d the distance to the
 // closest point of the cube [c 2^-n, (c+1) 2^-n].  Written as the same FP64
-// operations as the checker (explicit fma, no contraction) so that the lists
+// operations as the oracle (explicit fma, no contraction) so that the lists
 // agree bit for bit.
 __device__ inline bool accept(const int4 g, const double u[3], double theta2)
 {

@@ -3,7 +3,7 @@
 
 This module only draws input data: particle and source positions, smoothing
 lengths, neutral-hydrogen densities and source photon rates.  It holds none of
-the rate computation, so the HIP path and the CPU checker can both consume it.
+the rate computation, so the HIP path and the CPU oracle can both consume it.
 
 All arrays are float64, positions in structure-of-arrays layout ``[3, N]``,
 lengths in kpc with ``length_unit_cm`` converting to cm.

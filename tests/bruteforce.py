@@ -1,6 +1,6 @@
 """Independent brute-force evaluations for tiny inputs (test infrastructure).
 
-These do not share code or algorithms with the checker in ``oracle/``:
+These do not share code or algorithms with the oracle in ``oracle/``:
 
 * cells of the source octree are found by grouping sources on
   floor(u 2^n) at every level n (no recursion);

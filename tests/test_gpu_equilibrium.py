@@ -1,5 +1,5 @@
 """GPU equilibrium update and equilibrium loop (through the C-ABI) against
-the CPU checker in oracle/equilibrium.py."""
+the CPU oracle in oracle/equilibrium.py."""
 import numpy as np
 import pytest
 
@@ -142,7 +142,7 @@ def test_loop_converges_like_oracle(ctx):
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
 def test_stromgren_sphere_full_size(ctx, prec):
     """Test 4 at 2^21 particles on a 128^3 grid: properties that hold at any
-    size (the checker cannot run this many iterations here): a converged
+    size (the oracle cannot run this many iterations here): a converged
     field, the 5.4 kpc radius of eq. (17) within 5%, photon balance within
     10%, ionised inside and neutral outside."""
     import time
@@ -229,7 +229,7 @@ def test_recombination_input_errors(ctx):
 def test_diffuse_k_ion_pipeline_matches_oracle(ctx, prec):
     """Every particle an emitter (eq. 19), Gamma from all other emitters
     through the tree (self excluded), plus k_self: k_ion of eq. (25) on a
-    partly ionised medium, against the checker."""
+    partly ionised medium, against the oracle."""
     w = H.W.make_small(seed=12, n_gas=4096, n_src=1)
     rng = np.random.default_rng(13)
     nh = np.full(w.n_gas, 1e-3) * np.exp(rng.standard_normal(w.n_gas) * 0.5)

@@ -1,5 +1,5 @@
 """GPU H2 photodissociation rates (Appendix B, through the C-ABI) against the
-checker's or_lw_rates: same lists and rays as the photoionisation rates, the
+oracle's or_lw_rates: same lists and rays as the photoionisation rates, the
 H2 column shielding by f_sh instead of exp(-tau)."""
 import numpy as np
 import pytest

@@ -1,5 +1,5 @@
 """GPU upstream-particle chain (section 2.2.1, through the C-ABI) against the
-checker's or_upstream_rates: the same upstream particle for every (particle,
+oracle's or_upstream_rates: the same upstream particle for every (particle,
 list entry) pair, bit for bit, and the same rates to the FP64 tolerance."""
 import numpy as np
 import pytest

@@ -1,4 +1,4 @@
-"""Pins of the equilibrium checker (oracle/equilibrium.py) against what the
+"""Pins of the equilibrium oracle (oracle/equilibrium.py) against what the
 mathematics and the paper fix: the closed-form root, its limits, the order
 property of the iteration, and the Stromgren radius of Test 4 (section 4.2.1,
 eq. 17: 5.4 kpc for 5e48 photons/s in n_H = 1e-3 cm^-3)."""

@@ -1,4 +1,4 @@
-"""Pins of the checker's H2 photodissociation rate (Appendix B): the
+"""Pins of the oracle's H2 photodissociation rate (Appendix B): the
 self-shielding function, one source in uniform H2 gas (closed form for any
 theta), the unshielded limit (pure inverse-square sum), and theta = 0 against
 an independent brute force with exact columns."""

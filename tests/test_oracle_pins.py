@@ -1,6 +1,6 @@
-"""Pins of the CPU checker against what the paper and the mathematics fix.
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
 
-Each test names the passage it pins.  None of them re-types the checker's own
+Each test names the passage it pins.  None of them re-types the oracle's own
 formulas: they use exact rational geometry, closed forms, printed numbers,
 invariances and an independent brute force (tests/bruteforce.py).
 """
@@ -43,7 +43,7 @@ def member_sets(tree_export):
 @pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (17, 2), (200, 3), (1000, 4)])
 def test_tree_cells_equal_level_groups(n, seed):
     """Section 2.2.2: cubes split into 8 until one source is left.  Every cell
-    of the checker is exactly a group of sources sharing floor(u 2^n) at its
+    of the oracle is exactly a group of sources sharing floor(u 2^n) at its
     level, and every such group exists."""
     rng = np.random.default_rng(seed)
     box = unit_box(6.6)

@@ -1,4 +1,4 @@
-"""Pins of the checker's upstream-particle chain (section 2.2.1, eqs. 8-9, on
+"""Pins of the oracle's upstream-particle chain (section 2.2.1, eqs. 8-9, on
 the lists of section 2.2.2): the chain telescopes to the exact column in
 uniform gas; the upstream particles equal an independent re-derivation from
 the definition; and the difference to the ray-integrated optical depths is
