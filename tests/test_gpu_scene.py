@@ -132,3 +132,27 @@ def test_scene_edge_cases(ctx, case):
         assert not b.any()
     for o in (t1, g1, t2, g2):
         o.free()
+
+
+def test_pooled_blocks_give_way_under_a_budget():
+    """Under an HBM budget that holds one scene and its rate call but not two,
+    scenes of alternating sizes build and run one after another: blocks kept
+    for reuse are handed back to the device when a request of another size
+    needs the room."""
+    from paper_1005_5312_amd import workloads as W
+    wa = W.make_small(seed=3, n_gas=4096, n_src=64)
+    wb = W.make_small(seed=4, n_gas=8192, n_src=256)
+    need = max(B.estimate_bytes(w.n_tgt, w.n_src, w.n_gas, w.grid_log2) for w in (wa, wb))
+    with B.Context(0, hbm_budget=int(need * 1.3)) as c:
+        ref = {}
+        for k in range(6):
+            w = (wa, wb)[k % 2]
+            box = H.box_of(w)
+            t, g = c.build_scene(box, dev(w.src_xyz), dev(w.src_lum), dev(w.gas_xyz), dev(w.gas_h),
+                                 dev(w.gas_nhi), w.grid_log2)
+            out = c.compute_rates(t, g, dev(w.tgt_xyz), None, 1.0, w.sigma, "fp32c").cpu().numpy()
+            if k < 2:
+                ref[k % 2] = out
+            assert np.array_equal(out, ref[k % 2])
+            t.free()
+            g.free()
