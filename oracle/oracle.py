@@ -49,6 +49,7 @@ def lib():
         L.or_tree_ncells.argtypes = [P]
         L.or_tree_ncells.restype = i64
         L.or_tree_export.argtypes = [P] * 9
+        L.or_tree_kernel_luminosity.argtypes = [P, P, P, C.c_int]
         L.or_normalise.argtypes = [P, P, P]
         L.or_accept.argtypes = [C.c_int32, P, P, C.c_double]
         L.or_interaction_lists.argtypes = [P, i64, P, P, C.c_double, P, P, i64]
@@ -123,6 +124,16 @@ class Tree:
                                     _p(out["member_off"]), _p(out["member_idx"])), "or_tree_export")
         out["member_idx"] = out["member_idx"][: self.n]
         return out
+
+    def kernel_luminosity(self, h, vol=None, form=1):
+        """Kernel-weighted cell luminosities (section 2.2.2, the two forms
+        beside eq. (14)) at each cell's centre of luminosity; form 1 is the
+        kernel-weighted mean, form 2 the volume-weighted SPH sum."""
+        self._kh = _f64(h)
+        self._kv = None if vol is None else _f64(vol)
+        _check(lib().or_tree_kernel_luminosity(self._h, _p(self._kh), _p(self._kv), int(form)),
+               "or_tree_kernel_luminosity")
+        return self
 
     def lists(self, tgt_xyz, self_src=None, theta=1.0, capacity=None):
         """Per-target interaction lists: (offsets[n_t+1], entries[n, 4])."""

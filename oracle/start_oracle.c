@@ -9,7 +9,8 @@
  *      where a cube with several sources is a bucket whose sources are used
  *      one by one;
  *   2. the virtual source of every cell: total luminosity, eq. (14), at the
- *      centre of luminosity, eq. (15);
+ *      centre of luminosity, eq. (15); optionally one of the two kernel-weighted
+ *      luminosities of section 2.2.2 instead of the total;
  *   3. for every target particle the cells that pass the opening test
  *      l^n / d^n <= theta (eq. 12) while their parent fails it (eq. 13), with d
  *      the distance to the closest point of the cell, found top-down;
@@ -475,6 +476,46 @@ static double dist3(const double a[3], const double *xyz, int64_t n, int64_t k)
 {
     double dx = a[0] - xyz[k], dy = a[1] - xyz[n + k], dz = a[2] - xyz[2 * n + k];
     return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+/* Kernel-weighted luminosity of every cell of two or more sources, the two
+ * SPH-kernel forms offered in section 2.2.2 beside the sum of eq. (14).  Both
+ * are evaluated at the cell's centre of luminosity r (eq. 15, which stays the
+ * virtual source's position) with each member's own smoothing length h_j:
+ *   form 1:  L = sum_j L_j W(|r - r_j|, h_j) / sum_j W(|r - r_j|, h_j),
+ *            0 when no member's kernel reaches r;
+ *   form 2:  L = sum_j (m_j / rho_j) L_j W(|r - r_j|, h_j),  vol[j] = m_j / rho_j.
+ * Sums run over the members in the cell's own order.  A single source keeps
+ * its own luminosity (it is used as itself), and the members' luminosities
+ * are not changed, so a second call gives the same cells. */
+int or_tree_kernel_luminosity(or_tree *t, const double *h, const double *vol, int form)
+{
+    if (!t || (form != 1 && form != 2)) return OR_EINVAL;
+    if (t->n > 0 && (!h || (form == 2 && !vol))) return OR_EINVAL;
+    for (int64_t j = 0; j < t->n; ++j) {
+        if (!isfinite(h[j]) || (form == 2 && !isfinite(vol[j]))) return OR_ENONFINITE;
+        if (!(h[j] > 0.0) || (form == 2 && vol[j] < 0.0)) return OR_EINVAL;
+    }
+    for (int64_t ci = 0; ci < t->ncells; ++ci) {
+        or_cell *c = &t->cells[ci];
+        if (c->count < 2) continue;
+        double num = 0.0, den = 0.0;
+        for (int64_t m = c->first; m < c->first + c->count; ++m) {
+            int64_t j = t->idx[m];
+            double w = or_kernel_w(dist3(c->com, t->x, t->n, j), h[j]);
+            if (form == 1) {
+                num += t->lum[j] * w;
+                den += w;
+            } else {
+                num += vol[j] * t->lum[j] * w;
+            }
+        }
+        if (form == 1)
+            c->lum = den > 0.0 ? num / den : 0.0;
+        else
+            c->lum = num;
+    }
+    return OR_OK;
 }
 
 static int cmp_i64(const void *a, const void *b)

@@ -61,6 +61,14 @@ int or_tree_export(const or_tree *t, int32_t *level, int64_t *coord, int64_t *co
                    int32_t *nchild, double *lum, double *com, int64_t *member_off,
                    int64_t *member_idx);
 
+/* Replaces the luminosity of every cell of >= 2 sources by a kernel-weighted
+ * one (section 2.2.2, the forms offered beside eq. (14)), evaluated at the
+ * cell's centre of luminosity r (eq. 15) with the members' smoothing lengths
+ * h[n] > 0: form 1 = sum L_j W_j / sum W_j (0 if every W_j = 0), form 2 =
+ * sum vol_j L_j W_j with vol[n] = m_j / rho_j >= 0, W_j = W(|r - r_j|, h_j).
+ * Single sources keep their own L; calling again gives the same cells. */
+int or_tree_kernel_luminosity(or_tree *t, const double *h, const double *vol, int form);
+
 /* Normalised position u = min((x - lo) / size, 1) as used for the tree. */
 void or_normalise(const or_box *box, const double x[3], double u[3]);
 
