@@ -102,6 +102,26 @@ start_status start_build_source_tree(start_ctx *ctx, const start_box *box, int64
                                      const double *src_lum, start_tree **out);
 start_status start_tree_free(start_ctx *ctx, start_tree *tree);
 
+/* Kernel-weighted luminosities of the virtual sources: the two SPH-kernel
+ * forms that section 2.2.2 offers beside the sum of eq. (14), the second
+ * suggested there for diffuse radiation where every particle emits.  For
+ * every cell of two or more sources, with r its centre of luminosity (eq. 15,
+ * still the virtual source's position) and W_j = W(|r - r_j|, h_j) the cubic
+ * spline of section 2.1 with the member's own smoothing length:
+ *   START_LUM_KERNEL_MEAN:   L = sum_j L_j W_j / sum_j W_j, 0 (the cell is
+ *                            left out) when no member's kernel reaches r;
+ *   START_LUM_KERNEL_VOLUME: L = sum_j V_j L_j W_j, V_j = m_j / rho_j.
+ * Single sources keep their own luminosity.  The sums start from the
+ * sources' own luminosities, so calling again gives the same tree and the
+ * last form wins; a rebuild restores eq. (14).  src_h [n_s] > 0 in the box's
+ * length units, src_vol [n_s] >= 0 in length units cubed (NULL allowed for
+ * the mean form); both device arrays in the order the sources were given.
+ * Synchronous: START_EINVAL for a bad form, a NULL array, h <= 0 or V < 0,
+ * START_ENONFINITE for NaN or Inf (the tree is then unchanged). */
+typedef enum { START_LUM_KERNEL_MEAN = 1, START_LUM_KERNEL_VOLUME = 2 } start_lum_form;
+start_status start_tree_kernel_luminosity(start_ctx *ctx, start_tree *tree, start_lum_form form, const double *src_h,
+                                          const double *src_vol);
+
 /* Neutral-hydrogen grid: G = 2^grid_log2 cells per axis (1 <= grid_log2 <= 10;
  * 0 picks G = 2^ceil(log2(n_gas^(1/3)))), value at each cell centre
  *   n_c = sum_k nhi_k W(|x_c - r_k|, h_k) / sum_k W(|x_c - r_k|, h_k),

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libstart.so")
 
 OK, EINVAL, ENOMEM, EHIP, EOUTOFBOX, ENONFINITE, EBUDGET, ENOTIMPL, ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FP64, FP32C = 0, 1
+LUM_KERNEL_MEAN, LUM_KERNEL_VOLUME = 1, 2
 STATUS_NAMES = {OK: "START_OK", EINVAL: "START_EINVAL", ENOMEM: "START_ENOMEM", EHIP: "START_EHIP",
                 EOUTOFBOX: "START_EOUTOFBOX", ENONFINITE: "START_ENONFINITE", EBUDGET: "START_EBUDGET",
                 ENOTIMPL: "START_ENOTIMPL", ECAPACITY: "START_ECAPACITY"}
@@ -32,7 +33,7 @@ EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_s
            "start_ionization_equilibrium", "start_recombination_emission", "start_total_ionization",
            "start_compute_dissociation_rates", "start_set_tile_targets", "start_autotune_rates",
            "start_set_graph_replay", "start_compute_rates_upstream", "start_diffuse_equilibrium",
-           "start_set_grid_pairs")
+           "start_set_grid_pairs", "start_tree_kernel_luminosity")
 
 
 class LibraryMissing(RuntimeError):
@@ -90,6 +91,7 @@ def lib():
         "start_bytes_in_use": ([P], C.c_size_t),
         "start_build_source_tree": ([P, P, i64, P, P, P], C.c_int),
         "start_tree_free": ([P, P], C.c_int),
+        "start_tree_kernel_luminosity": ([P, P, C.c_int, P, P], C.c_int),
         "start_build_gas_grid": ([P, P, i64, P, P, P, C.c_int, P], C.c_int),
         "start_build_scene": ([P, P, i64, P, P, i64, P, P, P, C.c_int, P, P], C.c_int),
         "start_grid_free": ([P, P], C.c_int),
@@ -239,6 +241,19 @@ class Context:
                     "start_build_source_tree")
         self._leave(cur)
         return SourceTree(self, h, box, n)
+
+    def tree_kernel_luminosity(self, tree: SourceTree, form: int, src_h, src_vol=None) -> SourceTree:
+        """Kernel-weighted virtual-source luminosities (LUM_KERNEL_MEAN or
+        LUM_KERNEL_VOLUME) in place; src_h and src_vol in source input order."""
+        hh = _vec(src_h, self.device)
+        vv = None if src_vol is None else _vec(src_vol, self.device)
+        if hh.numel() != tree.n_src or (vv is not None and vv.numel() != tree.n_src):
+            raise ValueError("src_h / src_vol length does not match the tree's sources")
+        cur = self._enter(hh, vv)
+        self._check(lib().start_tree_kernel_luminosity(self._h, tree._h, int(form), _ptr(hh), _ptr(vv)),
+                    "start_tree_kernel_luminosity")
+        self._leave(cur)
+        return tree
 
     def build_gas_grid(self, box: Box, gas_xyz, gas_h, gas_nhi, grid_log2: int = 0) -> GasGrid:
         xyz = _xyz(gas_xyz, self.device)

@@ -370,6 +370,29 @@ start_status start_build_source_tree(start_ctx *ctx, const start_box *box, int64
     return START_OK;
 }
 
+start_status start_tree_kernel_luminosity(start_ctx *ctx, start_tree *tree, start_lum_form form, const double *src_h,
+                                          const double *src_vol)
+{
+    if (!ctx || !tree) return START_EINVAL;
+    if (form != START_LUM_KERNEL_MEAN && form != START_LUM_KERNEL_VOLUME)
+        return fail(ctx, START_EINVAL, "unknown luminosity form");
+    if (tree->t.n_src > 0 && (!src_h || (form == START_LUM_KERNEL_VOLUME && !src_vol)))
+        return fail(ctx, START_EINVAL, "smoothing length or volume array is NULL");
+    hipSetDevice(ctx->c.device);
+    start_status st = start_synchronize(ctx);
+    if (st) return st;
+    st = tree_kernel_luminosity(&ctx->c, &tree->t, src_h, src_vol, (int)form);
+    if (st == START_ENOMEM && ctx->c.budget) st = START_EBUDGET;
+    if (st) {
+        if (ctx->c.err.empty()) ctx->c.err = "kernel luminosity failed";
+        return st;
+    }
+    make_fp32_tree(&tree->t, ctx->c.stream);
+    hipError_t e = hipStreamSynchronize(ctx->c.stream);
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    return START_OK;
+}
+
 start_status start_tree_free(start_ctx *ctx, start_tree *tree)
 {
     if (!ctx) return START_EINVAL;

@@ -82,11 +82,14 @@ struct Tree {
     int *ref = nullptr;        // leaf: original source index
     double4 *mom = nullptr;    // (centre of luminosity x, y, z; luminosity)
     uint4 *momq = nullptr;     // FP32 path: centre as 32-bit fixed-point box
-                               // coordinates, L / L_root as float bits
+                               // coordinates, L / *lscale as float bits
     uint64_t *keys = nullptr;  // sorted source keys
     unsigned *perm = nullptr;  // sorted position -> original source index
     double4 *src = nullptr;    // sorted sources (x, y, z, L)
     uint4 *srcq = nullptr;     // same for the sorted sources (bucket members)
+    double *lscale = nullptr;  // L_root of the FP32 copies (device, one value > 0):
+                               // the root's luminosity, or after kernel weighting
+                               // the largest luminosity of any node or source
     size_t bytes = 0;
     Ctx *ctx = nullptr;
 };
@@ -280,5 +283,12 @@ void launch_parent_particle(Ctx *c, int64_t n_pairs, const int *parent, const un
 // ---- Morton keys (tree.hip) ----
 void launch_keys(const start_box &box, int64_t n, const double *xyz, const double *lum,
                  uint64_t *keys, unsigned *idx, unsigned *flags, hipStream_t s);
+
+// ---- kernel-weighted node luminosities (tree.hip) ----
+// Replaces the luminosity of every node of >= 2 sources by form 1 (kernel-
+// weighted mean) or form 2 (volume-weighted SPH sum) at its centre of
+// luminosity and sets t->lscale; the FP32 copies are left to the caller.
+// h, vol: device arrays in caller order.  Synchronises (validation).
+start_status tree_kernel_luminosity(Ctx *c, Tree *t, const double *h, const double *vol, int form);
 
 }  // namespace start

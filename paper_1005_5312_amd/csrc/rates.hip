@@ -50,6 +50,7 @@ struct Item {
     const int *ref;
     const double4 *mom;
     const uint4 *momq;
+    const double *lscale;   // luminosity unit of the FP32 copies (one value)
     const double4 *src;
     const uint4 *srcq;
     const unsigned *perm;
@@ -663,9 +664,8 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
         // terms are L / d^2 with d in cells: restore cm
         static_cast<double *>(P.gamma)[orig] = P.rate_scale * (double)acc / (P.cell_cm * P.cell_cm);
     } else {
-        // L' = L / L_root and lengths in cells: restore units in FP64
-        const double L0 = P.n_nodes > 0 ? P.mom[0].w : 0.0;   // empty tree: no arrays
-        const double Lref = L0 > 0.0 ? L0 : 1.0;
+        // L' = L / *lscale and lengths in cells: restore units in FP64
+        const double Lref = P.n_nodes > 0 ? *P.lscale : 1.0;   // empty tree: no arrays
         const double sum = (double)acc - (double)accc;
         static_cast<float *>(P.gamma)[orig] = (float)(P.rate_scale * sum * Lref / (P.cell_cm * P.cell_cm));
     }
@@ -758,23 +758,23 @@ __device__ inline unsigned fixed32(double x, double lo, double inv)
     return q >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned)q;
 }
 
-__global__ void __launch_bounds__(kThreads) make_fp32_nodes(int64_t m, const double4 *mom, start_box box,
-                                                            double inv, uint4 *momq)
+__global__ void __launch_bounds__(kThreads) make_fp32_nodes(int64_t m, const double4 *mom, const double *lscale,
+                                                            start_box box, double inv, uint4 *momq)
 {
     const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (p >= m) return;
-    const double Lref = mom[0].w > 0.0 ? mom[0].w : 1.0;
+    const double Lref = *lscale;
     const double4 v = mom[p];
     momq[p] = make_uint4(fixed32(v.x, box.lo[0], inv), fixed32(v.y, box.lo[1], inv), fixed32(v.z, box.lo[2], inv),
                          __float_as_uint((float)(v.w / Lref)));
 }
 
-__global__ void __launch_bounds__(kThreads) make_fp32_src(int64_t n, const double4 *src, const double4 *mom,
+__global__ void __launch_bounds__(kThreads) make_fp32_src(int64_t n, const double4 *src, const double *lscale,
                                                           start_box box, double inv, uint4 *srcq)
 {
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (j >= n) return;
-    const double Lref = mom[0].w > 0.0 ? mom[0].w : 1.0;
+    const double Lref = *lscale;
     const double4 v = src[j];
     srcq[j] = make_uint4(fixed32(v.x, box.lo[0], inv), fixed32(v.y, box.lo[1], inv), fixed32(v.z, box.lo[2], inv),
                          __float_as_uint((float)(v.w / Lref)));
@@ -788,8 +788,9 @@ void make_fp32_tree(Tree *t, hipStream_t s)
 {
     if (t->n_nodes == 0) return;
     const double inv = 1.0 / t->box.size;
-    make_fp32_nodes<<<blocks_for(t->n_nodes), kThreads, 0, s>>>(t->n_nodes, t->mom, t->box, inv, t->momq);
-    make_fp32_src<<<blocks_for(t->n_src), kThreads, 0, s>>>(t->n_src, t->src, t->mom, t->box, inv, t->srcq);
+    make_fp32_nodes<<<blocks_for(t->n_nodes), kThreads, 0, s>>>(t->n_nodes, t->mom, t->lscale, t->box, inv,
+                                                                 t->momq);
+    make_fp32_src<<<blocks_for(t->n_src), kThreads, 0, s>>>(t->n_src, t->src, t->lscale, t->box, inv, t->srcq);
 }
 
 // ------------------------------------------------------------------------
@@ -902,6 +903,7 @@ void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *s
         I.ref = t->ref;
         I.mom = t->mom;
         I.momq = t->momq;
+        I.lscale = t->lscale;
         I.src = t->src;
         I.srcq = t->srcq;
         I.perm = t->perm;

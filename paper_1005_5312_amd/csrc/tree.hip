@@ -18,6 +18,8 @@
 // A cell whose sources all sit in one sub-cube is represented by the deepest
 // cube with the same sources: the opening test is monotone from parent to
 // child, so testing that cube decides the whole chain.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace start {
@@ -288,9 +290,211 @@ __global__ void __launch_bounds__(kThreads) moments_finish(int64_t m, const int4
         mom[p] = make_double4(0.0, 0.0, 0.0, 0.0);
 }
 
+// The luminosity unit of the FP32 copies for a tree of eq. (14): the root's
+// luminosity, which no node or source exceeds (1 for a dark tree).
+__global__ void root_scale(const double4 *mom, double *lscale)
+{
+    if (threadIdx.x == 0) lscale[0] = mom[0].w > 0.0 ? mom[0].w : 1.0;
+}
+
+// ---- kernel-weighted node luminosities (section 2.2.2) -----------------
+// Each node of >= 2 sources gets, at its centre of luminosity r (eq. 15),
+//   form 1: L = sum_j L_j W_j / sum_j W_j (0 when every W_j = 0),
+//   form 2: L = sum_j V_j L_j W_j,
+// W_j = W(|r - r_j|, h_j), the cubic spline of section 2.1.  The members of
+// a node are a contiguous run of the sorted sources, so a node is split
+// into chunks of kLumChunk members, one wave per chunk (the root alone would
+// otherwise hold one wave for the whole source list); the chunks' partial
+// sums are added per node in chunk order, so the result does not depend on
+// the schedule.
+constexpr int kLumChunk = 1024;
+
+__device__ inline double spline_w(double d, double h)
+{
+    const double q = d / h;
+    const double a = fmax(2.0 - q, 0.0), b = fmax(1.0 - q, 0.0);
+    return (0.25 * a * a * a - b * b * b) / (M_PI * h * h * h);
+}
+
+// (h, V) of every source in sorted order, with the arguments' validation.
+__global__ void __launch_bounds__(kThreads) lum_gather(int64_t n, const unsigned *perm, const double *h,
+                                                       const double *vol, int form, double2 *hv, unsigned *flags)
+{
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n) return;
+    const unsigned j = perm[k];
+    const double hj = h[j];
+    const double vj = form == 2 ? vol[j] : 0.0;
+    unsigned bad = 0;
+    if (!isfinite(hj) || !isfinite(vj))
+        bad = kFlagNonFinite;
+    else if (!(hj > 0.0) || vj < 0.0)
+        bad = kFlagNegative;
+    if (bad) atomicOr(flags, bad);
+    hv[k] = make_double2(hj, vj);
+}
+
+// Chunks of every node (0 for single sources); element m is 0 so that the
+// exclusive scan ends with the total.
+__global__ void __launch_bounds__(kThreads) lum_chunks(int64_t m, const int4 *geo, const int *count,
+                                                       unsigned *nchunk)
+{
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p > m) return;
+    unsigned c = 0;
+    if (p < m && (geo[p].w >> 8) != kKindLeaf) c = (unsigned)((count[p] + kLumChunk - 1) / kLumChunk);
+    nchunk[p] = c;
+}
+
+__global__ void __launch_bounds__(kThreads) lum_owner(int64_t m, const unsigned *off, unsigned *owner)
+{
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= m) return;
+    for (unsigned i = off[p]; i < off[p + 1]; ++i) owner[i] = (unsigned)p;
+}
+
+__global__ void __launch_bounds__(kThreads) lum_partial(int64_t n_chunks, const unsigned *owner,
+                                                        const unsigned *off, const int *first, const int *count,
+                                                        const double4 *mom, const double4 *src, const double2 *hv,
+                                                        int form, double2 *part)
+{
+    const int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    if (t >= n_chunks) return;   // the whole wave
+    const unsigned p = owner[t];
+    const int64_t beg = (int64_t)first[p] + (t - (int64_t)off[p]) * kLumChunk;
+    const int64_t end = min((int64_t)first[p] + count[p], beg + kLumChunk);
+    const double4 r = mom[p];
+    double num = 0.0, den = 0.0;
+    for (int64_t k = beg + lane; k < end; k += 64) {
+        const double4 s = src[k];
+        const double2 q = hv[k];
+        const double dx = r.x - s.x, dy = r.y - s.y, dz = r.z - s.z;
+        const double w = spline_w(sqrt(dx * dx + dy * dy + dz * dz), q.x);
+        num += (form == 2 ? q.y * s.w : s.w) * w;
+        den += w;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        num += __shfl_xor(num, o, 64);
+        den += __shfl_xor(den, o, 64);
+    }
+    if (lane == 0) part[t] = make_double2(num, den);
+}
+
+__global__ void __launch_bounds__(kThreads) lum_finish(int64_t m, const unsigned *off, const double2 *part,
+                                                       int form, double4 *mom)
+{
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= m) return;
+    const unsigned a = off[p], b = off[p + 1];
+    if (a == b) return;   // a single source keeps its own luminosity
+    double num = 0.0, den = 0.0;
+    for (unsigned i = a; i < b; ++i) {
+        num += part[i].x;
+        den += part[i].y;
+    }
+    mom[p].w = form == 1 ? (den > 0.0 ? num / den : 0.0) : num;
+}
+
+// Largest luminosity of any node or source (as the bits of a non-negative
+// double, which order like the values), one atomic per block.
+__global__ void __launch_bounds__(kThreads) lum_max(int64_t m, const double4 *mom, int64_t n, const double4 *src,
+                                                    unsigned long long *best)
+{
+    __shared__ unsigned long long red[kThreads / 64];
+    unsigned long long v = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < m + n; i += (int64_t)gridDim.x * kThreads) {
+        const double L = i < m ? mom[i].w : src[i - m].w;
+        const unsigned long long b = (unsigned long long)__double_as_longlong(L);
+        v = b > v ? b : v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kThreads / 64; ++w) v = red[w] > v ? red[w] : v;
+        if (v) atomicMax(best, v);
+    }
+}
+
+__global__ void lum_scale(const unsigned long long *best, double *lscale)
+{
+    if (threadIdx.x == 0) lscale[0] = *best ? __longlong_as_double((long long)*best) : 1.0;
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
+
+start_status tree_kernel_luminosity(Ctx *c, Tree *t, const double *h, const double *vol, int form)
+{
+    const int64_t m = t->n_nodes, n = t->n_src;
+    if (n == 0) return START_OK;
+    hipStream_t s = c->stream;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_hv = al(n * sizeof(double2)), b_off = al((m + 1) * sizeof(unsigned));
+    const size_t bytes1 = b_hv + b_off + al(scan_temp_bytes(m + 1)) + 256;
+    char *t1 = nullptr;
+    if (dmalloc(c, (void **)&t1, bytes1) != hipSuccess) return START_ENOMEM;
+    double2 *hv = (double2 *)t1;
+    unsigned *off = (unsigned *)(t1 + b_hv);
+    void *scan_tmp = t1 + b_hv + b_off;
+    unsigned long long *best = (unsigned long long *)(t1 + bytes1 - 256);
+    unsigned *bflags = c->d_flags + 1;   // build validation word
+    hipMemsetAsync(bflags, 0, sizeof(unsigned), s);
+    hipMemsetAsync(best, 0, sizeof(*best), s);
+    lum_gather<<<blocks_for(n), kThreads, 0, s>>>(n, t->perm, h, vol, form, hv, bflags);
+    lum_chunks<<<blocks_for(m + 1), kThreads, 0, s>>>(m, t->geo, t->count, off);
+    exclusive_scan_u32(off, m + 1, scan_tmp, s);
+    unsigned flags = 0, n_chunks = 0;
+    hipMemcpyAsync(&flags, bflags, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(&n_chunks, off + m, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess || flags) {
+        dfree(c, t1, bytes1);
+        if (e != hipSuccess) {
+            c->err = hipGetErrorString(e);
+            return START_EHIP;
+        }
+        if (flags & kFlagNonFinite) {
+            c->err = "non-finite smoothing length or volume";
+            return START_ENONFINITE;
+        }
+        c->err = "smoothing length <= 0 or negative volume";
+        return START_EINVAL;
+    }
+    char *t2 = nullptr;
+    const size_t b_part = al((size_t)n_chunks * sizeof(double2));
+    const size_t bytes2 = b_part + al((size_t)n_chunks * sizeof(unsigned));
+    if (n_chunks > 0 && dmalloc(c, (void **)&t2, bytes2) != hipSuccess) {
+        dfree(c, t1, bytes1);
+        return START_ENOMEM;
+    }
+    if (n_chunks > 0) {
+        double2 *part = (double2 *)t2;
+        unsigned *owner = (unsigned *)(t2 + b_part);
+        lum_owner<<<blocks_for(m), kThreads, 0, s>>>(m, off, owner);
+        const unsigned waves_per_block = kThreads / 64;
+        lum_partial<<<(unsigned)((n_chunks + waves_per_block - 1) / waves_per_block), kThreads, 0, s>>>(
+            n_chunks, owner, off, t->first, t->count, t->mom, t->src, hv, form, part);
+        lum_finish<<<blocks_for(m), kThreads, 0, s>>>(m, off, part, form, t->mom);
+    }
+    const int64_t items = m + n;
+    const unsigned mb = (unsigned)std::min<int64_t>((items + kThreads - 1) / kThreads, 1024);
+    lum_max<<<mb, kThreads, 0, s>>>(m, t->mom, n, t->src, best);
+    lum_scale<<<1, 64, 0, s>>>(best, t->lscale);
+    e = hipStreamSynchronize(s);
+    if (t2) dfree(c, t2, bytes2);
+    dfree(c, t1, bytes1);
+    if (e != hipSuccess) {
+        c->err = hipGetErrorString(e);
+        return START_EHIP;
+    }
+    return START_OK;
+}
 
 void launch_keys(const start_box &box, int64_t n, const double *xyz, const double *lum, uint64_t *keys,
                  unsigned *idx, unsigned *flags, hipStream_t s)
@@ -316,7 +520,7 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     // persistent arrays
     size_t persist = al(n * sizeof(uint64_t)) + al(n * sizeof(unsigned)) + al(n * sizeof(double4)) +
                      al(n * sizeof(uint4)) + al(max_items * sizeof(int4)) + 4 * al(max_items * sizeof(int)) +
-                     al(max_items * sizeof(double4)) + al(max_items * sizeof(uint4));
+                     al(max_items * sizeof(double4)) + al(max_items * sizeof(uint4)) + al(sizeof(double));
     char *pm = nullptr;
     if (dmalloc(c, (void **)&pm, persist) != hipSuccess) return START_ENOMEM;
     t->bytes = persist;
@@ -333,6 +537,7 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     t->ref = (int *)take(max_items * sizeof(int));
     t->mom = (double4 *)take(max_items * sizeof(double4));
     t->momq = (uint4 *)take(max_items * sizeof(uint4));
+    t->lscale = (double *)take(sizeof(double));
 
     // temporaries
     size_t tmp_bytes = al(radix_temp_bytes(max_items)) + 6 * al(n * sizeof(int)) + 2 * al(n * sizeof(unsigned)) +
@@ -422,6 +627,7 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
         moments_level<<<blocks_for(m), kThreads, 0, s>>>(m, lv, lvl, t->geo, t->skip, t->first, t->count, t->src,
                                                          msum);
     moments_finish<<<blocks_for(m), kThreads, 0, s>>>(m, t->geo, t->first, t->src, msum, t->mom);
+    root_scale<<<1, 64, 0, s>>>(t->mom, t->lscale);
     e = hipStreamSynchronize(s);
     dfree(c, tm, tmp_bytes);
     (void)counts_host_dev;

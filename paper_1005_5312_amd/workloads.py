@@ -232,6 +232,16 @@ MAKERS = {"small": make_small, "clumpy": make_clumpy, "diffuse": make_diffuse,
           "shadow": make_shadow, "lw": make_lw}
 
 
+def source_kernel_inputs(w: Workload):
+    """Smoothing lengths and volumes m/rho of the sources, for the kernel-
+    weighted cell luminosities: h from the sources' own 32nd neighbour (as
+    for the gas), and the volume of a uniform medium holding N_NEIGHBOURS
+    particles in the sphere of radius 2h, (4 pi / 3) (2h)^3 / N_NEIGHBOURS."""
+    h = smoothing_lengths(w.src_xyz)
+    vol = (4.0 * math.pi / 3.0) * (2.0 * h) ** 3 / N_NEIGHBOURS
+    return np.ascontiguousarray(h), np.ascontiguousarray(vol)
+
+
 def make(name: str, **kw) -> Workload:
     return MAKERS[name](**kw)
 
