@@ -463,6 +463,57 @@ def tree_error_bench(ctx, w, tree, grid, n_sample=1024, seed=23):
             "fp32c_theta1_vs_theta0": _rel_stats(g32, g0)}
 
 
+def kernel_lum_bench(ctx, w, grid, theta, reps=3):
+    """Kernel-weighted virtual-source luminosities (section 2.2.2, both SPH
+    forms) on the benchmark tree: the call's wall time (synchronous: gather
+    and validation, per-node chunk sums, FP32 copies), the member visits it
+    makes (sum of the counts of the nodes of >= 2 sources), and the FP32C
+    rate call on the weighted tree beside the plain one."""
+    import torch
+    from paper_1005_5312_amd import Box, LUM_KERNEL_MEAN, LUM_KERNEL_VOLUME, workloads as W
+    dev = torch.device("cuda", 0)
+    h, vol = W.source_kernel_inputs(w)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    sx, sl, hh, vv = d(w.src_xyz), d(w.src_lum), d(h), d(vol)
+    tgt = d(w.tgt_xyz)
+    ss = d(w.self_src) if w.self_src is not None else None
+    box = Box(tuple(float(v) for v in w.box_lo), float(w.box_size), float(w.length_unit_cm))
+    out = {"n_sources": w.n_src}
+    plain = ctx.build_source_tree(box, sx, sl)
+    g0 = ctx.compute_rates(plain, grid, tgt, ss, theta, w.sigma, prec="fp32c")
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g0 = ctx.compute_rates(plain, grid, tgt, ss, theta, w.sigma, prec="fp32c")
+    ctx.synchronize()
+    out["rates_plain_ms"] = (time.perf_counter() - t0) * 1e3 / reps
+    e = ctx.tree_export(plain)
+    kind = e["geo"][:, 3] >> 8
+    out["member_visits"] = int(e["link"][kind != 2, 2].sum())
+    g0 = g0.double().cpu().numpy()
+    plain.free()
+    for form, name in ((LUM_KERNEL_MEAN, "mean"), (LUM_KERNEL_VOLUME, "volume")):
+        tree = ctx.build_source_tree(box, sx, sl)
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            ctx.tree_kernel_luminosity(tree, form, hh, vv)
+            best = min(best, (time.perf_counter() - t0) * 1e3)
+        g = ctx.compute_rates(tree, grid, tgt, ss, theta, w.sigma, prec="fp32c")
+        ctx.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g = ctx.compute_rates(tree, grid, tgt, ss, theta, w.sigma, prec="fp32c")
+        ctx.synchronize()
+        rms = (time.perf_counter() - t0) * 1e3 / reps
+        g = g.double().cpu().numpy()
+        ok = g0 > 0
+        out[name] = {"call_ms": best, "member_visits_per_s": out["member_visits"] / (best * 1e-3),
+                     "rates_ms": rms, "median_gamma_ratio_to_eq14": float(np.median(g[ok] / g0[ok]))}
+        tree.free()
+    return out
+
+
 def shadow_bench(reps=3):
     """The shadowing configuration (2^21 emitting particles, a 1e50/s star,
     16 dense neutral clumps, theta = 1, G = 128): rate-call time in both
@@ -725,6 +776,11 @@ def main():
         log("[bench] tree approximation against theta = 0 on sampled targets")
         tree_err = tree_error_bench(ctx, w, tree, grid)
 
+    klum_stats = None
+    if not args.rates_only:
+        log("[bench] kernel-weighted virtual-source luminosities")
+        klum_stats = kernel_lum_bench(ctx, w, grid, theta)
+
     shadow_stats = None
     if not args.rates_only and not args.no_shadow:
         log("[bench] shadowing configuration (2^21 particles)")
@@ -773,6 +829,7 @@ def main():
         "theta_sweep": sweep_stats,
         "tree_error": tree_err,
         "shadow": shadow_stats,
+        "kernel_luminosity": klum_stats,
         "k_ion_terms": kion_stats,
         "h2_dissociation": lw_stats,
         "upstream_chain": up_stats,
