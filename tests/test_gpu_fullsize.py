@@ -57,3 +57,40 @@ def test_fullsize_sampled(ctx, name, sample):
     nz = gw != 0
     assert np.array_equal(gg == 0, gw == 0)
     assert np.max(np.abs(gg[nz] / gw[nz] - 1)) <= 1e-12
+
+
+def test_fullsize_kernel_luminosity(ctx):
+    """The kernel-weighted luminosities (volume form) of every node of the
+    2^20 + 1-source benchmark tree against the oracle's cells, and the FP32C
+    rates on that tree on sampled targets, in the launch configuration the
+    benchmark times."""
+    w = H.workload("diffuse")
+    print(f"[case] full size kernel luminosity: {w.n_src} sources", flush=True)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    h, vol = H.W.source_kernel_inputs(w)
+    box = H.box_of(w)
+    tree = ctx.build_source_tree(box, d(w.src_xyz), d(w.src_lum))
+    ctx.tree_kernel_luminosity(tree, 2, d(h), d(vol))
+    grid = ctx.build_gas_grid(box, d(w.gas_xyz), d(w.gas_h), d(w.gas_nhi), w.grid_log2)
+    g32 = ctx.compute_rates(tree, grid, d(w.tgt_xyz), d(w.self_src), 1.0, w.sigma, "fp32c").cpu().numpy()
+    e = ctx.tree_export(tree)
+    obox = H.obox_of(w)
+    ot = O.Tree(obox, w.src_xyz, w.src_lum).kernel_luminosity(h, vol, 2)
+    oe = ot.export()
+    want = {(int(oe["level"][i]),) + tuple(int(v) for v in oe["coord"][i]): oe["lum"][i]
+            for i in range(len(oe["level"]))}
+    geo, mom = e["geo"], e["mom"]
+    multi = (geo[:, 3] >> 8) != 2
+    got = mom[multi, 3]
+    ref = np.array([want[(int(g[3] & 0xFF), int(g[0]), int(g[1]), int(g[2]))] for g in geo[multi]])
+    assert np.array_equal(got == 0, ref == 0)
+    nz = ref != 0
+    worst = float(np.max(np.abs(got[nz] / ref[nz] - 1)))
+    print(f"  {int(multi.sum())} cells, max rel {worst:.2e}", flush=True)
+    assert worst <= 1e-10
+    og = O.grid(obox, w.gas_xyz, w.gas_h, w.gas_nhi, w.grid_log2)
+    idx = H.W.sample_indices(w.n_tgt, 256, seed=103)
+    wr = O.rates(ot, w.grid_log2, og, w.tgt_xyz[:, idx], w.self_src[idx], 1.0, w.sigma)
+    r32 = H.rel_errors(g32[idx].astype(np.float64), wr)
+    print(f"  fp32c max rel {r32[0]:.3e} over {r32[2]} targets", flush=True)
+    assert r32[0] <= H.TOL_FP32C and r32[1] <= H.ABS_FLOOR
