@@ -89,7 +89,17 @@ def cpu_baseline(w, sample, seed=17):
     number of targets."""
     from oracle import oracle as O
     from paper_1005_5312_amd import workloads as W
-    threads = os.cpu_count() or 1
+    # the host cores this process may use (the box's CPU share), at most 16
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     box = O.make_box(w.box_lo, w.box_size, w.length_unit_cm)
     t0 = time.perf_counter()
     tree = O.Tree(box, w.src_xyz, w.src_lum)
@@ -105,7 +115,7 @@ def cpu_baseline(w, sample, seed=17):
             "sample": f"FP64 oracle, {threads} threads: full tree ({t1 - t0:.2f} s) and grid ({t2 - t1:.2f} s), "
                       f"rates for {len(idx)} of {w.n_tgt} targets ({t3 - t2:.2f} s); step time extrapolated "
                       f"to all targets = {step:.1f} s",
-            "rates_only_evals_per_s": len(idx) / (t3 - t2)}
+            "rates_only_evals_per_s": len(idx) / (t3 - t2), "cpu_model": model}
 
 
 def make_scene_pool(n, seed, lo_log2=14, hi_log2=17):
@@ -463,6 +473,28 @@ def tree_error_bench(ctx, w, tree, grid, n_sample=1024, seed=23):
             "fp32c_theta1_vs_theta0": _rel_stats(g32, g0)}
 
 
+def copy_bandwidth(reps=5):
+    """Achievable HBM bandwidth on this device: a plain 1 GiB device-to-device
+    copy (1 GiB read + 1 GiB written per copy), event-timed on the stream it
+    runs on."""
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2.0 * a.numel() * a.element_size() / (ms * 1e-3) / 1e9
+    del a, b
+    return gbs
+
+
 def kernel_lum_bench(ctx, w, grid, theta, reps=3):
     """Kernel-weighted virtual-source luminosities (section 2.2.2, both SPH
     forms) on the benchmark tree: the call's wall time (synchronous: gather
@@ -741,6 +773,11 @@ def main():
                 "kernel": "rates_kernel<FP32C> (tree walk + ray march + Gamma)",
                 "algorithmic_bytes_per_launch": alg[prec], "kernel_avg_ms": round(kern[prec]["avg_ms"], 4)}
     ach64 = alg["fp64"] / (kern["fp64"]["avg_ms"] * 1e-3) / 1e9
+    if not args.rates_only:
+        cbw = copy_bandwidth()
+        roofline["copy_GBs"] = round(cbw, 1)          # achievable: a plain device copy
+        roofline["frac_of_copy"] = round(ach / cbw, 4)
+        log(f"[bench] device copy {cbw:.0f} GB/s")
 
     serve_stats = batch_stats = None
     if not args.no_serve and not args.rates_only:
