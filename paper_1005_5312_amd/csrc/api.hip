@@ -638,13 +638,13 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     uint64_t *keys = (uint64_t *)alloc(Eb * sizeof(uint64_t));
     unsigned *owner = (unsigned *)alloc(Eb * sizeof(unsigned));
     int *par = (int *)alloc(Eb * sizeof(int));
-    int *par2 = (int *)alloc(Eb * sizeof(int));
     double *acc = (double *)alloc(Eb * sizeof(double));
-    double *acc2 = (double *)alloc(Eb * sizeof(double));
+    // two arrays of 16-byte (tau, parent) records for the pointer jumping
+    char *links = (char *)alloc(2 * Eb * 16);
     unsigned *roots = (unsigned *)alloc(Eb * sizeof(unsigned));
     unsigned *words = (unsigned *)alloc(256);   // [0] root count, [1] "more" flag
     unsigned *nbc = (unsigned *)alloc((size_t)(n + 1) * sizeof(unsigned));
-    if (!keys || !owner || !par || !par2 || !acc || !acc2 || !roots || !words || !nbc) return nomem();
+    if (!keys || !owner || !par || !links || !acc || !roots || !words || !nbc) return nomem();
     // 2. the lists as sorted keys, and the owner of every pair
     r.counts = nullptr;
     r.offsets = off64;
@@ -676,16 +676,20 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     // 5. roots: the column along the ray
     launch_upstream_roots(&c, &tree->t, &grid->g, n_roots, roots, keys, owner, gas_xyz, n, sigma_cm2, acc);
     // 6. sums along the chains by pointer jumping
-    for (int round = 0;; ++round) {
-        if (round > 40) return done(fail(ctx, START_EHIP, "upstream chains did not resolve"));
-        hipMemsetAsync(words + 1, 0, sizeof(unsigned), s);
-        launch_jump(&c, E, par, acc, par2, acc2, words + 1);
-        std::swap(par, par2);
-        std::swap(acc, acc2);
-        unsigned more = 0;
-        hipMemcpyAsync(&more, words + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s);
-        if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "pointer jumping failed"));
-        if (!more) break;
+    {
+        void *la = links, *lb = links + Eb * 16;
+        launch_pack_links(&c, E, par, acc, la);
+        for (int round = 0;; ++round) {
+            if (round > 40) return done(fail(ctx, START_EHIP, "upstream chains did not resolve"));
+            hipMemsetAsync(words + 1, 0, sizeof(unsigned), s);
+            launch_jump_links(&c, E, la, lb, words + 1);
+            std::swap(la, lb);
+            unsigned more = 0;
+            hipMemcpyAsync(&more, words + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+            if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "pointer jumping failed"));
+            if (!more) break;
+        }
+        launch_unpack_acc(&c, E, la, acc);
     }
     // 7. the rates
     launch_upstream_gamma(&c, &tree->t, n, gas_xyz, off, keys, acc, sigma_cm2, gamma_out);
@@ -698,9 +702,10 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
         if (!pp) return nomem();
         // the pair-level parent is lost to the jumping; search again
         hipMemsetAsync(words, 0, 256, s);
-        launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, off, keys, owner, nbc, nb, sigma_cm2, par2, acc2,
-                               roots, words);
-        launch_parent_particle(&c, E, par2, owner, pp);
+        // (into the link arrays, which are free again)
+        launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, off, keys, owner, nbc, nb, sigma_cm2,
+                               (int *)links, (double *)(links + Eb * 16), roots, words);
+        launch_parent_particle(&c, E, (const int *)links, owner, pp);
         if (E > 0) e = hipMemcpyAsync(parents_out, pp, (size_t)E * sizeof(int64_t), hipMemcpyDefault, s);
     }
     if (e != hipSuccess) return done(fail(ctx, START_EHIP, hipGetErrorString(e)));

@@ -274,8 +274,12 @@ void launch_upstream_parent(Ctx *c, const Tree *t, int64_t n_pairs, int64_t n, c
                             const unsigned *off, const uint64_t *keys, const unsigned *owner, const unsigned *nb_off,
                             const unsigned *nb, double sigma, int *parent, double *acc, unsigned *roots,
                             unsigned *n_roots);
-void launch_jump(Ctx *c, int64_t n_pairs, const int *par_in, const double *acc_in, int *par_out, double *acc_out,
-                 unsigned *more);
+// Pointer jumping on 16-byte (tau, parent) records: pack from the two
+// arrays, one round from `in` to `out` (sets *more when a parent still has
+// a parent), and the sums back into acc.
+void launch_pack_links(Ctx *c, int64_t n_pairs, const int *par, const double *acc, void *links);
+void launch_jump_links(Ctx *c, int64_t n_pairs, const void *in, void *out, unsigned *more);
+void launch_unpack_acc(Ctx *c, int64_t n_pairs, const void *links, double *acc);
 void launch_upstream_gamma(Ctx *c, const Tree *t, int64_t n, const double *xyz, const unsigned *off,
                            const uint64_t *keys, const double *tau, double sigma, double *gamma);
 void launch_parent_particle(Ctx *c, int64_t n_pairs, const int *parent, const unsigned *owner, int64_t *out);

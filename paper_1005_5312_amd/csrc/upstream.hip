@@ -158,23 +158,53 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
     }
 }
 
-// One round of pointer jumping: acc += acc[parent], parent = parent[parent].
-__global__ void __launch_bounds__(kThreads) jump(int64_t n_pairs, const int *__restrict__ par_in,
-                                                 const double *__restrict__ acc_in, int *__restrict__ par_out,
-                                                 double *__restrict__ acc_out, unsigned *__restrict__ more)
+// Pointer jumping on (tau, parent) records of 16 bytes: one round sets
+// acc += acc[parent] and parent = parent[parent], reading the parent's two
+// values from one cache line (the parents are scattered over the whole pair
+// array, so two separate arrays cost two lines per pair).
+struct __align__(16) Link {
+    double acc;
+    int par;
+    int pad;
+};
+
+__global__ void __launch_bounds__(kThreads) pack_links(int64_t n_pairs, const int *__restrict__ par,
+                                                       const double *__restrict__ acc, Link *__restrict__ out)
 {
     const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (p >= n_pairs) return;
-    const int q = par_in[p];
-    if (q < 0) {
-        par_out[p] = -1;
-        acc_out[p] = acc_in[p];
+    Link l;
+    l.acc = acc[p];
+    l.par = par[p];
+    l.pad = 0;
+    out[p] = l;
+}
+
+__global__ void __launch_bounds__(kThreads) jump_links(int64_t n_pairs, const Link *__restrict__ in,
+                                                       Link *__restrict__ out, unsigned *__restrict__ more)
+{
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= n_pairs) return;
+    const Link a = in[p];
+    if (a.par < 0) {
+        out[p] = a;
         return;
     }
-    acc_out[p] = acc_in[p] + acc_in[q];
-    const int r = par_in[q];
-    par_out[p] = r;
-    if (r >= 0) *more = 1u;
+    const Link b = in[a.par];
+    Link l;
+    l.acc = a.acc + b.acc;
+    l.par = b.par;
+    l.pad = 0;
+    out[p] = l;
+    if (b.par >= 0) *more = 1u;
+}
+
+__global__ void __launch_bounds__(kThreads) unpack_acc(int64_t n_pairs, const Link *__restrict__ in,
+                                                       double *__restrict__ acc)
+{
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= n_pairs) return;
+    acc[p] = in[p].acc;
 }
 
 // Gamma_i = sigma / (4 pi) sum_p L e^-tau / d_cm^2 over the pairs of i in list
@@ -265,10 +295,20 @@ void launch_upstream_parent(Ctx *c, const Tree *t, int64_t n_pairs, int64_t n, c
         parent, acc, roots, n_roots);
 }
 
-void launch_jump(Ctx *c, int64_t n_pairs, const int *par_in, const double *acc_in, int *par_out, double *acc_out,
-                 unsigned *more)
+void launch_pack_links(Ctx *c, int64_t n_pairs, const int *par, const double *acc, void *links)
 {
-    if (n_pairs > 0) jump<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, par_in, acc_in, par_out, acc_out, more);
+    if (n_pairs > 0) pack_links<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, par, acc, (Link *)links);
+}
+
+void launch_jump_links(Ctx *c, int64_t n_pairs, const void *in, void *out, unsigned *more)
+{
+    if (n_pairs > 0)
+        jump_links<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, (const Link *)in, (Link *)out, more);
+}
+
+void launch_unpack_acc(Ctx *c, int64_t n_pairs, const void *links, double *acc)
+{
+    if (n_pairs > 0) unpack_acc<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, (const Link *)links, acc);
 }
 
 void launch_upstream_gamma(Ctx *c, const Tree *t, int64_t n, const double *xyz, const unsigned *off,
