@@ -100,14 +100,30 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
     int best = -1;
     unsigned bj = 0;
     double bc = 0.0, bd = 0.0;
-    for (unsigned t = nb_off[i]; t < nb_off[i + 1]; ++t) {
-        const unsigned j = nb[t];
+    // the next neighbour's index and list bounds are loaded one iteration
+    // ahead, and its position before its search, so that the loads of
+    // successive neighbours overlap
+    const unsigned t0 = nb_off[i], t1 = nb_off[i + 1];
+    unsigned jn = 0, ljn = 0, ljn1 = 0;
+    if (t0 < t1) {
+        jn = nb[t0];
+        ljn = off[jn];
+        ljn1 = off[jn + 1];
+    }
+    for (unsigned t = t0; t < t1; ++t) {
+        const unsigned j = jn;
+        const unsigned lj = ljn, nj = ljn1 - ljn;
+        if (t + 1 < t1) {
+            jn = nb[t + 1];
+            ljn = off[jn];
+            ljn1 = off[jn + 1];
+        }
+        const double y[3] = {xyz[j], xyz[n + j], xyz[2 * n + j]};
         // alpha in j's list (keys ascending).  Neighbours' lists are nearly
         // the same, so the search starts at alpha's place in i's list,
         // scaled to j's length, and gallops to a bracket before bisecting:
         // the same lower bound as a plain bisection of the whole list, with
         // a few nearby loads instead of ~log2(length) scattered ones.
-        const unsigned lj = off[j], nj = off[j + 1] - lj;
         if (nj == 0) continue;
         const uint64_t *kj = keys + lj;
         unsigned g = ni > 0 ? (unsigned)(((uint64_t)rank * nj) / ni) : 0u;
@@ -137,7 +153,6 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
         }
         if (lo >= nj || kj[lo] != key) continue;
         lo += lj;
-        const double y[3] = {xyz[j], xyz[n + j], xyz[2 * n + j]};
         const double dj = dist3(y, a);
         if (!(dj < di)) continue;
         const double dot = (x[0] - a.x) * (y[0] - a.x) + (x[1] - a.y) * (y[1] - a.y) + (x[2] - a.z) * (y[2] - a.z);
