@@ -13,6 +13,9 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
 start_status build_grid(Ctx *c, const start_box &box, int64_t n, const double *xyz, const double *h,
                         const double *nhi, int grid_log2, Grid *g);
 void make_fp32_tree(Tree *t, hipStream_t s);
+size_t refit_bytes(const Tree *t);
+void refit_prepare(Ctx *c, const Tree *t, void *work);
+void refit_tree(Ctx *c, Tree *t, const double *lum, void *work);
 
 // Freed blocks stay with the context and are handed out again for a request
 // of the same size: the builds ask for the same sizes at every step, and a
@@ -1026,15 +1029,23 @@ start_status start_diffuse_equilibrium(start_ctx *ctx, const start_box *box, int
     have_grid = true;
     start_grid gh;
     start_tree th;
+    void *refit_work = nullptr;
     for (int it = 1; it <= max_iter; ++it) {
         // emitters: alpha_1 n_e n_p V of the current x (eq. 19)
         launch_recomb_terms(&c, n, n_h, x_hi, volume_cm3, sigma_cm2, alpha_1, lum, nullptr);
-        st = start_synchronize(ctx);
-        if (st) return done(st);
-        free_tree();
-        st = build_tree(&c, *box, ns, src, lum, &tree);
-        if (st) return done(st == START_ENOMEM && c.budget ? START_EBUDGET : st);
-        have_tree = true;
+        if (it == 1) {
+            st = start_synchronize(ctx);
+            if (st) return done(st);
+            st = build_tree(&c, *box, ns, src, lum, &tree);
+            if (st) return done(st == START_ENOMEM && c.budget ? START_EBUDGET : st);
+            have_tree = true;
+            refit_work = alloc(refit_bytes(&tree));
+            if (!refit_work) return nomem();
+            refit_prepare(&c, &tree, refit_work);
+        } else {
+            // the emitters do not move: the same tree with new luminosities
+            refit_tree(&c, &tree, lum, refit_work);
+        }
         make_fp32_tree(&tree, s);
         fill_grid(&c, bins, it == 1 ? nullptr : nhi, &grid);
         gh.g = grid;

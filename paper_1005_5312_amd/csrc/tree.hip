@@ -425,9 +425,60 @@ __global__ void lum_scale(const unsigned long long *best, double *lscale)
     if (threadIdx.x == 0) lscale[0] = *best ? __longlong_as_double((long long)*best) : 1.0;
 }
 
+// New luminosities of the same sources, in sorted order (for a refit inside
+// the equilibrium loop, whose emission they are); a negative or non-finite
+// value raises the equilibrium-input flag of the sticky word.
+__global__ void __launch_bounds__(kThreads) set_lum(int64_t n, const unsigned *perm, const double *lum,
+                                                    double4 *src, unsigned *flags)
+{
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n) return;
+    const double L = lum[perm[k]];
+    if (!(L >= 0.0) || !isfinite(L)) atomicOr(flags, kFlagEqInput);
+    src[k].w = L;
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
+
+// Work arrays of a refit: node levels (computed once) and the moment sums.
+size_t refit_bytes(const Tree *t)
+{
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return al((size_t)t->n_nodes * sizeof(double4)) + al((size_t)t->n_nodes);
+}
+
+void refit_prepare(Ctx *c, const Tree *t, void *work)
+{
+    const int64_t m = t->n_nodes;
+    if (m == 0) return;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    unsigned char *lvl = (unsigned char *)work + al((size_t)m * sizeof(double4));
+    node_levels<<<blocks_for(m), kThreads, 0, c->stream>>>(m, t->geo, lvl);
+}
+
+// The same tree for new luminosities of the same sources: keys, order and
+// nodes depend on the positions only, so only the sorted luminosities, the
+// moments of eqs. (14)-(15) (with the build's own kernels, so the result is
+// the rebuilt tree bit for bit) and the FP32 unit are redone.  Asynchronous;
+// bad luminosities are reported by the next start_synchronize (as an
+// equilibrium input).  `work` holds refit_bytes(t) after refit_prepare.
+void refit_tree(Ctx *c, Tree *t, const double *lum, void *work)
+{
+    const int64_t m = t->n_nodes, n = t->n_src;
+    if (n == 0) return;
+    hipStream_t s = c->stream;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    double4 *msum = (double4 *)work;
+    const unsigned char *lvl = (const unsigned char *)work + al((size_t)m * sizeof(double4));
+    set_lum<<<blocks_for(n), kThreads, 0, s>>>(n, t->perm, lum, t->src, c->d_flags);
+    for (int lv = 0; lv <= kMaxLevel; ++lv)
+        moments_level<<<blocks_for(m), kThreads, 0, s>>>(m, lv, lvl, t->geo, t->skip, t->first, t->count, t->src,
+                                                         msum);
+    moments_finish<<<blocks_for(m), kThreads, 0, s>>>(m, t->geo, t->first, t->src, msum, t->mom);
+    root_scale<<<1, 64, 0, s>>>(t->mom, t->lscale);
+}
 
 start_status tree_kernel_luminosity(Ctx *c, Tree *t, const double *h, const double *vol, int form)
 {
