@@ -286,7 +286,9 @@ start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree
 /* Photoionisation equilibrium with the transfer of recombination photons
  * (section 4.1) instead of the on-the-spot approximation: each iteration
  * makes every gas particle an emitter of alpha_1 n_e n_p V (eq. 19) next to
- * the n_star stars, builds the source tree of both, grids n_HI = x n_H,
+ * the n_star stars, builds the source tree of both (once: later iterations
+ * put the new luminosities into it and redo its moments, which gives the
+ * rebuilt tree bit for bit), grids n_HI = x n_H,
  * evaluates Gamma of every particle from every other emitter (self
  * excluded, k_other of eqs. 25-26) and solves
  *   x Gamma = alpha_eff n_H (1 - x)^2,  alpha_eff = alpha_A - alpha_1 (1 - exp(-tau_self)),
