@@ -119,6 +119,15 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
             ljn1 = off[jn + 1];
         }
         const double y[3] = {xyz[j], xyz[n + j], xyz[2 * n + j]};
+        // the geometric conditions first (strictly closer to the source, and
+        // closer to the ray than the best so far), so that only a candidate
+        // that would be taken is looked up: the same choice as testing them
+        // after the search, with far fewer searches
+        const double dj = dist3(y, a);
+        if (!(dj < di)) continue;
+        const double dot = (x[0] - a.x) * (y[0] - a.x) + (x[1] - a.y) * (y[1] - a.y) + (x[2] - a.z) * (y[2] - a.z);
+        const double c = dot / (di * dj);
+        if (!(best < 0 || c > bc || (c == bc && j < bj))) continue;
         // alpha in j's list (keys ascending).  Neighbours' lists are nearly
         // the same, so the search starts at alpha's place in i's list,
         // scaled to j's length, and gallops to a bracket before bisecting:
@@ -152,17 +161,10 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
             else hi = mid;
         }
         if (lo >= nj || kj[lo] != key) continue;
-        lo += lj;
-        const double dj = dist3(y, a);
-        if (!(dj < di)) continue;
-        const double dot = (x[0] - a.x) * (y[0] - a.x) + (x[1] - a.y) * (y[1] - a.y) + (x[2] - a.z) * (y[2] - a.z);
-        const double c = dot / (di * dj);
-        if (best < 0 || c > bc || (c == bc && j < bj)) {
-            best = (int)lo;
-            bj = j;
-            bc = c;
-            bd = dj;
-        }
+        best = (int)(lo + lj);
+        bj = j;
+        bc = c;
+        bd = dj;
     }
     parent[p] = best;
     if (best >= 0) {
