@@ -659,19 +659,20 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     st = bin_gas(&c, tree->t.box, n, gas_xyz, gas_h, gas_nhi, grid->g.grid_log2, &bins);
     if (st) return done(st == START_ENOMEM && c.budget ? START_EBUDGET : st);
     have_bins = true;
-    launch_neighbours(&c, bins, n, gas_xyz, gas_h, nbc, nullptr, nullptr);
+    launch_neighbours(&c, bins, n, gas_xyz, gas_h, nbc, nullptr, nullptr, nullptr);
     hipMemsetAsync(nbc + n, 0, sizeof(unsigned), s);
     exclusive_scan_u32(nbc, n + 1, scan_tmp, s);
     unsigned n_nb = 0;
     hipMemcpyAsync(&n_nb, nbc + n, sizeof(unsigned), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "neighbour count failed"));
     unsigned *nb = (unsigned *)alloc((size_t)(n_nb > 0 ? n_nb : 1) * sizeof(unsigned));
-    if (!nb) return nomem();
-    launch_neighbours(&c, bins, n, gas_xyz, gas_h, nullptr, nbc, nb);
+    unsigned *nbs = (unsigned *)alloc((size_t)(n_nb > 0 ? n_nb : 1) * sizeof(unsigned));
+    if (!nb || !nbs) return nomem();
+    launch_neighbours(&c, bins, n, gas_xyz, gas_h, nullptr, nbc, nb, nbs);
     // 4. upstream pair of every pair, its step, and the roots
     hipMemsetAsync(words, 0, 256, s);
-    launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, off, keys, owner, nbc, nb, sigma_cm2, par, acc, roots,
-                           words);
+    launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, off, keys, owner, nbc, nb, nbs, bins.pos_h, sigma_cm2,
+                           par, acc, roots, words);
     unsigned n_roots = 0;
     hipMemcpyAsync(&n_roots, words, sizeof(unsigned), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "upstream search failed"));
@@ -706,8 +707,8 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
         // the pair-level parent is lost to the jumping; search again
         hipMemsetAsync(words, 0, 256, s);
         // (into the link arrays, which are free again)
-        launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, off, keys, owner, nbc, nb, sigma_cm2,
-                               (int *)links, (double *)(links + Eb * 16), roots, words);
+        launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, off, keys, owner, nbc, nb, nbs, bins.pos_h,
+                               sigma_cm2, (int *)links, (double *)(links + Eb * 16), roots, words);
         launch_parent_particle(&c, E, (const int *)links, owner, pp);
         if (E > 0) e = hipMemcpyAsync(parents_out, pp, (size_t)E * sizeof(int64_t), hipMemcpyDefault, s);
     }

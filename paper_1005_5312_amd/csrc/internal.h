@@ -266,14 +266,15 @@ void launch_upstream_roots(Ctx *c, const Tree *t, const Grid *g, int64_t n_roots
 
 void launch_to_u32(Ctx *c, int64_t n, const int64_t *in, unsigned *out);
 void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out);
-// Neighbours within 2 h_i: counts (nb_off null) or the lists at nb_off.
+// Neighbours within 2 h_i: counts (nb_off null) or the lists at nb_off,
+// each neighbour's index in nb and its binned record's place in nbs.
 void launch_neighbours(Ctx *c, const GasBins &b, int64_t n, const double *xyz, const double *h, unsigned *count,
-                       const unsigned *nb_off, unsigned *nb);
+                       const unsigned *nb_off, unsigned *nb, unsigned *nbs);
 void launch_pair_owner(Ctx *c, int64_t n, const unsigned *off, unsigned *owner);
 void launch_upstream_parent(Ctx *c, const Tree *t, int64_t n_pairs, int64_t n, const double *xyz, const double *nhi,
                             const unsigned *off, const uint64_t *keys, const unsigned *owner, const unsigned *nb_off,
-                            const unsigned *nb, double sigma, int *parent, double *acc, unsigned *roots,
-                            unsigned *n_roots);
+                            const unsigned *nb, const unsigned *nbs, const double4 *pos_h, double sigma, int *parent,
+                            double *acc, unsigned *roots, unsigned *n_roots);
 // Pointer jumping on 16-byte (tau, parent) records: pack from the two
 // arrays, one round from `in` to `out` (sets *more when a parent still has
 // a parent), and the sums back into acc.

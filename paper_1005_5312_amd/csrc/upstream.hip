@@ -23,14 +23,16 @@ constexpr int kThreads = 256;
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
-// Neighbours within 2 h_i, found through the particles binned by grid cell.
+// Neighbours within 2 h_i, found through the particles binned by grid cell:
+// each neighbour's index and the place of its binned record.
 template <bool FILL>
 __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const double *__restrict__ xyz,
                                                        const double *__restrict__ h, start_box box, double delta,
                                                        int G, int K, const unsigned *__restrict__ start,
                                                        const double4 *__restrict__ pos_h,
                                                        const unsigned *__restrict__ idx, unsigned *__restrict__ count,
-                                                       const unsigned *__restrict__ nb_off, unsigned *__restrict__ nb)
+                                                       const unsigned *__restrict__ nb_off, unsigned *__restrict__ nb,
+                                                       unsigned *__restrict__ nbs)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
@@ -59,7 +61,10 @@ __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const double *
                 const double4 q = pos_h[s];
                 const double ex = q.x - x[0], ey = q.y - x[1], ez = q.z - x[2];
                 if (!(ex * ex + ey * ey + ez * ez <= r2)) continue;
-                if (FILL) nb[base + c] = j;
+                if (FILL) {
+                    nb[base + c] = j;
+                    nbs[base + c] = s;   // its binned record (x, y, z, h)
+                }
                 ++c;
             }
         }
@@ -85,7 +90,8 @@ __device__ inline double dist3(const double x[3], const double4 &a)
 __global__ void __launch_bounds__(kThreads) upstream_parent(
     int64_t n_pairs, int64_t n, const double *__restrict__ xyz, const double *__restrict__ nhi,
     const unsigned *__restrict__ off, const uint64_t *__restrict__ keys, const unsigned *__restrict__ owner,
-    const unsigned *__restrict__ nb_off, const unsigned *__restrict__ nb, const double4 *__restrict__ mom,
+    const unsigned *__restrict__ nb_off, const unsigned *__restrict__ nb, const unsigned *__restrict__ nbs,
+    const double4 *__restrict__ pos_h, const double4 *__restrict__ mom,
     const double4 *__restrict__ src, const int *__restrict__ first, double sigma, double ucm,
     int *__restrict__ parent, double *__restrict__ acc, unsigned *__restrict__ roots, unsigned *__restrict__ n_roots)
 {
@@ -100,25 +106,28 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
     int best = -1;
     unsigned bj = 0;
     double bc = 0.0, bd = 0.0;
-    // the next neighbour's index and list bounds are loaded one iteration
-    // ahead, and its position before its search, so that the loads of
-    // successive neighbours overlap
+    // the next neighbour's index, list bounds and position are loaded one
+    // iteration ahead, so that the loads of successive neighbours overlap;
+    // the position comes from the binned record (one line, not three)
     const unsigned t0 = nb_off[i], t1 = nb_off[i + 1];
     unsigned jn = 0, ljn = 0, ljn1 = 0;
+    double4 qn = make_double4(0.0, 0.0, 0.0, 0.0);
     if (t0 < t1) {
         jn = nb[t0];
+        qn = pos_h[nbs[t0]];
         ljn = off[jn];
         ljn1 = off[jn + 1];
     }
     for (unsigned t = t0; t < t1; ++t) {
         const unsigned j = jn;
         const unsigned lj = ljn, nj = ljn1 - ljn;
+        const double y[3] = {qn.x, qn.y, qn.z};
         if (t + 1 < t1) {
             jn = nb[t + 1];
+            qn = pos_h[nbs[t + 1]];
             ljn = off[jn];
             ljn1 = off[jn + 1];
         }
-        const double y[3] = {xyz[j], xyz[n + j], xyz[2 * n + j]};
         // the geometric conditions first (strictly closer to the source, and
         // closer to the ray than the best so far), so that only a candidate
         // that would be taken is looked up: the same choice as testing them
@@ -285,15 +294,15 @@ void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out)
 }
 
 void launch_neighbours(Ctx *c, const GasBins &b, int64_t n, const double *xyz, const double *h, unsigned *count,
-                       const unsigned *nb_off, unsigned *nb)
+                       const unsigned *nb_off, unsigned *nb, unsigned *nbs)
 {
     if (n <= 0) return;
     if (!nb_off)
         neighbours<false><<<blocks_for(n), kThreads, 0, c->stream>>>(n, xyz, h, b.box, b.delta, b.G, b.cls.K, b.start, b.pos_h,
-                                                                     b.idx, count, nullptr, nullptr);
+                                                                     b.idx, count, nullptr, nullptr, nullptr);
     else
         neighbours<true><<<blocks_for(n), kThreads, 0, c->stream>>>(n, xyz, h, b.box, b.delta, b.G, b.cls.K, b.start, b.pos_h,
-                                                                    b.idx, nullptr, nb_off, nb);
+                                                                    b.idx, nullptr, nb_off, nb, nbs);
 }
 
 void launch_pair_owner(Ctx *c, int64_t n, const unsigned *off, unsigned *owner)
@@ -303,13 +312,13 @@ void launch_pair_owner(Ctx *c, int64_t n, const unsigned *off, unsigned *owner)
 
 void launch_upstream_parent(Ctx *c, const Tree *t, int64_t n_pairs, int64_t n, const double *xyz, const double *nhi,
                             const unsigned *off, const uint64_t *keys, const unsigned *owner, const unsigned *nb_off,
-                            const unsigned *nb, double sigma, int *parent, double *acc, unsigned *roots,
-                            unsigned *n_roots)
+                            const unsigned *nb, const unsigned *nbs, const double4 *pos_h, double sigma, int *parent,
+                            double *acc, unsigned *roots, unsigned *n_roots)
 {
     if (n_pairs <= 0) return;
     upstream_parent<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(
-        n_pairs, n, xyz, nhi, off, keys, owner, nb_off, nb, t->mom, t->src, t->first, sigma, t->box.length_unit_cm,
-        parent, acc, roots, n_roots);
+        n_pairs, n, xyz, nhi, off, keys, owner, nb_off, nb, nbs, pos_h, t->mom, t->src, t->first, sigma,
+        t->box.length_unit_cm, parent, acc, roots, n_roots);
 }
 
 void launch_pack_links(Ctx *c, int64_t n_pairs, const int *par, const double *acc, void *links)
