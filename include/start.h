@@ -56,7 +56,8 @@ typedef enum {
     START_ENONFINITE = -5,   /* NaN or Inf in the input */
     START_EBUDGET = -6,      /* allocation would exceed the context's HBM budget */
     START_ENOTIMPL = -7,     /* not implemented */
-    START_ECAPACITY = -8     /* output buffer too small (required size is returned) */
+    START_ECAPACITY = -8     /* output buffer or fixed scratch too small (required size is returned
+                                where the call has an output for it) */
 } start_status;
 
 typedef enum {
@@ -154,6 +155,25 @@ int start_grid_size(const start_grid *grid);
 start_status start_compute_rates(start_ctx *ctx, const start_tree *tree, const start_grid *grid, int64_t n_t,
                                  const double *tgt_xyz, const int64_t *self_src, double theta_crit,
                                  double sigma_cm2, start_precision prec, void *gamma_out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * it): start_compute_rates with the same arguments and the same results (bit
+ * for bit: the same kernels), whose temporaries (target order, sorted
+ * positions, sort buffers, item and tile tables) live in a fixed 24 MiB
+ * device array that the library holds on every GPU it runs on until the
+ * process ends, instead of context scratch.  Its tables are written by a
+ * kernel, so the call allocates nothing, stages nothing on the host and
+ * never synchronises.  Limit: n_t <= 2^18 targets (any tile size);
+ * beyond it START_ECAPACITY, with nothing enqueued.  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (other streams, other
+ * contexts, other host threads) race and must be ordered by the caller.
+ * Asynchronous; device-side input errors are reported by the next
+ * start_synchronize, as for start_compute_rates. */
+start_status start_compute_rates_noalloc(start_ctx *ctx, const start_tree *tree, const start_grid *grid,
+                                         int64_t n_t, const double *tgt_xyz, const int64_t *self_src,
+                                         double theta_crit, double sigma_cm2, start_precision prec,
+                                         void *gamma_out);
 
 /* H2 photodissociation rate (s^-1) of each target by the Lyman-Werner band
  * (Appendix B, eq. B1, summed over the interaction list as in eq. A5):

@@ -33,7 +33,7 @@ EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_s
            "start_ionization_equilibrium", "start_recombination_emission", "start_total_ionization",
            "start_compute_dissociation_rates", "start_set_tile_targets", "start_autotune_rates",
            "start_set_graph_replay", "start_compute_rates_upstream", "start_diffuse_equilibrium",
-           "start_set_grid_pairs", "start_tree_kernel_luminosity")
+           "start_set_grid_pairs", "start_tree_kernel_luminosity", "start_compute_rates_noalloc")
 
 
 class LibraryMissing(RuntimeError):
@@ -97,6 +97,7 @@ def lib():
         "start_grid_free": ([P, P], C.c_int),
         "start_grid_size": ([P], C.c_int),
         "start_compute_rates": ([P, P, P, i64, P, P, d, d, C.c_int, P], C.c_int),
+        "start_compute_rates_noalloc": ([P, P, P, i64, P, P, d, d, C.c_int, P], C.c_int),
         "start_compute_rates_batched": ([P, C.c_int, P], C.c_int),
         "start_estimate_bytes": ([i64, i64, i64, C.c_int, C.c_int], C.c_size_t),
         "start_tree_export": ([P, P, P, P, P, P, P, P], C.c_int),
@@ -327,6 +328,30 @@ class Context:
         cur = self._enter(xyz, ss, out)
         self._check(lib().start_compute_rates(self._h, tree._h, grid._h, n, _ptr(xyz), _ptr(ss), float(theta),
                                               float(sigma), p, _ptr(out)), "start_compute_rates")
+        self._leave(cur)
+        return out
+
+    def compute_rates_noalloc(self, tree: SourceTree, grid: GasGrid, tgt_xyz, self_src=None, theta: float = 1.0,
+                              sigma: float = 6.3e-18, prec="fp32c", out=None):
+        """compute_rates through start_compute_rates_noalloc: the library's
+        fixed per-device scratch instead of context memory (at most 2^18
+        targets; calls on one GPU must not overlap).  Same results."""
+        import torch
+        p = _prec(prec)
+        xyz = _xyz(tgt_xyz, self.device)
+        n = xyz.shape[1]
+        ss = None if self_src is None else _vec(self_src, self.device, torch.int64)
+        if ss is not None and ss.numel() != n:
+            raise ValueError("self_src length does not match targets")
+        dt = torch.float64 if p == FP64 else torch.float32
+        if out is None:
+            out = torch.empty(n, dtype=dt, device=self.device)
+        elif out.dtype != dt or out.numel() != n or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype, size or layout")
+        cur = self._enter(xyz, ss, out)
+        self._check(lib().start_compute_rates_noalloc(self._h, tree._h, grid._h, n, _ptr(xyz), _ptr(ss),
+                                                      float(theta), float(sigma), p, _ptr(out)),
+                    "start_compute_rates_noalloc")
         self._leave(cur)
         return out
 

@@ -291,6 +291,9 @@ start_status start_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
         return START_ENOMEM;
     }
     hipMemset(ctx->c.d_flags, 0, 256);
+    // this device's address of the fixed scratch of start_compute_rates_noalloc
+    // (a failed lookup only disables that entry point, which then says so)
+    (void)noalloc_init(device);
     if (hipEventCreateWithFlags(&ctx->c.stage_ev, hipEventDisableTiming) != hipSuccess) {
         hipFree(ctx->c.d_flags);
         if (ctx->c.own_stream) hipStreamDestroy(ctx->c.stream);
@@ -561,6 +564,25 @@ start_status start_compute_rates(start_ctx *ctx, const start_tree *tree, const s
     RateSpec r = spec_of(tree, grid, n_t, tgt_xyz, self_src, theta_crit, sigma_cm2, prec);
     r.gamma = gamma_out;
     return enqueue(ctx, &r, 1, 0);
+}
+
+start_status start_compute_rates_noalloc(start_ctx *ctx, const start_tree *tree, const start_grid *grid,
+                                         int64_t n_t, const double *tgt_xyz, const int64_t *self_src,
+                                         double theta_crit, double sigma_cm2, start_precision prec, void *gamma_out)
+{
+    start_status st = check_rate_args(ctx, tree, grid, n_t, tgt_xyz, theta_crit, sigma_cm2, prec, true);
+    if (st) return st;
+    if (n_t == 0) return START_OK;
+    if (!gamma_out) return fail(ctx, START_EINVAL, "gamma_out is NULL");
+    hipSetDevice(ctx->c.device);
+    RateSpec r = spec_of(tree, grid, n_t, tgt_xyz, self_src, theta_crit, sigma_cm2, prec);
+    r.gamma = gamma_out;
+    const char *err = nullptr;
+    st = noalloc_rates(&ctx->c, r, tile_for(ctx->c, n_t, tree->t.n_src), &err);
+    if (st) return fail(ctx, st, err ? err : "start_compute_rates_noalloc failed");
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, START_EHIP, hipGetErrorString(e));
+    return START_OK;
 }
 
 start_status start_compute_dissociation_rates(start_ctx *ctx, const start_tree *tree, const start_grid *grid,

@@ -220,6 +220,18 @@ struct BatchLaunch {
 void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *scratch, hipEvent_t ev0,
                hipEvent_t ev1, BatchLaunch *launch = nullptr);
 void relaunch_batch(const BatchLaunch &b, hipStream_t s);
+// One rate problem (mode 0) on a caller-provided device scratch of at least
+// batch_scratch_bytes(r.n_t, 1, batch_tiles(&r, 1, tile)) bytes: its tables
+// are written by a kernel, so nothing is allocated or staged on the host.
+void run_single_fixed(Ctx *c, const RateSpec &r, int tile, void *scratch);
+
+// ---- fixed device scratch of start_compute_rates_noalloc (noalloc.hip) ----
+// Looks up this device's copy of the library's static scratch array (the
+// device must be current); returns false if the runtime refuses.
+bool noalloc_init(int device);
+// One rate call (mode 0) on that array: START_ECAPACITY (with *err) when the
+// call needs more than it holds, START_EHIP when it was not looked up.
+start_status noalloc_rates(Ctx *c, const RateSpec &r, int tile, const char **err);
 
 // ---- photoionisation equilibrium (equilibrium.hip) ----
 // x <- equilibrium neutral fraction for gamma (double or float by

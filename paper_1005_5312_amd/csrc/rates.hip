@@ -869,6 +869,114 @@ int64_t batch_tiles(const RateSpec *specs, int n, int tile)
     return t;
 }
 
+namespace {
+
+// The table entry of one rate problem; its targets are the run [off, off +
+// n_t) of the batch's sorted target arrays in bs.
+Item make_item(const RateSpec &r, const BatchScratch &bs, int64_t off)
+{
+    const Tree *t = r.tree;
+    const Grid *g = r.grid;
+    Item I;
+    memset(&I, 0, sizeof(I));
+    I.n_nodes = t->n_nodes;
+    I.n_src = t->n_src;
+    I.geo = t->geo;
+    I.skip = t->skip;
+    I.first = t->first;
+    I.count = t->count;
+    I.ref = t->ref;
+    I.mom = t->mom;
+    I.momq = t->momq;
+    I.lscale = t->lscale;
+    I.src = t->src;
+    I.srcq = t->srcq;
+    I.perm = t->perm;
+    if (g) {
+        I.grid = g->val;
+        I.gridf = g->valf;
+        I.G = g->G;
+        I.grid_log2 = g->grid_log2;
+        I.sx = g->sx;
+        I.sy = g->sy;
+    } else {
+        I.G = 1;
+        I.grid_log2 = 0;
+        I.sx = I.sy = 1;
+    }
+    I.frac_scale = ldexp(1.0, -(32 - I.grid_log2));
+    I.gs = (double)I.G / t->box.size;
+    for (int k = 0; k < 3; ++k) I.lo[k] = t->box.lo[k];
+    I.size = t->box.size;
+    I.inv_size = 1.0 / t->box.size;
+    I.unit_cm = t->box.length_unit_cm;
+    I.cell_cm = t->box.size / I.G * t->box.length_unit_cm;
+    I.theta2 = r.theta * r.theta;
+    I.sigma = r.sigma;
+    I.channel = r.channel;
+    I.col_scale = r.channel == 0 ? r.sigma * I.cell_cm : I.cell_cm * 1e-14;
+    I.rate_scale = (r.channel == 0 ? r.sigma : 1.13e8) / (4.0 * M_PI);
+    I.n_t = r.n_t;
+    I.tgt_xyz = r.tgt_xyz;
+    I.tgt = bs.tgt + off;
+    I.tgt_orig = bs.tgt_orig + off;
+    I.self_src = r.self_src;
+    I.gamma = r.gamma;
+    I.counts = r.counts;
+    I.offsets = r.offsets;
+    I.entries = r.entries;
+    I.stats = r.stats;
+    return I;
+}
+
+// Device part of a batch whose tables are in place: target keys, sort and
+// gather, then the kernels of the mode.
+void launch_staged(const BatchScratch &bs, int64_t N, int n, int64_t n_tiles, int64_t n64, int mode,
+                   unsigned *flags, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, BatchLaunch *launch)
+{
+    if (N == 0) return;
+    const unsigned nb = (unsigned)((N + kThreads - 1) / kThreads);
+    batch_keys<<<nb, kThreads, 0, s>>>(N, n, bs.offsets, bs.items, bs.keys, bs.vals, flags);
+    int bits = 30;
+    while ((1 << (bits - 30)) < n) ++bits;
+    radix_sort_pairs(bs.keys, bs.vals, N, bits, bs.radix_tmp, s);
+    batch_gather<<<nb, kThreads, 0, s>>>(N, bs.offsets, bs.items, bs.keys, bs.vals, bs.tgt, bs.tgt_orig);
+
+    if (mode == 2 || mode == 3 || mode == 4) {
+        const unsigned lb = (unsigned)((n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+        if (mode == 2) list_kernel<kCount><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
+        else if (mode == 3) list_kernel<kList><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
+        else list_kernel<kKeys><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
+        return;
+    }
+    BatchLaunch bl{bs.items, bs.tiles, n_tiles, n64, mode};
+    if (launch) *launch = bl;
+    if (ev0) hipEventRecord(ev0, s);
+    relaunch_batch(bl, s);
+    if (ev1) hipEventRecord(ev1, s);
+}
+
+static_assert(sizeof(Item) <= 1024, "the item table entry is passed as a kernel argument");
+
+// The tables of a one-item batch written on the device from the kernel
+// argument (no host staging): the item, its offsets (0, n_t) and its tiles.
+__global__ void __launch_bounds__(kThreads) single_tables(Item I, int tile, int64_t n_tiles, Item *items,
+                                                          int64_t *offsets, int4 *tiles)
+{
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k == 0) {
+        *items = I;
+        offsets[0] = 0;
+        offsets[1] = I.n_t;
+    }
+    if (k < n_tiles) {
+        const int64_t f = k * tile;
+        tiles[k] = make_int4(0, (int)f, (int)(I.n_t - f < tile ? I.n_t - f : tile), 0);
+    }
+}
+
+}  // namespace
+
 // Enqueues a batch (the scratch and the pinned staging area must be large
 // enough: batch_scratch_bytes / stage_bytes).  mode: 0 rates, 1 counters,
 // 2 list counts, 3 lists.  ev0/ev1 (may be null) bracket the rate kernels.
@@ -889,61 +997,9 @@ void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *s
     int4 *ht = (int4 *)(h + al256((size_t)n * sizeof(Item)) + al256((size_t)(n + 1) * sizeof(int64_t)));
     int64_t off = 0;
     for (int i = 0; i < n; ++i) {
-        const RateSpec &r = specs[i];
-        const Tree *t = r.tree;
-        const Grid *g = r.grid;
-        Item I;
-        memset(&I, 0, sizeof(I));
-        I.n_nodes = t->n_nodes;
-        I.n_src = t->n_src;
-        I.geo = t->geo;
-        I.skip = t->skip;
-        I.first = t->first;
-        I.count = t->count;
-        I.ref = t->ref;
-        I.mom = t->mom;
-        I.momq = t->momq;
-        I.lscale = t->lscale;
-        I.src = t->src;
-        I.srcq = t->srcq;
-        I.perm = t->perm;
-        if (g) {
-            I.grid = g->val;
-            I.gridf = g->valf;
-            I.G = g->G;
-            I.grid_log2 = g->grid_log2;
-            I.sx = g->sx;
-            I.sy = g->sy;
-        } else {
-            I.G = 1;
-            I.grid_log2 = 0;
-            I.sx = I.sy = 1;
-        }
-        I.frac_scale = ldexp(1.0, -(32 - I.grid_log2));
-        I.gs = (double)I.G / t->box.size;
-        for (int k = 0; k < 3; ++k) I.lo[k] = t->box.lo[k];
-        I.size = t->box.size;
-        I.inv_size = 1.0 / t->box.size;
-        I.unit_cm = t->box.length_unit_cm;
-        I.cell_cm = t->box.size / I.G * t->box.length_unit_cm;
-        I.theta2 = r.theta * r.theta;
-        I.sigma = r.sigma;
-        I.channel = r.channel;
-        I.col_scale = r.channel == 0 ? r.sigma * I.cell_cm : I.cell_cm * 1e-14;
-        I.rate_scale = (r.channel == 0 ? r.sigma : 1.13e8) / (4.0 * M_PI);
-        I.n_t = r.n_t;
-        I.tgt_xyz = r.tgt_xyz;
-        I.tgt = bs.tgt + off;
-        I.tgt_orig = bs.tgt_orig + off;
-        I.self_src = r.self_src;
-        I.gamma = r.gamma;
-        I.counts = r.counts;
-        I.offsets = r.offsets;
-        I.entries = r.entries;
-        I.stats = r.stats;
-        hi[i] = I;
+        hi[i] = make_item(specs[i], bs, off);
         ho[i] = off;
-        off += r.n_t;
+        off += specs[i].n_t;
     }
     ho[n] = off;
     int64_t t64 = 0;
@@ -958,27 +1014,19 @@ void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *s
         if (specs[i].prec == START_FP64) n64 += (specs[i].n_t + tile - 1) / tile;
     hipMemcpyAsync(bs.items, h, stage_bytes(n, n_tiles), hipMemcpyHostToDevice, s);
     hipEventRecord(c->stage_ev, s);
+    launch_staged(bs, N, n, n_tiles, n64, mode, c->d_flags, s, ev0, ev1, launch);
+}
 
-    if (N == 0) return;
-    const unsigned nb = (unsigned)((N + kThreads - 1) / kThreads);
-    batch_keys<<<nb, kThreads, 0, s>>>(N, n, bs.offsets, bs.items, bs.keys, bs.vals, c->d_flags);
-    int bits = 30;
-    while ((1 << (bits - 30)) < n) ++bits;
-    radix_sort_pairs(bs.keys, bs.vals, N, bits, bs.radix_tmp, s);
-    batch_gather<<<nb, kThreads, 0, s>>>(N, bs.offsets, bs.items, bs.keys, bs.vals, bs.tgt, bs.tgt_orig);
-
-    if (mode == 2 || mode == 3 || mode == 4) {
-        const unsigned lb = (unsigned)((n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
-        if (mode == 2) list_kernel<kCount><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
-        else if (mode == 3) list_kernel<kList><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
-        else list_kernel<kKeys><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
-        return;
-    }
-    BatchLaunch bl{bs.items, bs.tiles, n_tiles, n64, mode};
-    if (launch) *launch = bl;
-    if (ev0) hipEventRecord(ev0, s);
-    relaunch_batch(bl, s);
-    if (ev1) hipEventRecord(ev1, s);
+void run_single_fixed(Ctx *c, const RateSpec &r, int tile, void *scratch)
+{
+    hipStream_t s = c->stream;
+    const int64_t n_tiles = batch_tiles(&r, 1, tile);
+    BatchScratch bs = carve_batch(scratch, r.n_t, 1, n_tiles);
+    const Item I = make_item(r, bs, 0);
+    const int64_t nb = (n_tiles + kThreads - 1) / kThreads;
+    single_tables<<<(unsigned)(nb > 0 ? nb : 1), kThreads, 0, s>>>(I, tile, n_tiles, bs.items, bs.offsets, bs.tiles);
+    launch_staged(bs, r.n_t, 1, n_tiles, r.prec == START_FP64 ? n_tiles : 0, 0, c->d_flags, s, nullptr, nullptr,
+                  nullptr);
 }
 
 void relaunch_batch(const BatchLaunch &b, hipStream_t s)
