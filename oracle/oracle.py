@@ -64,6 +64,8 @@ def lib():
         L.or_fsh.restype = C.c_double
         L.or_lw_rates.argtypes = [P, C.c_int, P, i64, P, P, C.c_double, P, C.c_int]
         L.or_upstream_rates.argtypes = [P, C.c_int, P, i64, P, P, P, P, C.c_double, C.c_double, P, P, P, i64, P]
+        L.or_upstream_rates_ex.argtypes = [P, C.c_int, P, i64, P, P, P, P, C.c_double, C.c_double, P, P, P, i64, P,
+                                           C.c_int]
         _lib = L
     return _lib
 
@@ -229,11 +231,12 @@ def lw_rates(tree: Tree, grid_log2, grid_values, tgt_xyz, self_src=None, theta=1
 
 
 def upstream_rates(tree: Tree, grid_log2, grid_values, xyz, h, nhi, self_src=None, theta=1.0, sigma=6.3e-18,
-                   structure=False):
+                   structure=False, all_pairs=False):
     """Gamma per particle with the upstream-particle chain optical depths of
     section 2.2.1 (the particles are the targets).  With structure=True also
     returns (offsets [n+1], parents [pairs] as upstream particle index or -1,
-    stats [n, 2] = pairs, pairs integrated along the ray)."""
+    stats [n, 2] = pairs, pairs integrated along the ray).  all_pairs: test
+    every other particle as a neighbour (O(n^2)) instead of the cell list."""
     xyz = _f64(xyz).reshape(3, -1)
     n = xyz.shape[1]
     g = _f64(grid_values).reshape(-1)
@@ -244,12 +247,14 @@ def upstream_rates(tree: Tree, grid_log2, grid_values, xyz, h, nhi, self_src=Non
     cap = 0
     par = None
     if structure:
-        _check(lib().or_upstream_rates(tree._h, int(grid_log2), _p(g), n, _p(xyz), _p(_f64(h)), _p(_f64(nhi)),
-                                       _p(ss), float(theta), float(sigma), _p(out), _p(offs), None, 0, None),
-               "or_upstream_rates")
+        # the pair count from the lists alone (returns ECAPACITY with the offsets)
+        rc = lib().or_interaction_lists(tree._h, n, _p(xyz), _p(ss), float(theta), _p(offs), None, 0)
+        if rc not in (OK, ECAPACITY):
+            _check(rc, "or_interaction_lists")
         cap = int(offs[-1])
         par = np.zeros(max(cap, 1), np.int64)
-    _check(lib().or_upstream_rates(tree._h, int(grid_log2), _p(g), n, _p(xyz), _p(_f64(h)), _p(_f64(nhi)), _p(ss),
-                                   float(theta), float(sigma), _p(out), _p(offs), _p(par), cap, _p(stats)),
+    _check(lib().or_upstream_rates_ex(tree._h, int(grid_log2), _p(g), n, _p(xyz), _p(_f64(h)), _p(_f64(nhi)),
+                                      _p(ss), float(theta), float(sigma), _p(out), _p(offs), _p(par), cap, _p(stats),
+                                      int(bool(all_pairs))),
            "or_upstream_rates")
     return (out, offs, par[:cap], stats) if structure else out

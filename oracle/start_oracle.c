@@ -899,12 +899,100 @@ static int cmp_idpos(const void *a, const void *b)
     return x->id < y->id ? -1 : (x->id > y->id ? 1 : 0);
 }
 
+static int cmp_i64v(const void *a, const void *b)
+{
+    const int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* Cell list over the box for the neighbour search: M^3 cubic cells of side
+ * at least the largest 2h (at most 128 per axis), particles counting-sorted
+ * by cell in index order. */
+typedef struct {
+    int M;
+    double side;
+    int64_t *start;   /* [M^3 + 1] */
+    int64_t *order;   /* [n] */
+} or_cells;
+
+static int cell_axis(double x, double lo, double side, int M)
+{
+    const double f = floor((x - lo) / side);
+    return f < 0.0 ? 0 : (f > (double)(M - 1) ? M - 1 : (int)f);
+}
+
+static int cells_build(const or_box *box, int64_t n, const double *xyz, const double *h, or_cells *cl)
+{
+    double rmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) rmax = 2.0 * h[i] > rmax ? 2.0 * h[i] : rmax;
+    int M = rmax > 0.0 ? (int)floor(box->size / rmax) : 128;
+    M = M < 1 ? 1 : (M > 128 ? 128 : M);
+    cl->M = M;
+    cl->side = box->size / M;
+    const int64_t nc = (int64_t)M * M * M;
+    cl->start = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+    cl->order = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
+    int64_t *cell = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
+    if (!cl->start || !cl->order || !cell) {
+        free(cl->start); free(cl->order); free(cell);
+        return OR_ENOMEM;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int a[3];
+        for (int k = 0; k < 3; ++k) a[k] = cell_axis(xyz[(int64_t)k * n + i], box->lo[k], cl->side, M);
+        cell[i] = ((int64_t)a[0] * M + a[1]) * M + a[2];
+        cl->start[cell[i] + 1]++;
+    }
+    for (int64_t c = 0; c < nc; ++c) cl->start[c + 1] += cl->start[c];
+    int64_t *fill = (int64_t *)malloc((size_t)nc * sizeof(int64_t));
+    if (!fill) { free(cl->start); free(cl->order); free(cell); return OR_ENOMEM; }
+    memcpy(fill, cl->start, (size_t)nc * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) cl->order[fill[cell[i]]++] = i;
+    free(fill);
+    free(cell);
+    return OR_OK;
+}
+
+/* Every particle in the cells that a ball of radius r around x can touch,
+ * with one cell of margin on each side (the cell of a point is found by a
+ * rounded division), in increasing index.  Returns the count. */
+static int64_t cells_candidates(const or_cells *cl, const or_box *box, const double x[3], double r, int64_t *out)
+{
+    int a0[3], a1[3];
+    for (int k = 0; k < 3; ++k) {
+        a0[k] = cell_axis(x[k] - r, box->lo[k], cl->side, cl->M) - 1;
+        a1[k] = cell_axis(x[k] + r, box->lo[k], cl->side, cl->M) + 1;
+        a0[k] = a0[k] < 0 ? 0 : a0[k];
+        a1[k] = a1[k] > cl->M - 1 ? cl->M - 1 : a1[k];
+    }
+    int64_t m = 0;
+    for (int a = a0[0]; a <= a1[0]; ++a)
+        for (int b = a0[1]; b <= a1[1]; ++b)
+            for (int c = a0[2]; c <= a1[2]; ++c) {
+                const int64_t cell = ((int64_t)a * cl->M + b) * cl->M + c;
+                for (int64_t s = cl->start[cell]; s < cl->start[cell + 1]; ++s) out[m++] = cl->order[s];
+            }
+    qsort(out, (size_t)m, sizeof(int64_t), cmp_i64v);
+    return m;
+}
+
 int or_upstream_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n,
                       const double *xyz, const double *h, const double *nhi,
                       const int64_t *self_src, double theta, double sigma,
                       double *gamma_out, int64_t *offsets_out, int64_t *parent_out,
                       int64_t capacity, int64_t *stats)
 {
+    return or_upstream_rates_ex(t, grid_log2, grid, n, xyz, h, nhi, self_src, theta, sigma, gamma_out, offsets_out,
+                                parent_out, capacity, stats, 0);
+}
+
+int or_upstream_rates_ex(const or_tree *t, int grid_log2, const double *grid, int64_t n,
+                         const double *xyz, const double *h, const double *nhi,
+                         const int64_t *self_src, double theta, double sigma,
+                         double *gamma_out, int64_t *offsets_out, int64_t *parent_out,
+                         int64_t capacity, int64_t *stats, int all_pairs)
+{
+    or_cells cl = {0, 0.0, NULL, NULL};
     if (!t || !gamma_out || !grid || !h || !nhi || grid_log2 < 0 || grid_log2 > 10) return OR_EINVAL;
     if (!isfinite(sigma)) return OR_ENONFINITE;
     if (sigma < 0.0) return OR_EINVAL;
@@ -949,6 +1037,7 @@ int or_upstream_rates(const or_tree *t, int grid_log2, const double *grid, int64
     double *ts = (double *)malloc((size_t)(3 * G + 4) * sizeof(double));
     int64_t *stack = (int64_t *)malloc((size_t)(E ? E : 1) * sizeof(int64_t));
     if (!ra || !La || !dist || !par || !tau || !done || !sorted || !ts || !stack) { rc = OR_ENOMEM; goto out; }
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
         for (int64_t p = off[i]; p < off[i + 1]; ++p) {
@@ -975,36 +1064,67 @@ int or_upstream_rates(const or_tree *t, int grid_log2, const double *grid, int64
      * (virtual) source and have it in their own list, the one nearest to the
      * ray (largest cos phi; the lowest index on ties).  None: the pair is a
      * list-boundary particle and integrates along the ray. */
-    for (int64_t i = 0; i < n; ++i) {
-        const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
-        const double r2 = (2.0 * h[i]) * (2.0 * h[i]);
-        for (int64_t p = off[i]; p < off[i + 1]; ++p) par[p] = -1;
-        double *best = (double *)malloc((size_t)(off[i + 1] - off[i] + 1) * sizeof(double));
-        if (!best) { rc = OR_ENOMEM; goto out; }
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
-            const double ex = xyz[j] - x[0], ey = xyz[n + j] - x[1], ez = xyz[2 * n + j] - x[2];
-            if (!(ex * ex + ey * ey + ez * ez <= r2)) continue;       /* not a neighbour */
-            const double y[3] = {xyz[j], xyz[n + j], xyz[2 * n + j]};
-            for (int64_t p = off[i]; p < off[i + 1]; ++p) {
-                or_idpos key = {ids[p], 0};
-                const or_idpos *f = (const or_idpos *)bsearch(&key, sorted + off[j], (size_t)(off[j + 1] - off[j]),
-                                                              sizeof(or_idpos), cmp_idpos);
-                if (!f) continue;                                     /* not in the same list */
-                const int64_t q = f->pos;
-                if (!(dist[q] < dist[p])) continue;                   /* not upstream */
-                const double *a = ra + 3 * p;
-                const double dot = (x[0] - a[0]) * (y[0] - a[0]) + (x[1] - a[1]) * (y[1] - a[1]) +
-                                   (x[2] - a[2]) * (y[2] - a[2]);
-                const double cphi = dot / (dist[p] * dist[q]);
-                if (par[p] < 0 || cphi > best[p - off[i]]) {
-                    par[p] = q;
-                    best[p - off[i]] = cphi;
+    if (!all_pairs) {
+        rc = cells_build(&t->box, n, xyz, h, &cl);
+        if (rc) goto out;
+    }
+    int failed = 0;
+#pragma omp parallel
+    {
+        int64_t *cand = all_pairs ? NULL : (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
+        double *best = NULL;
+        int64_t best_cap = 0;
+        if (!all_pairs && !cand) {
+#pragma omp atomic write
+            failed = 1;
+        }
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            if (failed) continue;
+            const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
+            const double r2 = (2.0 * h[i]) * (2.0 * h[i]);
+            for (int64_t p = off[i]; p < off[i + 1]; ++p) par[p] = -1;
+            if (off[i + 1] - off[i] + 1 > best_cap) {
+                free(best);
+                best_cap = off[i + 1] - off[i] + 1;
+                best = (double *)malloc((size_t)best_cap * sizeof(double));
+                if (!best) {
+                    best_cap = 0;
+#pragma omp atomic write
+                    failed = 1;
+                    continue;
+                }
+            }
+            const int64_t m = all_pairs ? n : cells_candidates(&cl, &t->box, x, 2.0 * h[i], cand);
+            for (int64_t k = 0; k < m; ++k) {
+                const int64_t j = all_pairs ? k : cand[k];
+                if (j == i) continue;
+                const double ex = xyz[j] - x[0], ey = xyz[n + j] - x[1], ez = xyz[2 * n + j] - x[2];
+                if (!(ex * ex + ey * ey + ez * ez <= r2)) continue;       /* not a neighbour */
+                const double y[3] = {xyz[j], xyz[n + j], xyz[2 * n + j]};
+                for (int64_t p = off[i]; p < off[i + 1]; ++p) {
+                    or_idpos key = {ids[p], 0};
+                    const or_idpos *f = (const or_idpos *)bsearch(&key, sorted + off[j],
+                                                                  (size_t)(off[j + 1] - off[j]), sizeof(or_idpos),
+                                                                  cmp_idpos);
+                    if (!f) continue;                                     /* not in the same list */
+                    const int64_t q = f->pos;
+                    if (!(dist[q] < dist[p])) continue;                   /* not upstream */
+                    const double *a = ra + 3 * p;
+                    const double dot = (x[0] - a[0]) * (y[0] - a[0]) + (x[1] - a[1]) * (y[1] - a[1]) +
+                                       (x[2] - a[2]) * (y[2] - a[2]);
+                    const double cphi = dot / (dist[p] * dist[q]);
+                    if (par[p] < 0 || cphi > best[p - off[i]]) {
+                        par[p] = q;
+                        best[p - off[i]] = cphi;
+                    }
                 }
             }
         }
         free(best);
+        free(cand);
     }
+    if (failed) { rc = OR_ENOMEM; goto out; }
 
     /* 4. optical depths: tau = tau_up + sigma dl (n_target + n_up) / 2
      * (eqs. 8-9), dl = d_target - d_up; a pair without an upstream particle
@@ -1047,6 +1167,7 @@ int or_upstream_rates(const or_tree *t, int grid_log2, const double *grid, int64
     }
 
     /* 5. the rate per H I atom (eq. A2) with these optical depths */
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double sum = 0.0;
         int64_t roots = 0;
@@ -1077,5 +1198,6 @@ int or_upstream_rates(const or_tree *t, int grid_log2, const double *grid, int64
 out:
     free(off); free(ids); free(ra); free(La); free(dist); free(par); free(tau); free(done);
     free(sorted); free(ts); free(stack);
+    free(cl.start); free(cl.order);
     return rc;
 }

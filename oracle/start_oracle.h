@@ -142,12 +142,21 @@ int or_lw_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n_t
  * n_HI.  offsets_out [n+1] (may be NULL) receives the list offsets;
  * parent_out [capacity] (may be NULL) the upstream particle of each pair of
  * each list, in list order, or -1.  stats [n][2] (may be NULL): pairs, pairs
- * integrated along the ray.  O(n^2) neighbour search: small n only. */
+ * integrated along the ray.  Neighbours are searched through a cell list
+ * (cells within 2 h_i plus one of margin, candidates in increasing index),
+ * which only skips particles that fail the distance test. */
 int or_upstream_rates(const or_tree *t, int grid_log2, const double *grid, int64_t n,
                       const double *xyz, const double *h, const double *nhi,
                       const int64_t *self_src, double theta, double sigma,
                       double *gamma_out, int64_t *offsets_out, int64_t *parent_out,
                       int64_t capacity, int64_t *stats);
+/* The same with the neighbour search chosen: all_pairs != 0 tests every
+ * other particle (O(n^2), the definition as written), 0 the cell list. */
+int or_upstream_rates_ex(const or_tree *t, int grid_log2, const double *grid, int64_t n,
+                         const double *xyz, const double *h, const double *nhi,
+                         const int64_t *self_src, double theta, double sigma,
+                         double *gamma_out, int64_t *offsets_out, int64_t *parent_out,
+                         int64_t capacity, int64_t *stats, int all_pairs);
 
 #ifdef __cplusplus
 }

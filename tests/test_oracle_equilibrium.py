@@ -219,3 +219,44 @@ def test_diffuse_loop_without_ground_state_photons_is_the_plain_loop():
                                                 4.18e-13, max_iter=8, tol=0.0)
     assert itd == ito == 8
     assert np.array_equal(xd, xo) and np.array_equal(gd, go)
+
+
+def test_diffuse_loop_in_an_opaque_medium_is_the_case_b_loop():
+    """The statement after eq. (30): where every particle is opaque to its own
+    recombination photons the transfer of those photons reduces to case B.
+    2048 particles in a 1 kpc box at n_H = 1 (optical depth from a
+    particle's edge to its centre ~960 x), 32 stars of 5e44 photons/s each
+    placed 0.5 pc from a particle, which they ionise in part (x down to ~0.07,
+    still > 60 optical depths), theta = 0.  The converged diffuse loop
+    (alpha_A, alpha_1 > 0; every particle an emitter) equals the on-the-spot
+    loop with alpha_B = alpha_A - alpha_1 (the other particles' photons are
+    absorbed before they reach a neighbour); with alpha_A instead it does
+    not, so the comparison has power."""
+    w = W.make_small(seed=4, n_gas=2048, n_src=1)
+    size = 1.0
+    gas = np.ascontiguousarray(w.gas_xyz / w.box_size * size)
+    h = W.smoothing_lengths(gas)
+    box = O.make_box(np.zeros(3), size, W.KPC_CM)
+    n = w.n_gas
+    nh = np.full(n, 1.0)
+    vol = np.full(n, (size * W.KPC_CM) ** 3 / n)
+    rng = np.random.default_rng(8)
+    pick = rng.choice(n, 32, replace=False)
+    v = rng.normal(size=(3, 32))
+    v /= np.linalg.norm(v, axis=0)
+    stars = np.ascontiguousarray(np.clip(gas[:, pick] + v * 0.5e-3, 0.0, size))
+    slum = np.full(32, 5e44)
+    aA, a1, sigma = 4.18e-13, 1.58e-13, 6.3e-18
+    x0 = np.ones(n)
+    xd, _, itd, chd = E.diffuse_equilibrium(box, gas, h, nh, vol, stars, slum, x0, 4, 0.0, sigma, aA, a1,
+                                            max_iter=60, tol=1e-11)
+    tree = O.Tree(box, stars, slum)
+    xb, _, itb, chb = E.ionization_equilibrium(box, tree, gas, h, nh, x0, 4, 0.0, sigma, aA - a1,
+                                               max_iter=60, tol=1e-11)
+    xa, _, _, _ = E.ionization_equilibrium(box, tree, gas, h, nh, x0, 4, 0.0, sigma, aA, max_iter=60, tol=1e-11)
+    assert chd <= 1e-11 and chb <= 1e-11
+    tau = E.self_optical_depth(nh, xd, vol, sigma)
+    assert tau.min() >= 40.0                        # opaque everywhere, also at the ionised particles
+    assert int((xd < 0.9).sum()) >= 20              # not the trivial all-neutral state
+    assert np.max(np.abs(xd - xb)) <= 1e-12
+    assert np.max(np.abs(xd - xa)) >= 1e-2

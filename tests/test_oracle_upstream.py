@@ -113,6 +113,55 @@ def test_self_excluded_emitters_chain():
     assert np.array_equal(par, _parents_by_definition(w, 1.0, w.self_src))
 
 
+def _mixed_support(w, seed):
+    """Smoothing lengths spread over two decades (a few particles with a
+    support of a third of the box), so the cell list's cells and margins are
+    crossed in every way."""
+    rng = np.random.default_rng(seed)
+    w.gas_h = w.gas_h * np.exp(rng.uniform(-1.5, 1.5, w.n_gas))
+    big = rng.choice(w.n_gas, size=max(1, w.n_gas // 100), replace=False)
+    w.gas_h[big] = w.box_size / 6
+    return w
+
+
+@pytest.mark.parametrize("kind", ["uniform", "lognormal", "emitters", "mixed_support", "clustered"])
+def test_cell_list_search_equals_all_pairs(kind):
+    """The cell-list neighbour search only skips particles that fail the
+    distance test, in the all-pairs loop's order: offsets, upstream particles,
+    root counts and rates equal the O(n^2) search bit for bit."""
+    ss = None
+    if kind == "uniform":
+        w = W.make_small(seed=21, n_gas=1500, n_src=16)
+    elif kind == "lognormal":
+        w = W.make_clumpy(seed=22, n_gas=1500, n_src=24)
+    elif kind == "emitters":
+        w = W.make_diffuse(seed=23, n_gas=1200)
+        ss = w.self_src
+    elif kind == "mixed_support":
+        w = _mixed_support(W.make_clumpy(seed=24, n_gas=1200, n_src=20), 5)
+    else:
+        # particles packed into two small blobs and a few strays: cells of
+        # very uneven occupancy, some particles on the box faces
+        w = W.make_small(seed=25, n_gas=1200, n_src=10)
+        rng = np.random.default_rng(3)
+        c = np.array([[0.2, 0.8], [0.3, 0.7], [0.5, 0.5]]) * w.box_size
+        pick = rng.integers(0, 2, w.n_gas)
+        xyz = c[:, pick] + rng.normal(0, 0.03 * w.box_size, (3, w.n_gas))
+        xyz[:, :10] = rng.uniform(0, w.box_size, (3, 10))
+        xyz[0, 10:14] = 0.0
+        xyz[1, 14:18] = w.box_size
+        w.gas_xyz = np.clip(xyz, 0.0, w.box_size)
+        w.gas_h = W.smoothing_lengths(w.gas_xyz)
+    box, tree, grid = setup(w)
+    a = O.upstream_rates(tree, w.grid_log2, grid, w.gas_xyz, w.gas_h, w.gas_nhi, ss, 1.0, w.sigma,
+                         structure=True, all_pairs=True)
+    b = O.upstream_rates(tree, w.grid_log2, grid, w.gas_xyz, w.gas_h, w.gas_nhi, ss, 1.0, w.sigma,
+                         structure=True, all_pairs=False)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert (a[2] >= 0).mean() > 0.5
+
+
 def test_smooth_gas_chain_close_to_ray_integral():
     """A smooth field (n_HI varying by +-50% over the box, ~0.4 optical depths
     per particle spacing): both schemes approximate the same column, and the
