@@ -31,9 +31,19 @@ def cases():
             "uniform_theta0": (w1, 0.0)}
 
 
-@pytest.mark.parametrize("name", ["uniform", "lognormal", "emitters", "smooth", "uniform_theta0"])
+def large_cases():
+    # 2^15 particles: several grid cells of particles per kernel support, the
+    # neighbour lists' full range of lengths and deep chains (the oracle's
+    # cell-list search makes these sizes affordable)
+    return {"lognormal_2^15": (H.W.make_clumpy(seed=12, n_gas=1 << 15, n_src=1024), 1.0),
+            "emitters_2^15": (H.W.make_diffuse(seed=13, n_gas=1 << 15), 1.0)}
+
+
+@pytest.mark.parametrize("name", ["uniform", "lognormal", "emitters", "smooth", "uniform_theta0",
+                                  "lognormal_2^15", "emitters_2^15"])
 def test_upstream_chain_matches_oracle(ctx, name):
-    w, theta = cases()[name]
+    w, theta = (large_cases() if name.endswith("2^15") else cases())[name]
+    print(f"[case] upstream {name}: {w.n_gas} particles, {w.n_src} sources, theta {theta}", flush=True)
     dev = ctx.device
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     box = H.box_of(w)
