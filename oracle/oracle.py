@@ -14,7 +14,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB=liboracle_san.so loads the sanitizer build (build.sh sanitize)
+_LIB_PATH = os.path.join(_HERE, os.environ.get("ORACLE_LIB", "liboracle.so"))
 
 OK, EINVAL, ENOMEM, EOUTOFBOX, ENONFINITE, ECAPACITY = 0, -1, -2, -4, -5, -6
 
@@ -29,8 +30,8 @@ class _Box(C.Structure):
     _fields_ = [("lo", C.c_double * 3), ("size", C.c_double), ("unit_cm", C.c_double)]
 
 
-def build():
-    subprocess.run(["sh", os.path.join(_HERE, "build.sh")], check=True)
+def build(sanitize=False):
+    subprocess.run(["sh", os.path.join(_HERE, "build.sh")] + (["sanitize"] if sanitize else []), check=True)
 
 
 _lib = None
@@ -40,7 +41,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
-            build()
+            build(sanitize=_LIB_PATH.endswith("_san.so"))
         L = C.CDLL(_LIB_PATH)
         P = C.c_void_p
         i64 = C.c_int64

@@ -63,6 +63,8 @@ class Workload:
     grid_log2: int
     sigma: float = SIGMA_HI
     gas_nh2: np.ndarray | None = None   # (N_gas,) H2 density, cm^-3 (Lyman-Werner workloads)
+    gas_nh: np.ndarray | None = None    # (N_gas,) total hydrogen density, cm^-3, where drawn
+    meta: dict = dataclasses.field(default_factory=dict)   # drawn geometry (centres, radii)
 
     @property
     def n_gas(self):
@@ -108,7 +110,7 @@ def make_small(seed: int = 1, n_gas: int = 4096, n_src: int = 16) -> Workload:
     lum = np.full(n_src, 5e48)
     nhi = np.full(n_gas, 1e-3)
     return Workload("small", np.zeros(3), L, KPC_CM, gas, smoothing_lengths(gas), nhi,
-                    src, lum, gas, None, (0.0, 0.5, 1.0), auto_grid_log2(n_gas))
+                    src, lum, gas, None, (0.0, 0.5, 1.0), auto_grid_log2(n_gas), gas_nh=nhi.copy())
 
 
 def make_clumpy(seed: int = 2, n_gas: int = 1 << 18, n_src: int = 1024) -> Workload:
@@ -121,7 +123,7 @@ def make_clumpy(seed: int = 2, n_gas: int = 1 << 18, n_src: int = 1024) -> Workl
     nh = 1e-3 * np.exp(g - 0.5)             # lognormal, sigma_ln = 1, mean 1e-3
     xhi = rng.uniform(0.5, 1.0, n_gas)
     return Workload("clumpy", np.zeros(3), L, KPC_CM, gas, smoothing_lengths(gas), nh * xhi,
-                    src, lum, gas, None, (0.3, 0.5, 0.8, 1.0), auto_grid_log2(n_gas))
+                    src, lum, gas, None, (0.3, 0.5, 0.8, 1.0), auto_grid_log2(n_gas), gas_nh=nh)
 
 
 def _emitters(gas, nh, xhii, L, n_gas):
@@ -146,7 +148,8 @@ def make_diffuse(seed: int = 3, n_gas: int = 1 << 20, star_lum: float = 1e50,
     src_lum = np.concatenate([lum, [star_lum]])
     self_src = np.arange(n_gas, dtype=np.int64)
     return Workload("diffuse", np.zeros(3), L, KPC_CM, gas, smoothing_lengths(gas), nhi,
-                    src, src_lum, gas, self_src, (1.0,), auto_grid_log2(n_gas))
+                    src, src_lum, gas, self_src, (1.0,), auto_grid_log2(n_gas), gas_nh=nh,
+                    meta={"star": c[:, 0].copy(), "hii_radius": hii_radius * L})
 
 
 def make_shadow(seed: int = 4, n_gas: int = 1 << 21, n_clumps: int = 16,
@@ -176,7 +179,9 @@ def make_shadow(seed: int = 4, n_gas: int = 1 << 21, n_clumps: int = 16,
     src_lum = np.concatenate([lum, [star_lum]])
     self_src = np.arange(n_gas, dtype=np.int64)
     return Workload("shadow", np.zeros(3), L, KPC_CM, gas, smoothing_lengths(gas), nhi,
-                    src, src_lum, gas, self_src, (1.0,), auto_grid_log2(n_gas))
+                    src, src_lum, gas, self_src, (1.0,), auto_grid_log2(n_gas), gas_nh=nh,
+                    meta={"star": c[:, 0].copy(), "hii_radius": 0.3 * L, "clump_centres": centres,
+                          "clump_radius": 0.05 * L})
 
 
 @dataclasses.dataclass
