@@ -639,25 +639,29 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     };
     auto nomem = [&]() { return done(fail(ctx, c.budget ? START_EBUDGET : START_ENOMEM, "device allocation failed")); };
     const int64_t n = n_gas;
-    // 1. list sizes and offsets (32-bit: the pairs are counted in unsigned)
+    // 1. list sizes and offsets.  The pairs are indexed with 32-bit offsets:
+    // the sizes are first summed in 64 bits and the call is refused before
+    // anything is narrowed if the total does not fit.
     int64_t *off64 = (int64_t *)alloc((size_t)(n + 1) * sizeof(int64_t));
     unsigned *off = (unsigned *)alloc((size_t)(n + 1) * sizeof(unsigned));
     void *scan_tmp = alloc(scan_temp_bytes(n + 1) + (size_t)(n + 1) * sizeof(unsigned));
-    if (!off64 || !off || !scan_tmp) return nomem();
+    unsigned long long *total64 = (unsigned long long *)alloc(256);
+    if (!off64 || !off || !scan_tmp || !total64) return nomem();
     RateSpec r = spec_of(tree, grid, n, gas_xyz, self_src, theta_crit, sigma_cm2, START_FP64);
     r.counts = off64;
     st = enqueue(ctx, &r, 1, 2);
     if (st) return done(st);
+    hipMemsetAsync(total64, 0, sizeof(unsigned long long), s);
+    launch_sum_i64(&c, n, off64, total64);
+    unsigned long long total = 0;
+    hipMemcpyAsync(&total, total64, sizeof(total), hipMemcpyDeviceToHost, s);
+    st = start_synchronize(ctx);
+    if (st) return done(st);
+    if (!upstream_pairs_fit(total)) return done(fail(ctx, START_ECAPACITY, "more than 2^31 - 1 list entries"));
+    const int64_t E = (int64_t)total;
     launch_to_u32(&c, n, off64, off);
     hipMemsetAsync(off + n, 0, sizeof(unsigned), s);
     exclusive_scan_u32(off, n + 1, scan_tmp, s);
-    unsigned total_u = 0;
-    hipMemcpyAsync(&total_u, off + n, sizeof(unsigned), hipMemcpyDeviceToHost, s);
-    st = start_synchronize(ctx);
-    if (st) return done(st);
-    const int64_t E = total_u;
-    // (sums of at most 2^31 fit: a wrapped sum shows as offsets going down)
-    if (E > ((int64_t)1 << 31) - 1) return done(fail(ctx, START_ECAPACITY, "more than 2^31 list entries"));
     launch_to_i64(&c, n + 1, off, off64);
     const size_t Eb = (size_t)(E > 0 ? E : 1);
     uint64_t *keys = (uint64_t *)alloc(Eb * sizeof(uint64_t));

@@ -510,12 +510,25 @@ void free_bins(Ctx *c, GasBins *b)
     b->pw = b->pden = nullptr;
 }
 
+namespace {
+
+// Both copies of an empty grid set to 0 by a kernel (fill_grid may be
+// captured into a HIP graph, where memset nodes are avoided).
+__global__ void __launch_bounds__(256) zero_grid(int64_t span, double *val, float *valf)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= span) return;
+    val[k] = 0.0;
+    valf[k] = 0.0f;
+}
+
+}  // namespace
+
 void fill_grid(Ctx *c, const GasBins &b, const double *nhi, Grid *g)
 {
     hipStream_t s = c->stream;
     if (b.n == 0) {
-        hipMemsetAsync(g->val, 0, g->span * sizeof(double), s);
-        hipMemsetAsync(g->valf, 0, g->span * sizeof(float), s);
+        zero_grid<<<(unsigned)((g->span + 255) / 256), 256, 0, s>>>(g->span, g->val, g->valf);
         return;
     }
     if (nhi) gather_values<<<blocks_for(b.n), kThreads, 0, s>>>(b.n, b.idx, nhi, b.ns);

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/start.h"
+#include "limits.h"
 
 namespace start {
 
@@ -277,6 +278,8 @@ void launch_upstream_roots(Ctx *c, const Tree *t, const Grid *g, int64_t n_roots
                            double *acc);
 
 void launch_to_u32(Ctx *c, int64_t n, const int64_t *in, unsigned *out);
+// *total += sum of n non-negative int64 values (64-bit accumulation)
+void launch_sum_i64(Ctx *c, int64_t n, const int64_t *in, unsigned long long *total);
 void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out);
 // Neighbours within 2 h_i: counts (nb_off null) or the lists at nb_off,
 // each neighbour's index in nb and its binned record's place in nbs.

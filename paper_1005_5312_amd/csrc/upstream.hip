@@ -264,6 +264,24 @@ __global__ void __launch_bounds__(kThreads) to_u32(int64_t n, const int64_t *__r
     if (i < n) out[i] = (unsigned)in[i];
 }
 
+// 64-bit sum of non-negative counts: a block sum (wave reductions, then one
+// 64-bit atomic per block)
+__global__ void __launch_bounds__(kThreads) sum_i64(int64_t n, const int64_t *__restrict__ in,
+                                                    unsigned long long *__restrict__ total)
+{
+    __shared__ unsigned long long part[kThreads / 64];
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    unsigned long long v = i < n ? (unsigned long long)in[i] : 0ull;
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b = 0;
+        for (int w = 0; w < kThreads / 64; ++w) b += part[w];
+        atomicAdd(total, b);
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) to_i64(int64_t n, const unsigned *__restrict__ in, int64_t *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -286,6 +304,11 @@ __global__ void __launch_bounds__(kThreads) parent_particle(int64_t n_pairs, con
 void launch_to_u32(Ctx *c, int64_t n, const int64_t *in, unsigned *out)
 {
     if (n > 0) to_u32<<<blocks_for(n), kThreads, 0, c->stream>>>(n, in, out);
+}
+
+void launch_sum_i64(Ctx *c, int64_t n, const int64_t *in, unsigned long long *total)
+{
+    if (n > 0) sum_i64<<<blocks_for(n), kThreads, 0, c->stream>>>(n, in, total);
 }
 
 void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out)
