@@ -100,3 +100,73 @@ def test_admission_under_a_small_budget():
     srv.stop()
     assert all(o is not None and np.all(np.isfinite(o)) for o in outs)
     assert srv.used <= srv.budget
+
+
+def _step_until_idle(srv, limit_s=120.0):
+    import time
+    t0 = time.perf_counter()
+    while not srv._idle():
+        srv.step()
+        time.sleep(0.0005)
+        assert time.perf_counter() - t0 < limit_s, "server did not become idle"
+
+
+def test_nan_request_fails_alone_in_a_mixed_batch(monkeypatch):
+    """A request whose targets hold a NaN, let through the host-side checks
+    so that it reaches the device inside a batch of twelve good ones: the
+    library flags the batch, the server runs its requests one by one, the bad
+    one fails with START_ENONFINITE and every other result is bit-identical to
+    the same request served alone."""
+    from paper_1005_5312_amd import binding, serve
+    scenes = make_scenes()
+    ex = serve.GpuExecutor(0, n_slots=1)
+    print("[case] serve: NaN request in a mixed batch", flush=True)
+    srv = serve.Server(ex, hbm_budget=8 << 30, max_batch=32).start()
+    alone = [srv.submit(r).result(timeout=120) for r in make_requests(scenes, 12, seed=7)]
+    srv.drain()
+    srv.stop()
+    monkeypatch.setattr(serve, "validate_request", lambda r: None)
+    srv = serve.Server(ex, hbm_budget=8 << 30, max_batch=32)     # driven turn by turn below
+    for sc, w in scenes:                                            # scenes resident first
+        srv.submit(serve.Request(sc, np.ascontiguousarray(w.tgt_xyz[:, :4])))
+    _step_until_idle(srv)
+    reqs = make_requests(scenes, 12, seed=7)
+    bad_xyz = reqs[3].tgt_xyz.copy()
+    bad_xyz[1, 0] = np.nan
+    futs = [srv.submit(r) for r in reqs[:6]]
+    bad = srv.submit(serve.Request(reqs[3].scene, bad_xyz, reqs[3].self_src, reqs[3].theta, reqs[3].sigma,
+                                   reqs[3].prec))
+    futs += [srv.submit(r) for r in reqs[6:]]
+    srv.step()
+    assert len(srv.inflight) == 1 and len(srv.inflight[0][1]) == 13      # one batch of all thirteen
+    _step_until_idle(srv)
+    with pytest.raises(binding.StartError) as e:
+        bad.result(timeout=1)
+    assert e.value.code == binding.ENONFINITE
+    for a, f in zip(alone, futs):
+        b = f.result(timeout=1)
+        assert a.dtype == b.dtype and np.array_equal(a, b)
+    assert sum(srv.scene_users.values()) == 0
+
+
+def test_whole_scene_requests_use_resident_particles():
+    """Requests for every particle of a scene (targets left on the device with
+    the scene, the scene's own-source indices) equal a direct rate call."""
+    from paper_1005_5312_amd import binding, serve
+    w = H.W.make_diffuse(seed=24, n_gas=1 << 14)
+    sc = serve.Scene("d", H.box_of(w), w.src_xyz, w.src_lum, w.gas_xyz, w.gas_h, w.gas_nhi, w.grid_log2,
+                     self_src=w.self_src)
+    ex = serve.GpuExecutor(0, n_slots=2)
+    srv = serve.Server(ex, hbm_budget=8 << 30).start()
+    futs = [srv.submit(serve.Request(sc, None, theta=1.0, sigma=w.sigma, prec=p)) for p in ("fp32c", "fp64")]
+    outs = [f.result(timeout=120) for f in futs]
+    srv.drain()
+    srv.stop()
+    ctx = binding.Context(0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    tree = ctx.build_source_tree(sc.box, d(w.src_xyz), d(w.src_lum))
+    grid = ctx.build_gas_grid(sc.box, d(w.gas_xyz), d(w.gas_h), d(w.gas_nhi), w.grid_log2)
+    for p, o in zip(("fp32c", "fp64"), outs):
+        want = ctx.compute_rates(tree, grid, d(w.gas_xyz), d(w.self_src), 1.0, w.sigma, p).cpu().numpy()
+        assert np.array_equal(o, want)
+    ctx.close()
