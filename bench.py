@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CUS, CLOCK_HZ = 256, 2.4e9          # MI355X compute units and peak engine clock
 METRIC = "particle-rate evals/s at θ_crit=1 (FP32 vs FP64 GPU); serve p50/p99 latency"
 WORKLOAD_TEXT = {
     "diffuse": "diffuse recombination: N_p = 2^20 emitting SPH particles + central 1e50/s star "
@@ -83,14 +84,35 @@ def traffic_from_profiles(workload, prec, sha):
         return None
 
 
-def cpu_baseline(w, sample, seed=17):
-    """The CPU FP64 oracle on this host: tree and grid built in full, rates
-    on a seeded sample of targets, whole step extrapolated linearly in the
-    number of targets."""
+def counters_from_profiles(workload, prec, sha):
+    """SQ and L1 counters per walk launch from the committed rocprofv3 summary,
+    if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"rates_kernel_{prec}_{workload}_sq_tcp_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha") != sha:
+        return None
+    try:
+        return {k: float(v) for k, v in vals.items() if k != "source_sha"}
+    except ValueError:
+        return None
+
+
+def cpu_baseline(w):
+    """The CPU FP64 oracle on this host, on the whole benchmark workload: tree,
+    grid and the rates of every target, on the threads this process is given
+    (OMP_NUM_THREADS when set, else every core in its affinity mask)."""
     from oracle import oracle as O
-    from paper_1005_5312_amd import workloads as W
-    # the host cores this process may use (the box's CPU share), at most 16
-    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    n_aff = len(os.sched_getaffinity(0))
+    threads = n_aff
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        threads = min(threads, int(env))
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -106,16 +128,14 @@ def cpu_baseline(w, sample, seed=17):
     t1 = time.perf_counter()
     grid = O.grid(box, w.gas_xyz, w.gas_h, w.gas_nhi, w.grid_log2)
     t2 = time.perf_counter()
-    idx = W.sample_indices(w.n_tgt, sample, seed)
-    ss = None if w.self_src is None else w.self_src[idx]
-    O.rates(tree, w.grid_log2, grid, w.tgt_xyz[:, idx], ss, 1.0, w.sigma, nthreads=threads)
+    O.rates(tree, w.grid_log2, grid, w.tgt_xyz, w.self_src, 1.0, w.sigma, nthreads=threads)
     t3 = time.perf_counter()
-    step = (t1 - t0) + (t2 - t1) + (t3 - t2) * w.n_tgt / len(idx)
+    step = t3 - t0
     return {"value": w.n_tgt / step, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle, {threads} threads: full tree ({t1 - t0:.2f} s) and grid ({t2 - t1:.2f} s), "
-                      f"rates for {len(idx)} of {w.n_tgt} targets ({t3 - t2:.2f} s); step time extrapolated "
-                      f"to all targets = {step:.1f} s",
-            "rates_only_evals_per_s": len(idx) / (t3 - t2), "cpu_model": model}
+            "sample": f"the whole workload: FP64 oracle, {threads} threads, tree ({t1 - t0:.2f} s), grid "
+                      f"({t2 - t1:.2f} s) and the rates of all {w.n_tgt} targets ({t3 - t2:.2f} s) = {step:.1f} s",
+            "rates_only_evals_per_s": w.n_tgt / (t3 - t2), "cpu_model": model, "nproc": os.cpu_count(),
+            "affinity_cpus": n_aff, "omp_num_threads_env": env or None}
 
 
 def make_scene_pool(n, seed, lo_log2=14, hi_log2=17):
@@ -148,46 +168,102 @@ def make_scene_pool(n, seed, lo_log2=14, hi_log2=17):
     return pool
 
 
-def serve_bench(lam, n_req, seed=5, autotune=False):
-    """Poisson arrivals at `lam` requests/s; each request asks for the rates of
-    every particle of a scene drawn from a resident pool."""
+def make_serve_pool(n_scenes, seed, lo_log2=14, hi_log2=21):
+    """Scenes of the served mix: N_p = round(2^U[lo, hi]) particles, N_s drawn
+    from {1, 64, N_p}, the medium from the small / clumpy / diffuse generators
+    (uniform choices), every particle a target.  Diffuse scenes with N_s = N_p
+    keep all emitters (and the star; own sources excluded), with N_s = 1 or 64
+    the star and 63 emitters."""
+    from paper_1005_5312_amd import Box, serve
+    from paper_1005_5312_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    pool = []
+    for k in range(n_scenes):
+        n_p = int(round(2 ** rng.uniform(lo_log2, hi_log2)))
+        kind = ("small", "clumpy", "diffuse")[int(rng.integers(3))]
+        ns_kind = ("one", "64", "all")[int(rng.integers(3))]
+        s = int(rng.integers(1 << 30))
+        if kind == "diffuse":
+            w = W.make_diffuse(seed=s, n_gas=n_p)
+            if ns_kind != "all":
+                m = 1 if ns_kind == "one" else 64
+                keep = np.concatenate([rng.choice(n_p, size=m - 1, replace=False), [n_p]]) if m > 1 else [n_p]
+                w.src_xyz = np.ascontiguousarray(w.src_xyz[:, keep])
+                w.src_lum = np.ascontiguousarray(w.src_lum[keep])
+                w.self_src = None
+        else:
+            n_s = 1 if ns_kind == "one" else (64 if ns_kind == "64" else n_p)
+            w = (W.make_small if kind == "small" else W.make_clumpy)(seed=s, n_gas=n_p, n_src=n_s)
+        box = Box(tuple(float(v) for v in w.box_lo), float(w.box_size), float(w.length_unit_cm))
+        pool.append(serve.Scene(("scene", k, kind, ns_kind), box, w.src_xyz, w.src_lum, w.gas_xyz, w.gas_h,
+                                w.gas_nhi, w.grid_log2, self_src=w.self_src))
+    return pool
+
+
+def serve_bench(rates, window_s=15.0, max_requests=2000, n_scenes=32, seed=5, autotune=False, log_fn=None):
+    """The served workload: Poisson arrivals at each rate in `rates` (requests
+    per second), each request the rates of every particle of a scene drawn
+    uniformly from a pool of n_scenes (make_serve_pool), FP32C, theta = 1.
+    Every rate starts with no scene resident; the HBM budget holds the whole
+    pool, so a scene is built on its first request and stays resident (those
+    first requests are reported as "cold").  Requests per rate: min(
+    max_requests, rate x window_s).  Latency from submit to the result on the
+    host.  One more run at the lowest rate with a budget of half the pool
+    shows the cost of evicting and rebuilding scenes."""
     import threading
     from paper_1005_5312_amd import serve
-    pool = make_scene_pool(6, seed)
+    t_pool = time.perf_counter()
+    pool = make_serve_pool(n_scenes, seed)
+    t_pool = time.perf_counter() - t_pool
     ex = serve.GpuExecutor(0, n_slots=2, autotune=autotune)
-    srv = serve.Server(ex, hbm_budget=64 << 30, max_batch=32).start()
+    sb = [ex.scene_bytes(sc) for sc in pool]
+    rb = [ex.request_bytes(serve.Request(sc, None)) for sc in pool]
+    budget = int(1.25 * (sum(sb) + 32 * max(rb)))
+    small_budget = int(max(1.2 * (max(sb) + 4 * max(rb)), 0.5 * sum(sb)))
     rng = np.random.default_rng(seed + 1)
-    # warm: build every scene once (resident afterwards)
-    for sc, w in pool:
-        srv.submit(serve.Request(sc, w.tgt_xyz, w.self_src, 1.0, w.sigma, "fp32c")).result()
-    srv.completed.clear()
-    gaps = rng.exponential(1.0 / lam, n_req)
-    picks = rng.integers(0, len(pool), n_req)
-    futs = []
 
-    def client():
-        t0 = time.perf_counter()
-        at = 0.0
-        for g, k in zip(gaps, picks):
-            at += g
-            d = t0 + at - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            sc, w = pool[k]
-            futs.append(srv.submit(serve.Request(sc, w.tgt_xyz, w.self_src, 1.0, w.sigma, "fp32c")))
+    def run(lam, bud):
+        n_req = int(min(max_requests, max(20, round(lam * window_s))))
+        if log_fn:
+            log_fn(f"[bench] serving: Poisson arrivals at {lam}/s, {n_req} requests, budget {bud / 2**30:.2f} GiB")
+        srv = serve.Server(ex, hbm_budget=bud, max_batch=32).start()
+        gaps = rng.exponential(1.0 / lam, n_req)
+        picks = rng.integers(0, len(pool), n_req)
+        futs = []
 
-    th = threading.Thread(target=client)
-    th.start()
-    th.join()
-    for f in futs:
-        f.result(timeout=600)
-    srv.drain()
-    srv.stop()
-    st = srv.latency_stats()
-    st["arrival_rate_per_s"] = lam
-    st["autotuned_tiles"] = autotune
-    st["scene_sizes"] = sorted(int(w.n_tgt) for _, w in pool)
-    return st
+        def client():
+            t0 = time.perf_counter()
+            at = 0.0
+            for g, k in zip(gaps, picks):
+                at += g
+                d = t0 + at - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                futs.append(srv.submit(serve.Request(pool[k], None, theta=1.0, sigma=6.3e-18, prec="fp32c")))
+
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        for f in futs:
+            f.result(timeout=600)
+        srv.drain()
+        srv.close()
+        st = srv.latency_stats()
+        rps = st["requests"] / st["span_s"] if st.get("span_s") else None
+        st.update({"arrival_rate_per_s": lam, "requests_asked": n_req, "requests_per_s": rps,
+                   "saturated": bool(rps is not None and rps < 0.9 * lam),
+                   "scene_builds": srv.builds, "scene_evictions": srv.evictions, "hbm_budget_bytes": bud})
+        return st
+
+    out = [run(lam, budget) for lam in rates]
+    evict = run(min(rates), small_budget) if rates else None
+    sizes = sorted(sc.n_gas for sc in pool)
+    return {"workload": f"{n_scenes} scenes, N_p = round(2^U[14,21]) ({sizes[0]}-{sizes[-1]}), N_s from "
+                        "{1, 64, N_p}, medium from the small / clumpy / diffuse generators; every particle a "
+                        "target; FP32C, theta = 1; each request draws its scene uniformly",
+            "pool_scene_bytes": int(sum(sb)), "pool_targets": int(sum(sizes)), "pool_build_host_s": t_pool,
+            "slots": 2, "max_batch": 32, "autotuned_tiles": autotune, "by_rate": out,
+            "half_pool_budget": evict}
 
 
 def batch_bench(n_inst=256, n_p=1 << 14, seed=9, reps=3):
@@ -647,13 +723,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="diffuse", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--theta", type=float, default=1.0)
-    ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rates-only", action="store_true",
                     help="time only the rate call (profiling runs)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving and batching measurements")
-    ap.add_argument("--serve-rates", default="10,100,1000", help="Poisson arrival rates swept (requests/s)")
-    ap.add_argument("--serve-requests", type=int, default=100, help="requests per arrival rate")
+    ap.add_argument("--serve-rates", default="10,30,100,300,1000", help="Poisson arrival rates swept (requests/s)")
+    ap.add_argument("--serve-window", type=float, default=15.0,
+                    help="arrival window per rate (s): requests per rate = min(max, rate x window)")
+    ap.add_argument("--serve-max-requests", type=int, default=2000, help="most requests per arrival rate")
+    ap.add_argument("--serve-scenes", type=int, default=32, help="scenes in the served pool")
     ap.add_argument("--no-equilibrium", action="store_true", help="skip the equilibrium-loop measurement")
     ap.add_argument("--no-shadow", action="store_true", help="skip the 2^21-particle shadowing measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -767,9 +845,31 @@ def main():
     sha = source_sha()
     alg = {p: algorithmic_bytes(c, p) for p in ("fp32c", "fp64")}
     prec = "fp32c"
-    ach = alg[prec] / (kern[prec]["avg_ms"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(args.workload, prec, sha),
+    t_k = kern[prec]["avg_ms"] * 1e-3
+    ach = alg[prec] / t_k / 1e9
+    traffic = traffic_from_profiles(args.workload, prec, sha)
+    cnt_p = counters_from_profiles(args.workload, prec, sha)
+    # issue limits of the chip: one VALU wave-instruction per CU per cycle
+    # (a wave64 instruction occupies one of the 4 SIMDs for 4 cycles)
+    cyc = CUS * CLOCK_HZ * t_k
+    valu_frac = cnt_p["SQ_INSTS_VALU"] / cyc if cnt_p else None
+    l1_rate = cnt_p["TCP_TOTAL_CACHE_ACCESSES_sum"] / cyc if cnt_p else None
+    hbm_frac = traffic / t_k / (HBM_PEAK_GBS * 1e9) if traffic else None
+    if valu_frac is not None:
+        bound = "alu" if valu_frac >= (hbm_frac or 0.0) else "hbm"
+    else:
+        bound = "alu"   # by the last counters taken (VALU issue and L1), not retaken for these sources
+    roofline = {"bound": bound, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "frac_basis": "algorithmic bytes per launch (per target: 28 + 12 per opening test + 16 per entry "
+                              "+ 4 per grid cell crossed, exact counters of this launch) / walk-kernel time / "
+                              "8 TB/s; these bytes are served mostly by L1 and L2, measured HBM traffic is "
+                              "'traffic'",
+                "valu_issue_frac": round(valu_frac, 4) if valu_frac is not None else None,
+                "l1_accesses_per_cu_cycle": round(l1_rate, 4) if l1_rate is not None else None,
+                "hbm_traffic_frac": round(hbm_frac, 4) if hbm_frac is not None else None,
+                "counters": "profiles/rates_kernel_fp32c_{}_sq_tcp_counters.txt".format(args.workload)
+                if cnt_p else None,
                 "kernel": "rates_kernel<FP32C> (tree walk + ray march + Gamma)",
                 "algorithmic_bytes_per_launch": alg[prec], "kernel_avg_ms": round(kern[prec]["avg_ms"], 4)}
     ach64 = alg["fp64"] / (kern["fp64"]["avg_ms"] * 1e-3) / 1e9
@@ -783,10 +883,9 @@ def main():
     if not args.no_serve and not args.rates_only:
         log(f"[bench] batched launch: 256 instances of 2^14 targets")
         batch_stats = batch_bench()
-        serve_stats = []
-        for lam in (float(v) for v in args.serve_rates.split(",") if v):
-            log(f"[bench] serving: Poisson arrivals at {lam}/s, {args.serve_requests} requests")
-            serve_stats.append(serve_bench(lam, args.serve_requests))
+        rates_list = [float(v) for v in args.serve_rates.split(",") if v]
+        serve_stats = serve_bench(rates_list, args.serve_window, args.serve_max_requests, args.serve_scenes,
+                                  log_fn=log)
 
     kion_stats = None
     if not args.rates_only:
@@ -830,8 +929,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline and not args.rates_only:
-        log(f"[bench] CPU baseline (oracle) on {args.cpu_sample} sampled targets")
-        cpu = cpu_baseline(w, args.cpu_sample)
+        log("[bench] CPU baseline (oracle) on the whole workload")
+        cpu = cpu_baseline(w)
 
     ms_step = result.get("ms_per_step", rates["fp32c"]["ms_per_call"])
     line = {
@@ -845,10 +944,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64+f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "n_targets": w.n_tgt, "n_sources": w.n_src,
-                   "grid": 1 << w.grid_log2, "theta_crit": theta, "precision": "fp32c (fp64 opening test)",
+                   "grid": 1 << w.grid_log2, "theta_crit": theta, "precision": "fp32c: fp64 opening test, ray geometry and column sums; fp32 grid values, exp, terms and Kahan-compensated Gamma",
                    "step": "tree build and gas grid (concurrent, start_build_scene) + target order + walk/march/Gamma"
                    if not args.rates_only else "rate call only"},
         "roofline": roofline,

@@ -88,6 +88,7 @@ class Request:
     t_done: float = 0.0
     future: Optional[Future] = None
     solo: bool = False       # run alone (its batch failed once)
+    cold: bool = False       # waited for its scene's build
 
     @property
     def n_t(self):
@@ -290,6 +291,8 @@ class Server:
         self.scene_cost: dict = {}
         self.scene_users: collections.Counter = collections.Counter()
         self.used = 0                  # bytes: resident scenes + admitted requests
+        self.builds = 0                # scene builds queued
+        self.evictions = 0             # resident scenes freed for room
         self.next_id = 0
         self.completed: list = []
         self.errors: list = []
@@ -352,6 +355,17 @@ class Server:
             self.jobs_cv.notify()
         if self.builder is not None:
             self.builder.join()
+
+    def close(self):
+        """Stops the server and frees every resident scene."""
+        self.stop()
+        with self.lock:
+            handles = [h for h in self.scenes.values() if h is not _BUILDING]
+            self.scenes.clear()
+            self.scene_cost.clear()
+        for h in handles:
+            self.ex.free_scene(h)
+        self.used = sum(self.ex.request_bytes(r) for r in self.ready)
 
     def drain(self, timeout: float = 600.0):
         """Waits until every submitted request has completed."""
@@ -456,10 +470,12 @@ class Server:
                 self.scene_cost[key] = self.ex.scene_bytes(r.scene)
                 self.used += self.scene_cost[key]
                 self._queue_job(("build", r.scene))
+                self.builds += 1
             self.scenes.move_to_end(key)
             self.scene_users[key] += 1
             self.used += self.ex.request_bytes(r)
             if self.scenes[key] is _BUILDING:
+                r.cold = True
                 self.waiting[key].append(r)
             else:
                 self.ready.append(r)
@@ -473,6 +489,7 @@ class Server:
             if self.scene_users[key] > 0 or self.scenes[key] is _BUILDING:
                 continue
             self._queue_job(("free", self.scenes.pop(key)))
+            self.evictions += 1
             cost = self.scene_cost.pop(key)
             self.used -= cost
             freed += cost
@@ -568,7 +585,13 @@ class Server:
             return {}
         n_t = sum(r.n_t for r in ok)
         span = max(r.t_done for r in ok) - min(r.t_submit for r in ok)
-        return {"requests": int(lat.size), "failed": len(self.completed) - len(ok),
-                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                "mean_ms": float(lat.mean() * 1e3),
-                "targets_per_s": float(n_t / span) if span > 0 else None, "span_s": float(span)}
+        out = {"requests": int(lat.size), "failed": len(self.completed) - len(ok),
+               "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+               "mean_ms": float(lat.mean() * 1e3),
+               "targets_per_s": float(n_t / span) if span > 0 else None, "span_s": float(span)}
+        for name, sel in (("warm", [not r.cold for r in ok]), ("cold", [r.cold for r in ok])):
+            v = lat[np.array(sel, dtype=bool)]
+            if v.size:
+                out[name] = {"requests": int(v.size), "p50_ms": float(np.percentile(v, 50) * 1e3),
+                             "p99_ms": float(np.percentile(v, 99) * 1e3)}
+        return out
