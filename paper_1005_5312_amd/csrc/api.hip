@@ -524,7 +524,7 @@ start_status start_build_scene(start_ctx *ctx, const start_box *box, int64_t n_s
     if (gst == START_ENOMEM && c.budget) gst = START_EBUDGET;
     if (tst || gst) {
         if (have_tree) dfree(&c, t->t.keys, t->t.bytes);
-        if (!gst) dfree(&c, g->g.val, g->g.bytes);
+        if (!gst) dfree(&c, g->g.mem, g->g.bytes);
         delete t;
         delete g;
         if (tst) {
@@ -545,7 +545,7 @@ start_status start_grid_free(start_ctx *ctx, start_grid *grid)
     if (!grid) return START_OK;
     hipSetDevice(ctx->c.device);
     hipStreamSynchronize(ctx->c.stream);
-    dfree(&ctx->c, grid->g.val, grid->g.bytes);
+    dfree(&ctx->c, grid->g.mem, grid->g.bytes);
     delete grid;
     return START_OK;
 }
@@ -876,7 +876,7 @@ start_status start_ionization_equilibrium(start_ctx *ctx, const start_tree *tree
     auto cleanup = [&](start_status code) {
         hipStreamSynchronize(c.stream);
         if (have_bins) free_bins(&c, &bins);
-        if (have_grid) dfree(&c, grid.val, grid.bytes);
+        if (have_grid) dfree(&c, grid.mem, grid.bytes);
         dfree(&c, nhi, nhi_bytes);
         return code;
     };
@@ -1023,7 +1023,7 @@ start_status start_diffuse_equilibrium(start_ctx *ctx, const start_box *box, int
         hipStreamSynchronize(s);
         free_tree();
         if (have_bins) free_bins(&c, &bins);
-        if (have_grid) dfree(&c, grid.val, grid.bytes);
+        if (have_grid) dfree(&c, grid.mem, grid.bytes);
         for (auto &b : bufs) dfree(&c, b.first, b.second);
         return code;
     };

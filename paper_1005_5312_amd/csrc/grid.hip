@@ -625,13 +625,17 @@ start_status alloc_grid(Ctx *c, const start_box &box, int grid_log2, Grid *g)
     g->sy = G + pad;
     g->sx = G * g->sy + pad;
     g->span = (int64_t)(G - 1) * g->sx + (int64_t)(G - 1) * g->sy + G;
-    size_t persist = al(g->span * sizeof(double)) + al(g->span * sizeof(float));
+    g->guard = G <= 512 ? 6 * ((int64_t)g->sx + g->sy + 1) : 0;
+    const int64_t held = g->span + 2 * g->guard;
+    size_t persist = al(held * sizeof(double)) + al(held * sizeof(float));
     char *pm = nullptr;
     if (dmalloc(c, (void **)&pm, persist) != hipSuccess) return START_ENOMEM;
     g->bytes = persist;
-    g->val = (double *)pm;
-    g->valf = (float *)(pm + al(g->span * sizeof(double)));
-    if (pad) hipMemsetAsync(pm, 0, persist, c->stream);   // the padding is never written again
+    g->mem = pm;
+    g->val = (double *)pm + g->guard;
+    g->valf = (float *)(pm + al(held * sizeof(double))) + g->guard;
+    // guards and padding are never written again
+    if (pad || g->guard) hipMemsetAsync(pm, 0, persist, c->stream);
     return START_OK;
 }
 
@@ -644,7 +648,7 @@ start_status build_grid(Ctx *c, const start_box &box, int64_t n, const double *x
     st = bin_gas(c, box, n, xyz, h, nhi, grid_log2, &b);
     if (st) {
         hipStreamSynchronize(c->stream);   // the padding clear may still run
-        dfree(c, g->val, g->bytes);
+        dfree(c, g->mem, g->bytes);
         return st;
     }
     fill_grid(c, b, nullptr, g);   // the binning already gathered n_HI
@@ -652,7 +656,7 @@ start_status build_grid(Ctx *c, const start_box &box, int64_t n, const double *x
     free_bins(c, &b);
     if (e != hipSuccess) {
         c->err = hipGetErrorString(e);
-        dfree(c, g->val, g->bytes);
+        dfree(c, g->mem, g->bytes);
         return START_EHIP;
     }
     return START_OK;

@@ -100,14 +100,23 @@ struct Tree {
 // strides the lanes of a gather that sit in neighbouring rows or planes hit
 // the same L1 tag banks, and the padded grid marches ~5% faster (FP32
 // offsets stay below 2^32 up to G = 512; G = 1024 is left unpadded).
+//
+// Each copy also has `guard` zeroed elements before its first and after its
+// last cell (G <= 512): a march may step up to 4 cells per axis past its
+// target before it stops (its last turn runs to the end), and those reads
+// land in the guard band instead of needing a clamp on every step.  G = 1024
+// has no guard (its FP32 byte offsets already use all 32 bits) and its
+// marches clamp the offset.
 struct Grid {
     start_box box;
     int grid_log2 = 0;
     int G = 1;
     int sx = 1, sy = 1;        // element strides of x and y
-    int64_t span = 1;          // elements held (padding included, zeroed)
-    double *val = nullptr;     // FP64 values
-    float *valf = nullptr;     // FP32 copy
+    int64_t span = 1;          // elements of the cells (padding included, zeroed)
+    int64_t guard = 0;         // zeroed elements before and after the cells
+    void *mem = nullptr;       // the allocation (both copies with their guards)
+    double *val = nullptr;     // FP64 values (cell 0)
+    float *valf = nullptr;     // FP32 copy (cell 0)
     size_t bytes = 0;
 };
 
@@ -215,6 +224,7 @@ struct BatchLaunch {
     int64_t n_tiles;
     int64_t n64;     // tiles of FP64 items (first)
     int mode;
+    bool clamp;      // some grid has no guard band: clamp the march offsets
 };
 // Stages a batch (host tables, upload, target sort) and launches it; the
 // launch is described in *launch when non-null.

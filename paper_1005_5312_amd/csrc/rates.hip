@@ -60,6 +60,7 @@ struct Item {
     int G;
     int grid_log2;
     int sx, sy;         // element strides of the grid copies (padded rows and planes)
+    int64_t guard;      // zeroed elements before cell 0 (and after the last cell)
     double frac_scale;  // 2^-(32 - grid_log2)
     double gs;          // G / size
     double lo[3];
@@ -219,7 +220,7 @@ __device__ inline double load_cell(const double *grid, unsigned idx)
     return *((const __attribute__((address_space(1))) double *)grid + idx);
 }
 
-template <typename TV, bool STATS>
+template <typename TV, bool STATS, bool CLAMP>
 __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned last, unsigned idx0,
                            const double fb[3], const double D[3], int &ncell)
 {
@@ -266,7 +267,7 @@ __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned
         tn[1] = fma(s1 ? 1.0 : 0.0, a[1], tn[1]);
         tn[2] = fma(s2 ? 1.0 : 0.0, a[2], tn[2]);
         off += (s0 ? (unsigned)ds[0] : 0u) + (s1 ? (unsigned)ds[1] : 0u) + (s2 ? (unsigned)ds[2] : 0u);
-        off = off > off_max ? off_max : off;   // also catches a step below 0
+        if (CLAMP) off = off > off_max ? off_max : off;   // also catches a step below 0
         vnext = load_cell(grid, off);
         m = min3(tn[0], tn[1], tn[2]);
     };
@@ -294,7 +295,7 @@ __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned
             tn[1] = fma(s1 ? 1.0 : 0.0, a[1], tn[1]);
             tn[2] = fma(s2 ? 1.0 : 0.0, a[2], tn[2]);
             off += (s0 ? (unsigned)ds[0] : 0u) + (s1 ? (unsigned)ds[1] : 0u) + (s2 ? (unsigned)ds[2] : 0u);
-            off = off > off_max ? off_max : off;   // also catches a step below 0
+            if (CLAMP) off = off > off_max ? off_max : off;   // also catches a step below 0
             vnext = load_cell(grid, off);
             m = min3(tn[0], tn[1], tn[2]);
         };
@@ -420,8 +421,23 @@ __global__ void __launch_bounds__(kThreads) list_kernel(const Item *__restrict__
 // ---------------------------------------------------------------------------
 constexpr int kRing = 128;   // items; a node adds <= 64 and a batch drains 64
 
-// TF: the target's fraction inside its cell, FP64 for the FP64 path and
-// 32-bit fixed point (2^-32 cell) for the FP32 path, which halves that array.
+// 32-bit fixed point of the box: floor(u 2^32) of the normalised coordinate
+// u in [0, 1] (1 itself to 2^32 - 1).  The FP32 path encodes the virtual
+// sources and the targets alike, so a target at a source's position is at
+// distance 0 exactly (both skipped as in the FP64 path); positions closer
+// than 2^-32 of the box count as the same.  The top g bits of a coordinate
+// are its cell on a 2^g grid, the rest the fraction inside it (exact in FP64).
+__device__ inline unsigned fixed32(double x, double lo, double inv)
+{
+    double u = (x - lo) * inv;
+    u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+    const double q = floor(u * 4294967296.0);
+    return q >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned)q;
+}
+
+// TF: the target's fraction inside its cell in FP64 for the FP64 path; for
+// the FP32 path its 32-bit box fixed-point coordinates (fixed32; tcell is
+// then unused).
 template <typename T, typename TF>
 struct WaveLds {
     uint64_t rec_mask[kRing];     // per node: lanes that took it
@@ -429,23 +445,15 @@ struct WaveLds {
     int rec_start[kRing];         // per node: first slot (absolute) of its items
     T term[kRing];
     unsigned tcell[kWave];        // target cell, linear index
-    TF tfrac[kWave][3];           // target fraction inside its cell
+    TF tfrac[kWave][3];           // target fraction inside its cell (FP64), or fixed32 coordinates
     unsigned char lane[kRing];    // target lane of the item
 };
 
-__device__ inline double frac_of(double f) { return f; }
-__device__ inline double frac_of(unsigned f) { return (double)f * 0x1p-32; }
-__device__ inline void store_frac(double &d, double f) { d = f; }
-__device__ inline void store_frac(unsigned &d, double f)
-{
-    const double q = floor(f * 4294967296.0);
-    d = q >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned)q;
-}
 
-template <int PREC, bool STATS, typename T, typename TF>
+template <int PREC, bool STATS, bool CLAMP, typename T, typename TF>
 __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveLds<T, TF> &L, int *lds_ncell);
 
-template <int PREC, bool STATS>
+template <int PREC, bool STATS, bool CLAMP>
 __global__ void __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(PREC == START_FP64 ? 5 : 7))) rates_kernel(const Item *__restrict__ items,
                                                          const int4 *__restrict__ tiles, int n_tiles)
@@ -466,10 +474,10 @@ __attribute__((amdgpu_waves_per_eu(PREC == START_FP64 ? 5 : 7))) rates_kernel(co
     if (ti >= n_tiles) return;
     const int4 tile = tiles[ti];
     const int item = __builtin_amdgcn_readfirstlane(tile.x);
-    rates_tile<PREC, STATS, T, TF>(items[item], tile, lds_all[wv], ncell_all[STATS ? wv : 0]);
+    rates_tile<PREC, STATS, CLAMP, T, TF>(items[item], tile, lds_all[wv], ncell_all[STATS ? wv : 0]);
 }
 
-template <int PREC, bool STATS, typename T, typename TF>
+template <int PREC, bool STATS, bool CLAMP, typename T, typename TF>
 __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveLds<T, TF> &L, int *lds_ncell)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -479,7 +487,11 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
 
     const int G = P.G;
     const int gl = P.grid_log2;
-    const int last = (G - 1) * (P.sx + P.sy + 1);   // element of the last cell
+    // the march addresses the grid from the start of its guard band, which
+    // takes the steps past a ray's end (CLAMP: G = 1024, no band, offsets
+    // clamped to the last cell's element)
+    const int64_t guard = P.guard;
+    const int last = (G - 1) * (P.sx + P.sy + 1);
     double u[3] = {0.0, 0.0, 0.0};
     unsigned orig = 0;
     int self = -1;   // source indices fit in 31 bits (n_s <= 2^30)
@@ -502,9 +514,16 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             }
         }
         L.tcell[lane] = (unsigned)((bi[0] * G + bi[1]) * G + bi[2]);
-        store_frac(L.tfrac[lane][0], fb[0]);
-        store_frac(L.tfrac[lane][1], fb[1]);
-        store_frac(L.tfrac[lane][2], fb[2]);
+        if constexpr (PREC == START_FP64) {
+            L.tfrac[lane][0] = fb[0];
+            L.tfrac[lane][1] = fb[1];
+            L.tfrac[lane][2] = fb[2];
+        } else {
+            const double4 p = valid ? P.tgt[it] : make_double4(P.lo[0], P.lo[1], P.lo[2], 0.0);
+            L.tfrac[lane][0] = fixed32(p.x, P.lo[0], P.inv_size);
+            L.tfrac[lane][1] = fixed32(p.y, P.lo[1], P.inv_size);
+            L.tfrac[lane][2] = fixed32(p.z, P.lo[2], P.inv_size);
+        }
     }
 
     T acc = T(0), accc = T(0);
@@ -517,10 +536,24 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
     auto march_item = [&](int slot, T &term, int &nc) {
         const int code = L.code[slot];
         const int tl = L.lane[slot];
-        const unsigned tcell = L.tcell[tl];
-        const double fb[3] = {frac_of(L.tfrac[tl][0]), frac_of(L.tfrac[tl][1]), frac_of(L.tfrac[tl][2])};
-        const int tb[3] = {(int)(tcell >> (2 * gl)), (int)((tcell >> gl) & (unsigned)(G - 1)),
-                           (int)(tcell & (unsigned)(G - 1))};
+        int tb[3];
+        double fb[3];
+        if constexpr (PREC == START_FP64) {
+            const unsigned tcell = L.tcell[tl];
+            tb[0] = (int)(tcell >> (2 * gl));
+            tb[1] = (int)((tcell >> gl) & (unsigned)(G - 1));
+            tb[2] = (int)(tcell & (unsigned)(G - 1));
+#pragma unroll
+            for (int k = 0; k < 3; ++k) fb[k] = L.tfrac[tl][k];
+        } else {
+            const unsigned fmask = (1u << sh) - 1u;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const unsigned q = L.tfrac[tl][k];
+                tb[k] = (int)(q >> sh);
+                fb[k] = (double)(q & fmask) * P.frac_scale;
+            }
+        }
         // the ray runs from the (virtual) source (t = 0) to the target (t = 1):
         // D = target - source, the march starts in the source's cell
         double D[3], fa[3];
@@ -553,13 +586,18 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
         }
         const double d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
         if (d2 > 0.0) {
-            const unsigned e0 = (unsigned)(ab[0] * P.sx + ab[1] * P.sy + ab[2]);
-            const T col = march<T, STATS>(PREC == START_FP64 ? (const T *)P.grid : (const T *)P.gridf, P.sx, P.sy,
-                                          (unsigned)last, e0, fa, D, nc);
-            const T dist = (T)sqrt(d2);                        // grid units
+            const unsigned e0 = (unsigned)(ab[0] * P.sx + ab[1] * P.sy + ab[2] + guard);
+            const T *base = (PREC == START_FP64 ? (const T *)P.grid : (const T *)P.gridf) - guard;
+            const T col = march<T, STATS, CLAMP>(base, P.sx, P.sy, (unsigned)(last + guard), e0, fa, D, nc);
+            // FP32C: the term from the hardware square root, exp2 and
+            // reciprocal (each ~1 ulp; the argument of exp2 is rounded to
+            // ~6e-8 relative, i.e. 6e-8 tau of the term), FP64 as written
+            const T dist = PREC == START_FP64 ? (T)sqrt(d2) : (T)__builtin_amdgcn_sqrtf((float)d2);   // grid units
             const T c = col_scale * (col * dist);
-            if (P.channel == 0)
-                term = w * exp(-c) / (T)d2;                    // c = tau
+            if (P.channel == 0)                                // c = tau
+                term = PREC == START_FP64 ? w * exp(-c) / (T)d2
+                                          : (T)(w * __builtin_amdgcn_exp2f((float)c * -1.44269504f) *
+                                                __builtin_amdgcn_rcpf((float)d2));
             else
                 term = w * fsh(c) / (T)d2;                     // c = N_H2 / 1e14
         } else {
@@ -758,18 +796,9 @@ __global__ void __launch_bounds__(kThreads) batch_gather(int64_t n, const int64_
 }
 
 
-// FP32-path copies of the virtual sources: the centre as 32-bit fixed-point
-// coordinates of the box (resolution 2^-32 of the side, so the source end of
-// every ray is placed to ~1e-8 cell in FP32 arithmetic) and the luminosity
-// relative to the root's (every L' <= 1).
-__device__ inline unsigned fixed32(double x, double lo, double inv)
-{
-    double u = (x - lo) * inv;
-    u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
-    const double q = floor(u * 4294967296.0);
-    return q >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned)q;
-}
-
+// FP32-path copies of the virtual sources (fixed32 above, with the targets'
+// encoding): the centre as 32-bit fixed-point coordinates of the box and the
+// luminosity relative to the root's (every L' <= 1).
 __global__ void __launch_bounds__(kThreads) make_fp32_nodes(int64_t m, const double4 *mom, const double *lscale,
                                                             start_box box, double inv, uint4 *momq)
 {
@@ -855,11 +884,21 @@ BatchScratch carve_batch(void *base, int64_t n, int n_items, int64_t n_tiles)
 }
 
 template <int PREC, bool STATS>
-void launch_tiles(const Item *items, const int4 *tiles, int64_t n_tiles, hipStream_t s)
+void launch_tiles(const Item *items, const int4 *tiles, int64_t n_tiles, bool clamp, hipStream_t s)
 {
     int64_t blocks = (n_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks >= 64) blocks = (blocks + 7) / 8 * 8;   // whole rounds over the 8 XCDs
-    rates_kernel<PREC, STATS><<<(unsigned)blocks, kThreads, 0, s>>>(items, tiles, (int)n_tiles);
+    if (clamp) rates_kernel<PREC, STATS, true><<<(unsigned)blocks, kThreads, 0, s>>>(items, tiles, (int)n_tiles);
+    else rates_kernel<PREC, STATS, false><<<(unsigned)blocks, kThreads, 0, s>>>(items, tiles, (int)n_tiles);
+}
+
+// Whether any item's grid has no guard band (G = 1024): the launch then
+// clamps every march step.
+bool needs_clamp(const RateSpec *specs, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (specs[i].grid && specs[i].grid->guard == 0) return true;
+    return false;
 }
 
 }  // namespace
@@ -911,6 +950,7 @@ Item make_item(const RateSpec &r, const BatchScratch &bs, int64_t off)
         I.grid_log2 = g->grid_log2;
         I.sx = g->sx;
         I.sy = g->sy;
+        I.guard = g->guard;
     } else {
         I.G = 1;
         I.grid_log2 = 0;
@@ -943,7 +983,7 @@ Item make_item(const RateSpec &r, const BatchScratch &bs, int64_t off)
 
 // Device part of a batch whose tables are in place: target keys, sort and
 // gather, then the kernels of the mode.
-void launch_staged(const BatchScratch &bs, int64_t N, int n, int64_t n_tiles, int64_t n64, int mode,
+void launch_staged(const BatchScratch &bs, int64_t N, int n, int64_t n_tiles, int64_t n64, int mode, bool clamp,
                    unsigned *flags, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, BatchLaunch *launch)
 {
     if (N == 0) return;
@@ -961,7 +1001,7 @@ void launch_staged(const BatchScratch &bs, int64_t N, int n, int64_t n_tiles, in
         else list_kernel<kKeys><<<lb, kThreads, 0, s>>>(bs.items, bs.tiles, (int)n_tiles);
         return;
     }
-    BatchLaunch bl{bs.items, bs.tiles, n_tiles, n64, mode};
+    BatchLaunch bl{bs.items, bs.tiles, n_tiles, n64, mode, clamp};
     if (launch) *launch = bl;
     if (ev0) hipEventRecord(ev0, s);
     relaunch_batch(bl, s);
@@ -1026,7 +1066,7 @@ void run_batch(Ctx *c, const RateSpec *specs, int n, int mode, int tile, void *s
         if (specs[i].prec == START_FP64) n64 += (specs[i].n_t + tile - 1) / tile;
     hipMemcpyAsync(bs.items, h, stage_bytes(n, n_tiles), hipMemcpyHostToDevice, s);
     hipEventRecord(c->stage_ev, s);
-    launch_staged(bs, N, n, n_tiles, n64, mode, c->d_flags, s, ev0, ev1, launch);
+    launch_staged(bs, N, n, n_tiles, n64, mode, needs_clamp(specs, n), c->d_flags, s, ev0, ev1, launch);
 }
 
 void run_single_fixed(Ctx *c, const RateSpec &r, int tile, void *scratch)
@@ -1037,20 +1077,20 @@ void run_single_fixed(Ctx *c, const RateSpec &r, int tile, void *scratch)
     const Item I = make_item(r, bs, 0);
     const int64_t nb = (n_tiles + kThreads - 1) / kThreads;
     single_tables<<<(unsigned)(nb > 0 ? nb : 1), kThreads, 0, s>>>(I, tile, n_tiles, bs.items, bs.offsets, bs.tiles);
-    launch_staged(bs, r.n_t, 1, n_tiles, r.prec == START_FP64 ? n_tiles : 0, 0, c->d_flags, s, nullptr, nullptr,
-                  nullptr);
+    launch_staged(bs, r.n_t, 1, n_tiles, r.prec == START_FP64 ? n_tiles : 0, 0, needs_clamp(&r, 1), c->d_flags, s,
+                  nullptr, nullptr, nullptr);
 }
 
 void relaunch_batch(const BatchLaunch &b, hipStream_t s)
 {
     const Item *items = static_cast<const Item *>(b.items);
     if (b.n64 > 0) {
-        if (b.mode == 1) launch_tiles<START_FP64, true>(items, b.tiles, b.n64, s);
-        else launch_tiles<START_FP64, false>(items, b.tiles, b.n64, s);
+        if (b.mode == 1) launch_tiles<START_FP64, true>(items, b.tiles, b.n64, b.clamp, s);
+        else launch_tiles<START_FP64, false>(items, b.tiles, b.n64, b.clamp, s);
     }
     if (b.n_tiles - b.n64 > 0) {
-        if (b.mode == 1) launch_tiles<START_FP32C, true>(items, b.tiles + b.n64, b.n_tiles - b.n64, s);
-        else launch_tiles<START_FP32C, false>(items, b.tiles + b.n64, b.n_tiles - b.n64, s);
+        if (b.mode == 1) launch_tiles<START_FP32C, true>(items, b.tiles + b.n64, b.n_tiles - b.n64, b.clamp, s);
+        else launch_tiles<START_FP32C, false>(items, b.tiles + b.n64, b.n_tiles - b.n64, b.clamp, s);
     }
 }
 
@@ -1061,12 +1101,14 @@ void relaunch_batch(const BatchLaunch &b, hipStream_t s)
 // ---------------------------------------------------------------------------
 namespace {
 
+template <bool CLAMP>
 __global__ void __launch_bounds__(256) upstream_roots(int64_t n_roots, const unsigned *__restrict__ roots,
                                                       const uint64_t *__restrict__ keys,
                                                       const unsigned *__restrict__ owner, const double *__restrict__ xyz,
                                                       int64_t n, const double4 *__restrict__ mom,
                                                       const double4 *__restrict__ src, const int *__restrict__ first,
-                                                      const double *__restrict__ grid, int G, int sx, int sy, double lo0,
+                                                      const double *__restrict__ grid, int64_t guard, int G, int sx,
+                                                      int sy, double lo0,
                                                       double lo1, double lo2, double gs, double tau_scale,
                                                       double *__restrict__ acc)
 {
@@ -1095,8 +1137,9 @@ __global__ void __launch_bounds__(256) upstream_roots(int64_t n_roots, const uns
         return;
     }
     int nc = 0;
-    const unsigned e0 = (unsigned)(tb[0] * sx + tb[1] * sy + tb[2]);
-    const double col = march<double, false>(grid, sx, sy, (unsigned)((G - 1) * (sx + sy + 1)), e0, fb, D, nc);
+    const unsigned e0 = (unsigned)(tb[0] * sx + tb[1] * sy + tb[2] + guard);
+    const double col = march<double, false, CLAMP>(grid - guard, sx, sy, (unsigned)((G - 1) * (sx + sy + 1) + guard),
+                                                   e0, fb, D, nc);
     acc[p] = tau_scale * (col * sqrt(d2));
 }
 
@@ -1109,9 +1152,15 @@ void launch_upstream_roots(Ctx *c, const Tree *t, const Grid *g, int64_t n_roots
     if (n_roots <= 0) return;
     const double gs = (double)g->G / t->box.size;
     const double tau_scale = sigma * (t->box.size / g->G * t->box.length_unit_cm);
-    upstream_roots<<<(unsigned)((n_roots + 255) / 256), 256, 0, c->stream>>>(
-        n_roots, roots, keys, owner, xyz, n, t->mom, t->src, t->first, g->val, g->G, g->sx, g->sy, t->box.lo[0],
-        t->box.lo[1], t->box.lo[2], gs, tau_scale, acc);
+    const unsigned nb = (unsigned)((n_roots + 255) / 256);
+    if (g->guard == 0)
+        upstream_roots<true><<<nb, 256, 0, c->stream>>>(n_roots, roots, keys, owner, xyz, n, t->mom, t->src, t->first,
+                                                        g->val, g->guard, g->G, g->sx, g->sy, t->box.lo[0],
+                                                        t->box.lo[1], t->box.lo[2], gs, tau_scale, acc);
+    else
+        upstream_roots<false><<<nb, 256, 0, c->stream>>>(n_roots, roots, keys, owner, xyz, n, t->mom, t->src,
+                                                         t->first, g->val, g->guard, g->G, g->sx, g->sy, t->box.lo[0],
+                                                         t->box.lo[1], t->box.lo[2], gs, tau_scale, acc);
 }
 
 }  // namespace start

@@ -488,3 +488,86 @@ def test_autotune_picks_a_tile_and_keeps_results(ctx):
     assert np.array_equal(items[0]["out"].cpu().numpy(), ref)
     again = ctx.compute_rates(tree, grid, items[0]["tgt_xyz"], None, 1.0, w.sigma, "fp32c").cpu().numpy()
     assert np.array_equal(again, ref)
+
+
+def _on_faces_edges_planes(rng, n, size, G):
+    """n points whose coordinates are each, at random, on the lower or upper
+    face of the box, on a grid plane, or anywhere."""
+    p = rng.uniform(0.0, size, (3, n))
+    kind = rng.integers(0, 4, (3, n))
+    plane = np.floor(rng.uniform(0.0, size, (3, n)) / size * G) * (size / G)
+    p = np.where(kind == 0, 0.0, np.where(kind == 1, size, np.where(kind == 2, plane, p)))
+    return np.ascontiguousarray(p)
+
+
+@pytest.mark.parametrize("grid_log2", [4, 6, 7])
+def test_rays_ending_on_faces_edges_and_planes(ctx, grid_log2):
+    """Sources and targets on the box's faces, edges and corners and on grid
+    planes, so that rays end on the grid's boundary and the last turn of a
+    march runs past it (into the grid's guard band), theta 0 and 1, both
+    precisions, against the oracle."""
+    rng = np.random.default_rng(100 + grid_log2)
+    w = H.W.make_clumpy(seed=40 + grid_log2, n_gas=4096, n_src=8)
+    G = 1 << grid_log2
+    print(f"[case] faces, edges and planes, G = {G}", flush=True)
+    src = np.concatenate([w.src_xyz, _on_faces_edges_planes(rng, 40, w.box_size, G)], axis=1)
+    lum = 10.0 ** rng.uniform(47.0, 50.0, src.shape[1])
+    tgt = _on_faces_edges_planes(rng, 400, w.box_size, G)
+    box, obox = H.box_of(w), H.obox_of(w)
+    tree = ctx.build_source_tree(box, dev(src), dev(lum))
+    grid = ctx.build_gas_grid(box, dev(w.gas_xyz), dev(w.gas_h), dev(w.gas_nhi), grid_log2)
+    ot = O.Tree(obox, src, lum)
+    og = O.grid(obox, w.gas_xyz, w.gas_h, w.gas_nhi, grid_log2)
+    for theta in (0.0, 1.0):
+        want = O.rates(ot, grid_log2, og, tgt, None, theta, w.sigma)
+        for prec, tol in (("fp64", H.TOL_FP64), ("fp32c", H.TOL_FP32C)):
+            got = ctx.compute_rates(tree, grid, dev(tgt), None, theta, w.sigma, prec)
+            ctx.synchronize()
+            rel, ab, _ = H.rel_errors(got.cpu().numpy(), want)
+            print(f"  theta {theta} {prec}: max rel {rel:.2e}", flush=True)
+            assert rel <= tol and ab <= H.ABS_FLOOR
+
+
+def test_largest_grids(ctx):
+    """The largest grids: G = 512 (the largest with a guard band) against the
+    oracle, on a sparse field (65536 particles with kernels of 0.6 cells, so
+    the gather stays cheap at 512^3 centres; ~25 optical depths per filled
+    cell), and G = 1024 (no band: the march clamps its offsets) in gas without
+    neutral hydrogen, where the rate has the optically thin closed form
+    L sigma / (4 pi d^2).  Targets also on faces, edges and grid planes."""
+    rng = np.random.default_rng(7)
+    w = H.W.make_small(seed=17, n_gas=1 << 16, n_src=1)
+    src = np.concatenate([np.array([[1.7], [4.1], [2.9]]), np.array([[0.0], [6.6], [6.6]]),
+                          _on_faces_edges_planes(rng, 1, w.box_size, 512)], axis=1)
+    lum = np.array([5e48, 1e49, 2e48])
+    tgt = np.concatenate([rng.uniform(0.0, w.box_size, (3, 300)), _on_faces_edges_planes(rng, 100, w.box_size, 512)],
+                         axis=1)
+    box, obox = H.box_of(w), H.obox_of(w)
+    tree = ctx.build_source_tree(box, dev(src), dev(lum))
+    ot = O.Tree(obox, src, lum)
+    print("[case] G = 512, sparse field", flush=True)
+    h = np.full(w.n_gas, 0.6 * w.box_size / 512)
+    nhi = rng.uniform(0.05, 0.2, w.n_gas)
+    grid = ctx.build_gas_grid(box, dev(w.gas_xyz), dev(h), dev(nhi), 9)
+    og = O.grid(obox, w.gas_xyz, h, nhi, 9)
+    want = O.rates(ot, 9, og, tgt, None, 0.0, w.sigma)
+    del og
+    for prec, tol in (("fp64", H.TOL_FP64), ("fp32c", H.TOL_FP32C)):
+        got = ctx.compute_rates(tree, grid, dev(tgt), None, 0.0, w.sigma, prec)
+        ctx.synchronize()
+        rel, ab, nbig = H.rel_errors(got.cpu().numpy(), want)
+        print(f"  {prec}: max rel {rel:.2e} over {nbig} targets", flush=True)
+        assert rel <= tol and ab <= H.ABS_FLOOR
+    grid.free()
+    print("[case] G = 1024, no neutral gas", flush=True)
+    grid = ctx.build_gas_grid(box, dev(w.gas_xyz), dev(h * 0.5), dev(np.zeros(w.n_gas)), 10)
+    d = np.sqrt(((tgt[:, :, None] - src[:, None, :]) ** 2).sum(axis=0)) * w.length_unit_cm
+    with np.errstate(divide="ignore"):
+        want = np.where(d > 0, lum * w.sigma / (4 * np.pi * d * d), 0.0).sum(axis=1)   # a source at 0 is skipped
+    for prec, tol in (("fp64", 1e-12), ("fp32c", 1e-5)):
+        got = ctx.compute_rates(tree, grid, dev(tgt), None, 0.0, w.sigma, prec)
+        ctx.synchronize()
+        rel = float(np.max(np.abs(got.cpu().numpy().astype(np.float64) / want - 1)))
+        print(f"  {prec}: max rel {rel:.2e}", flush=True)
+        assert rel <= tol
+    grid.free()
