@@ -315,6 +315,31 @@ def batch_bench(n_inst=256, n_p=1 << 14, seed=9, reps=3):
     ctx.synchronize()
     t_single_tuned = (time.perf_counter() - t0) / reps
     n_total = sum(it["tgt_xyz"].shape[1] for it in items)
+    # the same batch staged once and replayed from a HIP graph (a rate plan),
+    # and one instance alone, plain call against its plan
+    plan = ctx.rates_plan(items)
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.launch()
+    ctx.synchronize()
+    t_plan = (time.perf_counter() - t0) / reps
+    plan.free()
+    one = items[:1]
+    plan1 = ctx.rates_plan(one)
+    k1 = 50
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(k1):
+        ctx.compute_rates_batched(one)
+    ctx.synchronize()
+    t_one = (time.perf_counter() - t0) / k1
+    t0 = time.perf_counter()
+    for _ in range(k1):
+        plan1.launch()
+    ctx.synchronize()
+    t_one_plan = (time.perf_counter() - t0) / k1
+    plan1.free()
     # the same batch in plain FP64 (same lists and rays, FP64 grid and sums)
     items64 = [dict(it, prec="fp64", out=torch.empty(it["out"].numel(), dtype=torch.float64, device=dev))
                for it in items]
@@ -337,7 +362,11 @@ def batch_bench(n_inst=256, n_p=1 << 14, seed=9, reps=3):
                           "batched_evals_per_s": n_total / t_batched_tuned,
                           "single_tile_targets": best_single, "one_call_each_ms": t_single_tuned * 1e3,
                           "one_call_each_evals_per_s": n_total / t_single_tuned},
-            "default_tiles": "from the call size: about total targets / 4096, a power of two in [1, 64]"}
+            "default_tiles": "from the call size: about total targets / 4096, a power of two in [1, 64]",
+            "plan_replay": {"batched_ms": t_plan * 1e3, "one_instance_call_ms": t_one * 1e3,
+                            "one_instance_plan_ms": t_one_plan * 1e3,
+                            "what": "the batch (and one 2^14 instance) staged once and its rate kernels replayed "
+                                    "from a HIP graph, against the plain call (host staging, target sort, launch)"}}
 
 
 def equilibrium_bench(n_gas=1 << 21, grid_log2=7, tol=1e-4, max_iter=200):
@@ -726,6 +755,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rates-only", action="store_true",
                     help="time only the rate call (profiling runs)")
+    ap.add_argument("--upstream-only", action="store_true",
+                    help="time only the upstream-particle chain on the clumpy medium (profiling runs)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving and batching measurements")
     ap.add_argument("--serve-rates", default="10,30,100,300,1000", help="Poisson arrival rates swept (requests/s)")
     ap.add_argument("--serve-window", type=float, default=15.0,
@@ -750,6 +781,21 @@ def main():
         log("bench.py needs a GPU")
         sys.exit(1)
     S.lib()   # fail loudly if the HIP library is missing
+    def calibration_copy():
+        # a plain 1 GiB device copy: the reference for the HBM byte counters
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    if args.upstream_only:
+        if args.copy_calibration:
+            calibration_copy()
+        print(json.dumps({"upstream_chain": upstream_bench(reps=max(1, args.steps))}), flush=True)
+        return
 
     log(f"[bench] generating workload {args.workload}")
     w = W.make(args.workload)
@@ -831,13 +877,7 @@ def main():
         log(f"[bench] rates {prec}: {ms:.3f} ms/call, walk kernel avg {tot / max(n, 1):.3f} ms")
 
     if args.copy_calibration:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        calibration_copy()
 
     log("[bench] work counters")
     cnt = {p: ctx.rate_counters(tree, grid, tgt, ss, theta, p) for p in ("fp32c",)}

@@ -229,6 +229,25 @@ typedef struct {
  * compute it) enqueued together on the context stream. */
 start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const start_item *items);
 
+/* A batch staged once and replayed from a HIP graph, for callers that repeat
+ * the same rate problems (a served scene asked again, an iteration that
+ * recomputes the rates after changing the gas): start_rates_plan_create
+ * checks the items as start_compute_rates_batched does, stages the batch
+ * (item and tile tables, the targets' order and a sorted copy of their
+ * positions, in memory the plan owns), runs it once (so the outputs are
+ * written) and captures its rate kernels; start_rates_plan_launch enqueues
+ * that graph on the context stream, which recomputes every output from the
+ * current contents of the trees, grids and self_src arrays, with the target
+ * positions as they were at creation (a changed position needs a new plan).
+ * Trees, grids, self_src and outputs must stay allocated, at the same
+ * addresses and sizes, until start_rates_plan_free.  A plan is used with the
+ * context that made it; launches of one plan on one stream run in order.
+ * Create and free synchronise the context stream; launch is asynchronous. */
+typedef struct start_plan start_plan;
+start_status start_rates_plan_create(start_ctx *ctx, int n_items, const start_item *items, start_plan **out);
+start_status start_rates_plan_launch(start_ctx *ctx, start_plan *plan);
+start_status start_rates_plan_free(start_ctx *ctx, start_plan *plan);
+
 /* Work decomposition of the rate kernels: each wavefront walks the tree for
  * a tile of up to tile_targets targets (one per lane) and marches the rays of
  * that tile 64 at a time.  1 <= tile_targets <= 64 fixes the tile size for

@@ -33,7 +33,8 @@ EXPORTS = ("start_ctx_create", "start_ctx_destroy", "start_last_error", "start_s
            "start_ionization_equilibrium", "start_recombination_emission", "start_total_ionization",
            "start_compute_dissociation_rates", "start_set_tile_targets", "start_autotune_rates",
            "start_set_graph_replay", "start_compute_rates_upstream", "start_diffuse_equilibrium",
-           "start_set_grid_pairs", "start_tree_kernel_luminosity", "start_compute_rates_noalloc")
+           "start_set_grid_pairs", "start_tree_kernel_luminosity", "start_compute_rates_noalloc",
+           "start_rates_plan_create", "start_rates_plan_launch", "start_rates_plan_free")
 
 
 class LibraryMissing(RuntimeError):
@@ -99,6 +100,9 @@ def lib():
         "start_compute_rates": ([P, P, P, i64, P, P, d, d, C.c_int, P], C.c_int),
         "start_compute_rates_noalloc": ([P, P, P, i64, P, P, d, d, C.c_int, P], C.c_int),
         "start_compute_rates_batched": ([P, C.c_int, P], C.c_int),
+        "start_rates_plan_create": ([P, C.c_int, P, P], C.c_int),
+        "start_rates_plan_launch": ([P, P], C.c_int),
+        "start_rates_plan_free": ([P, P], C.c_int),
         "start_estimate_bytes": ([i64, i64, i64, C.c_int, C.c_int], C.c_size_t),
         "start_tree_export": ([P, P, P, P, P, P, P, P], C.c_int),
         "start_interaction_lists": ([P, P, i64, P, P, d, P, P, i64], C.c_int),
@@ -179,6 +183,31 @@ class GasGrid:
     def free(self):
         if self._h:
             lib().start_grid_free(self.ctx._h, self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            if self._h and self.ctx._h:
+                self.free()
+        except Exception:
+            pass
+
+
+class RatePlan:
+    """A staged batch replayed from a HIP graph (start_rates_plan_*): launch()
+    recomputes the outputs the items named.  Keeps the item tensors alive."""
+
+    def __init__(self, ctx, handle, keep):
+        self.ctx, self._h, self._keep = ctx, handle, keep
+
+    def launch(self):
+        cur = self.ctx._enter(*self._keep)
+        self.ctx._check(lib().start_rates_plan_launch(self.ctx._h, self._h), "start_rates_plan_launch")
+        self.ctx._leave(cur)
+
+    def free(self):
+        if self._h:
+            lib().start_rates_plan_free(self.ctx._h, self._h)
             self._h = None
 
     def __del__(self):
@@ -444,6 +473,16 @@ class Context:
         cur = self._enter(*keep)
         self._check(lib().start_compute_rates_batched(self._h, len(items), arr), "start_compute_rates_batched")
         self._leave(cur)
+
+    def rates_plan(self, items) -> RatePlan:
+        """Stages the batch (items as for compute_rates_batched), runs it once
+        and captures its rate kernels; RatePlan.launch() replays them."""
+        arr, keep = self._items(items)
+        cur = self._enter(*keep)
+        h = C.c_void_p()
+        self._check(lib().start_rates_plan_create(self._h, len(items), arr, C.byref(h)), "start_rates_plan_create")
+        self._leave(cur)
+        return RatePlan(self, h, [k for k in keep if k is not None])
 
     def set_graph_replay(self, enable: bool):
         """Replay the equilibrium iterations from a captured HIP graph (default)

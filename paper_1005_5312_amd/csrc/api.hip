@@ -95,6 +95,15 @@ struct start_tree {
 struct start_grid {
     start::Grid g;
 };
+// A staged rate batch and the HIP graph of its rate kernels.
+struct start_plan {
+    start::Ctx *c = nullptr;
+    void *scratch = nullptr;     // item and tile tables, sorted targets
+    size_t bytes = 0;
+    start::BatchLaunch bl{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 using namespace start;
 
@@ -743,7 +752,8 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     return done(st);
 }
 
-start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const start_item *items)
+// Checks the items of a batch and turns the non-empty ones into specs.
+static start_status batch_specs(start_ctx *ctx, int n_items, const start_item *items, std::vector<RateSpec> *specs)
 {
     if (!ctx) return START_EINVAL;
     if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, START_EINVAL, "bad item array");
@@ -754,18 +764,98 @@ start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const star
         if (st) return st;
         if (it.n_t > 0 && !it.gamma_out) return fail(ctx, START_EINVAL, "gamma_out is NULL");
     }
-    std::vector<RateSpec> specs;
-    specs.reserve((size_t)n_items);
+    specs->reserve((size_t)n_items);
     for (int i = 0; i < n_items; ++i) {
         const start_item &it = items[i];
         if (it.n_t == 0) continue;
         RateSpec r = spec_of(it.tree, it.grid, it.n_t, it.tgt_xyz, it.self_src, it.theta_crit, it.sigma_cm2, it.prec);
         r.gamma = it.gamma_out;
-        specs.push_back(r);
+        specs->push_back(r);
     }
-    if (specs.empty()) return START_OK;
+    return START_OK;
+}
+
+start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const start_item *items)
+{
+    std::vector<RateSpec> specs;
+    start_status st = batch_specs(ctx, n_items, items, &specs);
+    if (st || specs.empty()) return st;
     hipSetDevice(ctx->c.device);
     return enqueue(ctx, specs.data(), (int)specs.size(), 0);
+}
+
+start_status start_rates_plan_create(start_ctx *ctx, int n_items, const start_item *items, start_plan **out)
+{
+    if (!out) return ctx ? fail(ctx, START_EINVAL, "out is NULL") : START_EINVAL;
+    *out = nullptr;
+    std::vector<RateSpec> specs;
+    start_status st = batch_specs(ctx, n_items, items, &specs);
+    if (st) return st;
+    Ctx &c = ctx->c;
+    hipSetDevice(c.device);
+    st = start_synchronize(ctx);
+    if (st) return st;
+    start_plan *pl = new (std::nothrow) start_plan;
+    if (!pl) return START_ENOMEM;
+    pl->c = &c;
+    if (specs.empty()) {   // nothing to compute: an empty plan
+        *out = pl;
+        return START_OK;
+    }
+    const int n = (int)specs.size();
+    int64_t total = 0, max_src = 0;
+    batch_size(specs.data(), n, &total, &max_src);
+    const int tile = tile_for(c, total, max_src);
+    const int64_t tiles = batch_tiles(specs.data(), n, tile);
+    pl->bytes = batch_scratch_bytes(total, n, tiles);
+    st = ensure_stage(ctx, batch_stage_bytes(n, tiles));
+    if (st || dmalloc(&c, &pl->scratch, pl->bytes) != hipSuccess) {
+        delete pl;
+        return st ? st : fail(ctx, c.budget ? START_EBUDGET : START_ENOMEM, "plan allocation failed");
+    }
+    // stage and run once (this computes the outputs), then capture the rate
+    // kernels of the staged batch
+    run_batch(&c, specs.data(), n, 0, tile, pl->scratch, nullptr, nullptr, &pl->bl);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        relaunch_batch(pl->bl, c.stream);
+        e = hipStreamEndCapture(c.stream, &pl->graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipStreamSynchronize(c.stream);
+        if (pl->graph) hipGraphDestroy(pl->graph);
+        dfree(&c, pl->scratch, pl->bytes);
+        delete pl;
+        return fail(ctx, START_EHIP, hipGetErrorString(e));
+    }
+    *out = pl;
+    return START_OK;
+}
+
+start_status start_rates_plan_launch(start_ctx *ctx, start_plan *plan)
+{
+    if (!ctx || !plan) return ctx ? fail(ctx, START_EINVAL, "plan is NULL") : START_EINVAL;
+    if (plan->c != &ctx->c) return fail(ctx, START_EINVAL, "plan belongs to another context");
+    if (!plan->exec) return START_OK;
+    hipSetDevice(ctx->c.device);
+    const hipError_t e = hipGraphLaunch(plan->exec, ctx->c.stream);
+    return e == hipSuccess ? START_OK : fail(ctx, START_EHIP, hipGetErrorString(e));
+}
+
+start_status start_rates_plan_free(start_ctx *ctx, start_plan *plan)
+{
+    if (!ctx) return START_EINVAL;
+    if (!plan) return START_OK;
+    if (plan->c != &ctx->c) return fail(ctx, START_EINVAL, "plan belongs to another context");
+    hipSetDevice(ctx->c.device);
+    hipStreamSynchronize(ctx->c.stream);
+    if (plan->exec) hipGraphExecDestroy(plan->exec);
+    if (plan->graph) hipGraphDestroy(plan->graph);
+    dfree(&ctx->c, plan->scratch, plan->bytes);
+    delete plan;
+    return START_OK;
 }
 
 start_status start_equilibrium_update(start_ctx *ctx, int64_t n, const double *n_h, const void *gamma,

@@ -147,6 +147,10 @@ class Executor:
     def free_scene(self, handle: Any) -> None:
         raise NotImplementedError
 
+    def forget_scene(self, key: Any) -> None:
+        """Drops what the executor keeps for a scene that is about to be freed
+        (called from the scheduler thread first)."""
+
     def launch(self, slot: int, batch: list, scenes: dict) -> Any:
         raise NotImplementedError
 
@@ -166,6 +170,11 @@ class GpuExecutor(Executor):
     for every particle; other targets are uploaded through a pinned staging
     buffer per slot, asynchronously on the slot's stream.
 
+    With plans (the default), a request for every particle of a scene is
+    served from a rate plan of that slot (start_rates_plan_*: staged once,
+    then replayed from a HIP graph), kept while the scene is resident; other
+    requests of a batch share one batched call.
+
     Without autotune the library picks the tile size from the call's size.
     With autotune, the first batch of each size class (total targets and
     largest source count, each rounded up to a power of two) up to 2^17
@@ -176,7 +185,7 @@ class GpuExecutor(Executor):
 
     TUNE_MAX_CLASS = 17
 
-    def __init__(self, device: int = 0, n_slots: int = 2, autotune: bool = False):
+    def __init__(self, device: int = 0, n_slots: int = 2, autotune: bool = False, plans: bool = True):
         import torch
 
         from . import binding
@@ -189,13 +198,17 @@ class GpuExecutor(Executor):
         self.autotune = autotune
         self.tuned = [set() for _ in range(n_slots)]
         self.stage = [None] * n_slots    # pinned staging of targets per slot
+        self.plans = plans
+        self.plan_cache = [dict() for _ in range(n_slots)]   # (scene key, prec, theta, sigma) -> (plan, out)
 
     def _est(self, n_t, n_s, n_gas, grid_log2, prec):
         return self.binding.estimate_bytes(n_t, n_s, n_gas, grid_log2, prec)
 
     def scene_bytes(self, scene):
-        # tree, grid and the resident particle positions and own sources
-        return self._est(0, scene.n_src, scene.n_gas, scene.grid_log2, "fp64") + scene.n_gas * (24 + 8)
+        # tree, grid and the resident particle positions and own sources, and
+        # the rate plans of the slots (staging, sorted targets, output)
+        plans = self.n_slots * (self._est(scene.n_gas, 0, 0, 0, "fp64") + scene.n_gas * 8) if self.plans else 0
+        return self._est(0, scene.n_src, scene.n_gas, scene.grid_log2, "fp64") + scene.n_gas * (24 + 8) + plans
 
     def request_bytes(self, req):
         # targets on the device, output, and the rate call's scratch
@@ -218,10 +231,16 @@ class GpuExecutor(Executor):
         tree.free()
         grid.free()
 
+    def forget_scene(self, key):
+        for slot, cache in enumerate(self.plan_cache):
+            for k in [k for k in cache if k[0] == key]:
+                cache.pop(k)[0].free()
+
     def launch(self, slot, batch, scenes):
         t = self.torch
         ctx = self.ctxs[slot]
         items = []
+        outs = [None] * len(batch)
         with t.cuda.stream(ctx.stream):
             uploads = [r for r in batch if r.tgt_xyz is not None]
             total_up = sum(3 * r.n_t for r in uploads)
@@ -230,9 +249,23 @@ class GpuExecutor(Executor):
                 buf = t.empty(max(total_up, 1 << 16), dtype=t.float64, pin_memory=True)
                 self.stage[slot] = buf
             at = 0
-            for r in batch:
+            batched = []
+            for k, r in enumerate(batch):
                 tree, grid, gas, gss = scenes[r.scene.key]
                 dt = t.float64 if r.prec == "fp64" else t.float32
+                if r.tgt_xyz is None and self.plans:
+                    key = (r.scene.key, r.prec, float(r.theta), float(r.sigma))
+                    entry = self.plan_cache[slot].get(key)
+                    if entry is None:   # created (and run once) on first use
+                        out = t.empty(r.n_t, dtype=dt, device=self.dev)
+                        plan = ctx.rates_plan([dict(tree=tree, grid=grid, tgt_xyz=gas, self_src=gss, theta=r.theta,
+                                                    sigma=r.sigma, prec=r.prec, out=out)])
+                        self.plan_cache[slot][key] = (plan, out)
+                    else:
+                        plan, out = entry
+                        plan.launch()
+                    outs[k] = out.to("cpu", non_blocking=True)
+                    continue
                 if r.tgt_xyz is None:
                     xyz, ss = gas, gss
                 else:
@@ -246,15 +279,18 @@ class GpuExecutor(Executor):
                 out = t.empty(r.n_t, dtype=dt, device=self.dev)
                 items.append(dict(tree=tree, grid=grid, tgt_xyz=xyz, self_src=ss, theta=r.theta, sigma=r.sigma,
                                   prec=r.prec, out=out))
-            total = sum(r.n_t for r in batch)
-            n_src = max(r.scene.n_src for r in batch)
-            key = (max(0, (total - 1).bit_length()), max(0, (n_src - 1).bit_length()))
-            if self.autotune and key[0] <= self.TUNE_MAX_CLASS and key not in self.tuned[slot]:
-                ctx.autotune_rates(items, reps=2)
-                self.tuned[slot].add(key)
-            else:
-                ctx.compute_rates_batched(items)
-            outs = [it["out"].to("cpu", non_blocking=True) for it in items]
+                batched.append(k)
+            if items:
+                total = sum(batch[k].n_t for k in batched)
+                n_src = max(batch[k].scene.n_src for k in batched)
+                key = (max(0, (total - 1).bit_length()), max(0, (n_src - 1).bit_length()))
+                if self.autotune and key[0] <= self.TUNE_MAX_CLASS and key not in self.tuned[slot]:
+                    ctx.autotune_rates(items, reps=2)
+                    self.tuned[slot].add(key)
+                else:
+                    ctx.compute_rates_batched(items)
+                for k, it in zip(batched, items):
+                    outs[k] = it["out"].to("cpu", non_blocking=True)
             ev = t.cuda.Event()
             ev.record(ctx.stream)
         return (ctx, ev, items, outs)
@@ -360,6 +396,8 @@ class Server:
         """Stops the server and frees every resident scene."""
         self.stop()
         with self.lock:
+            for key in list(self.scenes.keys()):
+                self.ex.forget_scene(key)
             handles = [h for h in self.scenes.values() if h is not _BUILDING]
             self.scenes.clear()
             self.scene_cost.clear()
@@ -488,6 +526,7 @@ class Server:
                 break
             if self.scene_users[key] > 0 or self.scenes[key] is _BUILDING:
                 continue
+            self.ex.forget_scene(key)
             self._queue_job(("free", self.scenes.pop(key)))
             self.evictions += 1
             cost = self.scene_cost.pop(key)

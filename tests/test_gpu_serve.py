@@ -170,3 +170,35 @@ def test_whole_scene_requests_use_resident_particles():
         want = ctx.compute_rates(tree, grid, d(w.gas_xyz), d(w.self_src), 1.0, w.sigma, p).cpu().numpy()
         assert np.array_equal(o, want)
     ctx.close()
+
+
+def test_whole_scene_plans_with_eviction():
+    """Whole-scene requests served from per-slot rate plans while scenes are
+    evicted and rebuilt under a budget that holds about one of them: every
+    result equals a direct rate call bit for bit."""
+    from paper_1005_5312_amd import binding, serve
+    scenes = []
+    for k, w in enumerate((H.W.make_diffuse(seed=61, n_gas=1 << 13), H.W.make_clumpy(seed=62, n_gas=1 << 13, n_src=64),
+                           H.W.make_small(seed=63, n_gas=1 << 13, n_src=1))):
+        scenes.append((serve.Scene(("s", k), H.box_of(w), w.src_xyz, w.src_lum, w.gas_xyz, w.gas_h, w.gas_nhi,
+                                   w.grid_log2, self_src=w.self_src), w))
+    ex = serve.GpuExecutor(0, n_slots=2)
+    need = max(ex.scene_bytes(s) + ex.request_bytes(serve.Request(s, None)) for s, _ in scenes)
+    srv = serve.Server(ex, hbm_budget=int(need * 1.3), max_batch=4).start()
+    order = [0, 1, 0, 2, 1, 1, 0, 2, 2, 0]
+    futs = [srv.submit(serve.Request(scenes[k][0], None, theta=1.0, sigma=6.3e-18,
+                                     prec="fp64" if j % 2 else "fp32c")) for j, k in enumerate(order)]
+    outs = [f.result(timeout=120) for f in futs]
+    srv.drain()
+    assert srv.evictions > 0
+    srv.close()
+    ctx = binding.Context(0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    for j, (k, o) in enumerate(zip(order, outs)):
+        sc, w = scenes[k]
+        tree = ctx.build_source_tree(sc.box, d(w.src_xyz), d(w.src_lum))
+        grid = ctx.build_gas_grid(sc.box, d(w.gas_xyz), d(w.gas_h), d(w.gas_nhi), w.grid_log2)
+        ss = None if w.self_src is None else d(w.self_src)
+        want = ctx.compute_rates(tree, grid, d(w.gas_xyz), ss, 1.0, 6.3e-18, "fp64" if j % 2 else "fp32c")
+        assert np.array_equal(o, want.cpu().numpy())
+    ctx.close()
