@@ -98,7 +98,7 @@ def counters_from_profiles(workload, prec, sha):
     if vals.get("source_sha") != sha:
         return None
     try:
-        return {k: float(v) for k, v in vals.items() if k != "source_sha"}
+        return {k: float(v) for k, v in vals.items() if not k.endswith("source_sha")}
     except ValueError:
         return None
 
