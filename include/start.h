@@ -204,8 +204,11 @@ start_status start_compute_dissociation_rates(start_ctx *ctx, const start_tree *
  * upstream particle of each pair in the order of start_interaction_lists, or
  * -1; n_roots_out (host, may be NULL) the number of pairs integrated along
  * the ray.  Synchronous; allocates its work arrays (about 40 bytes per list
- * entry) for the duration of the call.  More than 2^31 list entries ->
- * START_ECAPACITY. */
+ * entry, 40 bytes per neighbour pair, and a membership table of
+ * n_gas * ceil((n_nodes + n_src) / 32) 32-bit words where that takes at most
+ * max(8 bytes per list entry, 64 MiB) and 4 GiB; larger trees search the
+ * neighbours' sorted lists instead, with the same result) for the duration of
+ * the call.  More than 2^31 list entries -> START_ECAPACITY. */
 start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree, const start_grid *grid,
                                           int64_t n_gas, const double *gas_xyz, const double *gas_h,
                                           const double *gas_nhi, const int64_t *self_src, double theta_crit,

@@ -668,6 +668,26 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     if (st) return done(st);
     if (!upstream_pairs_fit(total)) return done(fail(ctx, START_ECAPACITY, "more than 2^31 - 1 list entries"));
     const int64_t E = (int64_t)total;
+    // the pairs' layout: each particle's list contiguous, the lists in the
+    // Morton order of the particles, so that the lists of neighbours (searched
+    // for each pair) and a pair's upstream pair (read in every jumping round)
+    // lie close to the pair; sl[i] = (first pair, count)
+    uint64_t *mk = (uint64_t *)alloc((size_t)n * sizeof(uint64_t));
+    unsigned *perm = (unsigned *)alloc((size_t)n * sizeof(unsigned));
+    void *radix_tmp = alloc(radix_temp_bytes(n));
+    unsigned *lc = (unsigned *)alloc((size_t)(n + 1) * sizeof(unsigned));
+    uint2 *sl = (uint2 *)alloc((size_t)n * sizeof(uint2));
+    int64_t *first_pair = (int64_t *)alloc((size_t)n * sizeof(int64_t));
+    unsigned *kflags = (unsigned *)alloc(256);
+    if (!mk || !perm || !radix_tmp || !lc || !sl || !first_pair || !kflags) return nomem();
+    hipMemsetAsync(kflags, 0, sizeof(unsigned), s);
+    launch_keys(tree->t.box, n, gas_xyz, nullptr, mk, perm, kflags, s);
+    radix_sort_pairs(mk, perm, n, 63, radix_tmp, s);
+    launch_layout_counts(&c, n, perm, off64, lc);
+    hipMemsetAsync(lc + n, 0, sizeof(unsigned), s);
+    exclusive_scan_u32(lc, n + 1, scan_tmp, s);
+    launch_layout_starts(&c, n, perm, lc, sl, first_pair);
+    // the offsets of the export (lists in particle order)
     launch_to_u32(&c, n, off64, off);
     hipMemsetAsync(off + n, 0, sizeof(unsigned), s);
     exclusive_scan_u32(off, n + 1, scan_tmp, s);
@@ -685,29 +705,46 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     if (!keys || !owner || !par || !links || !acc || !roots || !words || !nbc) return nomem();
     // 2. the lists as sorted keys, and the owner of every pair
     r.counts = nullptr;
-    r.offsets = off64;
+    r.offsets = first_pair;
     r.entries = (int64_t *)keys;
     st = enqueue(ctx, &r, 1, 4);
     if (st) return done(st);
-    launch_pair_owner(&c, n, off, owner);
+    launch_pair_owner(&c, n, sl, owner);
     // 3. neighbours within 2h (particles binned on the grid's cells)
     st = bin_gas(&c, tree->t.box, n, gas_xyz, gas_h, gas_nhi, grid->g.grid_log2, &bins);
     if (st) return done(st == START_ENOMEM && c.budget ? START_EBUDGET : st);
     have_bins = true;
-    launch_neighbours(&c, bins, n, gas_xyz, gas_h, nbc, nullptr, nullptr, nullptr);
+    launch_neighbours(&c, bins, n, perm, gas_xyz, gas_h, sl, nbc, nullptr, nullptr);
     hipMemsetAsync(nbc + n, 0, sizeof(unsigned), s);
     exclusive_scan_u32(nbc, n + 1, scan_tmp, s);
     unsigned n_nb = 0;
     hipMemcpyAsync(&n_nb, nbc + n, sizeof(unsigned), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "neighbour count failed"));
-    unsigned *nb = (unsigned *)alloc((size_t)(n_nb > 0 ? n_nb : 1) * sizeof(unsigned));
-    unsigned *nbs = (unsigned *)alloc((size_t)(n_nb > 0 ? n_nb : 1) * sizeof(unsigned));
-    if (!nb || !nbs) return nomem();
-    launch_neighbours(&c, bins, n, gas_xyz, gas_h, nullptr, nbc, nb, nbs);
-    // 4. upstream pair of every pair, its step, and the roots
+    void *nrec = alloc((size_t)(n_nb > 0 ? n_nb : 1) * neighbour_record_bytes());
+    if (!nrec) return nomem();
+    launch_neighbours(&c, bins, n, perm, gas_xyz, gas_h, sl, nullptr, nbc, nrec);
+    // 4. upstream pair of every pair, its step, and the roots.  Membership of
+    // a source in a neighbour's list comes from a bit table (one row of
+    // n_nodes + n_src bits per particle) where that table is small beside
+    // the pair arrays (at most 8 bytes per pair, or 64 MiB); otherwise, or
+    // if it cannot be allocated, from searches of the sorted lists.
+    unsigned *bits = nullptr;
+    unsigned W = 0;
+    {
+        const int64_t ids = tree->t.n_nodes + tree->t.n_src;
+        const int64_t w = (ids + 31) / 32;
+        const double table = (double)n * (double)w * 4.0;
+        if (table <= std::max(8.0 * (double)E, 64.0 * 1048576.0) && table <= 4.0 * 1073741824.0) {
+            bits = (unsigned *)alloc((size_t)n * (size_t)w * sizeof(unsigned));
+            if (bits) {
+                W = (unsigned)w;
+                launch_member_bits(&c, &tree->t, n, E, keys, sl, owner, W, bits);
+            }
+        }
+    }
     hipMemsetAsync(words, 0, 256, s);
-    launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, off, keys, owner, nbc, nb, nbs, bins.pos_h, sigma_cm2,
-                           par, acc, roots, words);
+    launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, sl, keys, owner, nbc, nrec, bits, W, sigma_cm2, par,
+                           acc, roots, words);
     unsigned n_roots = 0;
     hipMemcpyAsync(&n_roots, words, sizeof(unsigned), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "upstream search failed"));
@@ -731,7 +768,7 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
         launch_unpack_acc(&c, E, la, acc);
     }
     // 7. the rates
-    launch_upstream_gamma(&c, &tree->t, n, gas_xyz, off, keys, acc, sigma_cm2, gamma_out);
+    launch_upstream_gamma(&c, &tree->t, n, gas_xyz, sl, keys, acc, sigma_cm2, gamma_out);
     // exports
     hipError_t e = hipSuccess;
     if (offsets_out) e = hipMemcpyAsync(offsets_out, off64, (size_t)(n + 1) * sizeof(int64_t), hipMemcpyDefault, s);
@@ -742,9 +779,9 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
         // the pair-level parent is lost to the jumping; search again
         hipMemsetAsync(words, 0, 256, s);
         // (into the link arrays, which are free again)
-        launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, off, keys, owner, nbc, nb, nbs, bins.pos_h,
-                               sigma_cm2, (int *)links, (double *)(links + Eb * 16), roots, words);
-        launch_parent_particle(&c, E, (const int *)links, owner, pp);
+        launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, sl, keys, owner, nbc, nrec, bits, W, sigma_cm2,
+                               (int *)links, (double *)(links + Eb * 16), roots, words);
+        launch_parent_particle(&c, E, (const int *)links, owner, sl, off64, pp);
         if (E > 0) e = hipMemcpyAsync(parents_out, pp, (size_t)E * sizeof(int64_t), hipMemcpyDefault, s);
     }
     if (e != hipSuccess) return done(fail(ctx, START_EHIP, hipGetErrorString(e)));

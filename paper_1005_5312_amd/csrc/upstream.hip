@@ -23,19 +23,31 @@ constexpr int kThreads = 256;
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
-// Neighbours within 2 h_i, found through the particles binned by grid cell:
-// each neighbour's index and the place of its binned record.
+// A neighbour j of a particle as the upstream search reads it: position,
+// index and the place of j's own list (one contiguous record per neighbour,
+// so that the search streams through them without dependent loads).
+struct NbRec {
+    double x, y, z;
+    unsigned j, first, count, pad;
+};
+
+// Neighbours within 2 h_i, found through the particles binned by grid cell.
+// Threads take the particles in Morton order (perm), so that a wave's
+// particles search overlapping cells.  FILL = false counts, FILL = true
+// writes the records at nb_off[i].
 template <bool FILL>
-__global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const double *__restrict__ xyz,
+__global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const unsigned *__restrict__ perm,
+                                                       const double *__restrict__ xyz,
                                                        const double *__restrict__ h, start_box box, double delta,
                                                        int G, int K, const unsigned *__restrict__ start,
                                                        const double4 *__restrict__ pos_h,
-                                                       const unsigned *__restrict__ idx, unsigned *__restrict__ count,
-                                                       const unsigned *__restrict__ nb_off, unsigned *__restrict__ nb,
-                                                       unsigned *__restrict__ nbs)
+                                                       const unsigned *__restrict__ idx, const uint2 *__restrict__ sl,
+                                                       unsigned *__restrict__ count,
+                                                       const unsigned *__restrict__ nb_off, NbRec *__restrict__ rec)
 {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
+    const int64_t rk = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (rk >= n) return;
+    const unsigned i = perm[rk];
     const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
     const double r = 2.0 * h[i];
     const double r2 = r * r;
@@ -57,13 +69,21 @@ __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const double *
             const unsigned s0 = start[row + lo[2]], s1 = start[row + hi[2] + 1];
             for (unsigned s = s0; s < s1; ++s) {
                 const unsigned j = idx[s];
-                if (j == (unsigned)i) continue;
+                if (j == i) continue;
                 const double4 q = pos_h[s];
                 const double ex = q.x - x[0], ey = q.y - x[1], ez = q.z - x[2];
                 if (!(ex * ex + ey * ey + ez * ez <= r2)) continue;
                 if (FILL) {
-                    nb[base + c] = j;
-                    nbs[base + c] = s;   // its binned record (x, y, z, h)
+                    const uint2 lj = sl[j];
+                    NbRec o;
+                    o.x = q.x;
+                    o.y = q.y;
+                    o.z = q.z;
+                    o.j = j;
+                    o.first = lj.x;
+                    o.count = lj.y;
+                    o.pad = 0u;
+                    rec[base + c] = o;
                 }
                 ++c;
             }
@@ -71,12 +91,39 @@ __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const double *
     if (!FILL) count[i] = c;
 }
 
-__global__ void __launch_bounds__(kThreads) pair_owner(int64_t n, const unsigned *__restrict__ off,
+__global__ void __launch_bounds__(kThreads) pair_owner(int64_t n, const uint2 *__restrict__ sl,
                                                        unsigned *__restrict__ owner)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
-    for (unsigned p = off[i]; p < off[i + 1]; ++p) owner[p] = (unsigned)i;
+    const uint2 r = sl[i];
+    for (unsigned k = 0; k < r.y; ++k) owner[r.x + k] = (unsigned)i;
+}
+
+// The pairs' layout: each particle's pairs stay contiguous, and the
+// particles' runs follow the Morton order of their positions (perm: Morton
+// rank -> particle), so that a neighbour's list and a pair's upstream pair
+// lie near the pair itself instead of anywhere in the pair arrays.
+// lc[r] = pair count of the particle of rank r (then scanned in place).
+__global__ void __launch_bounds__(kThreads) layout_counts(int64_t n, const unsigned *__restrict__ perm,
+                                                          const int64_t *__restrict__ counts,
+                                                          unsigned *__restrict__ lc)
+{
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r < n) lc[r] = (unsigned)counts[perm[r]];
+}
+
+// sl[i] = (first pair, pair count) and st[i] = first pair (64-bit, for the
+// list writer) of every particle from the scanned counts in Morton order.
+__global__ void __launch_bounds__(kThreads) layout_starts(int64_t n, const unsigned *__restrict__ perm,
+                                                          const unsigned *__restrict__ lc,
+                                                          uint2 *__restrict__ sl, int64_t *__restrict__ st)
+{
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    const unsigned i = perm[r];
+    sl[i] = make_uint2(lc[r], lc[r + 1] - lc[r]);
+    st[i] = (int64_t)lc[r];
 }
 
 __device__ inline double dist3(const double x[3], const double4 &a)
@@ -85,99 +132,239 @@ __device__ inline double dist3(const double x[3], const double4 &a)
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
-// Upstream pair of every pair (or -1) and its step sigma (d_i - d_j) ucm
-// (n_i + n_j) / 2; root pairs are appended to `roots`.
-__global__ void __launch_bounds__(kThreads) upstream_parent(
-    int64_t n_pairs, int64_t n, const double *__restrict__ xyz, const double *__restrict__ nhi,
-    const unsigned *__restrict__ off, const uint64_t *__restrict__ keys, const unsigned *__restrict__ owner,
-    const unsigned *__restrict__ nb_off, const unsigned *__restrict__ nb, const unsigned *__restrict__ nbs,
-    const double4 *__restrict__ pos_h, const double4 *__restrict__ mom,
-    const double4 *__restrict__ src, const int *__restrict__ first, double sigma, double ucm,
-    int *__restrict__ parent, double *__restrict__ acc, unsigned *__restrict__ roots, unsigned *__restrict__ n_roots)
+// Place of `key` in the ascending keys kj[0, nj), or -1.  Neighbours' lists
+// are nearly the same, so the search starts at guess g (the entry's place in
+// the particle's own list, scaled to this list's length) and gallops to a
+// bracket before bisecting: the same lower bound as a plain bisection of the
+// whole list, with a few nearby loads instead of ~log2(length) scattered ones.
+__device__ inline int find_key(const uint64_t *__restrict__ kj, unsigned nj, uint64_t key, unsigned g)
+{
+    if (nj == 0) return -1;
+    g = g < nj ? g : nj - 1;
+    unsigned lo, hi;
+    if (kj[g] < key) {          // the lower bound is above g
+        lo = g + 1;
+        unsigned b = 1;
+        while (g + b < nj && kj[g + b] < key) {
+            lo = g + b + 1;
+            b <<= 1;
+        }
+        hi = g + b < nj ? g + b : nj;
+    } else {                    // the lower bound is at most g
+        hi = g;
+        unsigned b = 1;
+        while (b <= g && kj[g - b] >= key) {
+            hi = g - b;
+            b <<= 1;
+        }
+        lo = b <= g ? g - b + 1 : 0u;
+    }
+    while (lo < hi) {
+        const unsigned mid = (lo + hi) >> 1;
+        if (kj[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < nj && kj[lo] == key) ? (int)lo : -1;
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run
+// of blocks instead, so that the pairs one XCD works on (and the nearby
+// pairs their neighbours' lists and parents sit in) share its L2.
+__device__ inline int64_t xcd_block()
+{
+    const int nb = (int)gridDim.x;
+    const int per = nb / 8;
+    int blk = (int)blockIdx.x;
+    if (per > 0 && blk < per * 8) blk = (blk & 7) * per + (blk >> 3);
+    return blk;
+}
+
+// Dense index of a list entry: a node as itself, a bucket member as n_nodes
+// plus its place in the sorted sources.
+__device__ inline uint64_t entry_id(uint64_t key, const int *__restrict__ first, int64_t n_nodes)
+{
+    const int node = (int)(key >> 32);
+    const unsigned m = (unsigned)(key & 0xffffffffu);
+    return m == 0 ? (uint64_t)node : (uint64_t)n_nodes + (uint64_t)first[node] + m - 1u;
+}
+
+// Membership table: bit entry_id(alpha) of row i is set when alpha is in
+// particle i's list (rows of W words).  One wave per particle builds its row
+// in LDS (the entries of one list fall in few words, so global atomics from
+// neighbouring lanes would wait on each other) and writes it out whole.
+constexpr unsigned kRowWordsLds = 2048;     // rows up to 8 KiB per wave in LDS
+
+// LDS writes of a wave's lanes made visible to the wave's other lanes
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void __launch_bounds__(kThreads) member_rows(int64_t n, const uint64_t *__restrict__ keys,
+                                                        const uint2 *__restrict__ sl, const int *__restrict__ first,
+                                                        int64_t n_nodes, unsigned W, unsigned *__restrict__ bits)
+{
+    extern __shared__ unsigned rows[];
+    unsigned *row = rows + (threadIdx.x >> 6) * W;
+    const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+    const unsigned lane = threadIdx.x & 63u;
+    if (i >= n) return;         // whole waves leave together
+    for (unsigned w = lane; w < W; w += 64u) row[w] = 0u;
+    wave_sync();
+    const uint2 r = sl[i];
+    for (unsigned p = r.x + lane; p < r.x + r.y; p += 64u) {
+        const uint64_t id = entry_id(keys[p], first, n_nodes);
+        atomicOr(row + (id >> 5), 1u << (unsigned)(id & 31u));
+    }
+    wave_sync();
+    unsigned *out = bits + (size_t)i * W;
+    for (unsigned w = lane; w < W; w += 64u) out[w] = row[w];
+}
+
+// The same for rows too long for LDS: one global atomic per pair (the table
+// must be zeroed first).
+__global__ void __launch_bounds__(kThreads) member_bits(int64_t n_pairs, const uint64_t *__restrict__ keys,
+                                                        const unsigned *__restrict__ owner,
+                                                        const int *__restrict__ first, int64_t n_nodes, unsigned W,
+                                                        unsigned *__restrict__ bits)
 {
     const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (p >= n_pairs) return;
+    const uint64_t id = entry_id(keys[p], first, n_nodes);
+    atomicOr(bits + (size_t)owner[p] * W + (id >> 5), 1u << (unsigned)(id & 31u));
+}
+
+// Upstream pair of every pair (or -1) and its step sigma (d_i - d_j) ucm
+// (n_i + n_j) / 2; root pairs are appended to `roots`.  sl[i] = (first pair,
+// pair count) of particle i.
+//
+// The choice is the one the definition makes with the rounded values
+// d = sqrt(d2) and cos phi = dot / (d_i d_j): among the neighbours with
+// d_j < d_i that hold the source in their own list, the largest cos phi, the
+// lowest index on ties.  The scan decides both comparisons from d2 and dot
+// alone, without a square root or a division, wherever the margin is far
+// wider than their rounding (d2_j below d2_i by more than 1e-14 relative;
+// dot^2 d2_best against dot_best^2 d2_j by more than 1e-13, both dots
+// positive) and falls back to the rounded values themselves otherwise, so
+// the choice is the definition's bit for bit.
+//
+// Membership of the source in a neighbour's list: BITS = false searches the
+// neighbour's sorted list for every neighbour that would be taken (the
+// lanes of a wave wait for each other's searches); BITS = true reads one bit
+// of the membership table, loaded a neighbour ahead with the neighbour's
+// record, and searches only the chosen neighbour's list once at the end.
+template <bool BITS>
+__global__ void __launch_bounds__(kThreads) upstream_parent(
+    int64_t n_pairs, int64_t n, const double *__restrict__ xyz, const double *__restrict__ nhi,
+    const uint2 *__restrict__ sl, const uint64_t *__restrict__ keys, const unsigned *__restrict__ owner,
+    const unsigned *__restrict__ nb_off, const NbRec *__restrict__ rec, const double4 *__restrict__ mom,
+    const double4 *__restrict__ src, const int *__restrict__ first, int64_t n_nodes, const unsigned *__restrict__ bits,
+    unsigned W, double sigma, double ucm, int *__restrict__ parent, double *__restrict__ acc,
+    unsigned *__restrict__ roots, unsigned *__restrict__ n_roots)
+{
+    const int64_t p = xcd_block() * kThreads + threadIdx.x;
+    if (p >= n_pairs) return;
     const unsigned i = owner[p];
     const uint64_t key = keys[p];
-    const unsigned li = off[i], ni = off[i + 1] - li, rank = (unsigned)(p - li);   // alpha's place in i's list
+    const uint2 si = sl[i];
+    // alpha's place in i's list as a fraction: the first probe of the search
+    // in a neighbour's list (any probe gives the same answer; a near one is
+    // quicker)
+    const float place = si.y > 0 ? (float)(unsigned)(p - si.x) / (float)si.y : 0.0f;
     const double4 a = source_of_key(mom, src, first, key);
-    const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
-    const double di = dist3(x, a);
+    const double ux = xyz[i] - a.x, uy = xyz[n + i] - a.y, uz = xyz[2 * n + i] - a.z;
+    const double d2i = ux * ux + uy * uy + uz * uz;
+    const double di = sqrt(d2i);
+    const double d2i_lo = d2i * (1.0 - 1e-14);
+    unsigned wo = 0, bit = 0;
+    if (BITS) {
+        const uint64_t id = entry_id(key, first, n_nodes);
+        wo = (unsigned)(id >> 5);
+        bit = 1u << (unsigned)(id & 31u);
+    }
     int best = -1;
+    bool have = false;          // a neighbour taken
+    uint2 bsl = make_uint2(0u, 0u);
     unsigned bj = 0;
-    double bc = 0.0, bd = 0.0;
-    // the next neighbour's index, list bounds and position are loaded one
-    // iteration ahead, so that the loads of successive neighbours overlap;
-    // the position comes from the binned record (one line, not three)
+    double bdot = 0.0, bd2 = 0.0, bdot2 = 0.0;
+    // the next neighbour's record is loaded one iteration ahead, so that the
+    // loads of successive neighbours overlap (BITS: two ahead, and the next
+    // neighbour's table word one ahead)
     const unsigned t0 = nb_off[i], t1 = nb_off[i + 1];
-    unsigned jn = 0, ljn = 0, ljn1 = 0;
-    double4 qn = make_double4(0.0, 0.0, 0.0, 0.0);
-    if (t0 < t1) {
-        jn = nb[t0];
-        qn = pos_h[nbs[t0]];
-        ljn = off[jn];
-        ljn1 = off[jn + 1];
+    NbRec qn, qm;
+    qn.x = qn.y = qn.z = 0.0;
+    qn.j = qn.first = qn.count = qn.pad = 0u;
+    qm = qn;
+    unsigned wn = 0;
+    if (t0 < t1) qn = rec[t0];
+    if (BITS) {
+        if (t0 < t1) wn = bits[(size_t)qn.j * W + wo];
+        if (t0 + 1 < t1) qm = rec[t0 + 1];
     }
     for (unsigned t = t0; t < t1; ++t) {
-        const unsigned j = jn;
-        const unsigned lj = ljn, nj = ljn1 - ljn;
-        const double y[3] = {qn.x, qn.y, qn.z};
-        if (t + 1 < t1) {
-            jn = nb[t + 1];
-            qn = pos_h[nbs[t + 1]];
-            ljn = off[jn];
-            ljn1 = off[jn + 1];
-        }
-        // the geometric conditions first (strictly closer to the source, and
-        // closer to the ray than the best so far), so that only a candidate
-        // that would be taken is looked up: the same choice as testing them
-        // after the search, with far fewer searches
-        const double dj = dist3(y, a);
-        if (!(dj < di)) continue;
-        const double dot = (x[0] - a.x) * (y[0] - a.x) + (x[1] - a.y) * (y[1] - a.y) + (x[2] - a.z) * (y[2] - a.z);
-        const double c = dot / (di * dj);
-        if (!(best < 0 || c > bc || (c == bc && j < bj))) continue;
-        // alpha in j's list (keys ascending).  Neighbours' lists are nearly
-        // the same, so the search starts at alpha's place in i's list,
-        // scaled to j's length, and gallops to a bracket before bisecting:
-        // the same lower bound as a plain bisection of the whole list, with
-        // a few nearby loads instead of ~log2(length) scattered ones.
-        if (nj == 0) continue;
-        const uint64_t *kj = keys + lj;
-        unsigned g = ni > 0 ? (unsigned)(((uint64_t)rank * nj) / ni) : 0u;
-        g = g < nj ? g : nj - 1;
-        unsigned lo, hi;
-        if (kj[g] < key) {          // the lower bound is above g
-            lo = g + 1;
-            unsigned b = 1;
-            while (g + b < nj && kj[g + b] < key) {
-                lo = g + b + 1;
-                b <<= 1;
+        const unsigned j = qn.j;
+        const uint2 sj = make_uint2(qn.first, qn.count);
+        const double ex = qn.x - a.x, ey = qn.y - a.y, ez = qn.z - a.z;
+        const unsigned wc = wn;
+        if (BITS) {
+            if (t + 1 < t1) {
+                qn = qm;
+                wn = bits[(size_t)qn.j * W + wo];
             }
-            hi = g + b < nj ? g + b : nj;
-        } else {                    // the lower bound is at most g
-            hi = g;
-            unsigned b = 1;
-            while (b <= g && kj[g - b] >= key) {
-                hi = g - b;
-                b <<= 1;
+            if (t + 2 < t1) qm = rec[t + 2];
+        } else if (t + 1 < t1) {
+            qn = rec[t + 1];
+        }
+        // strictly closer to the source: d_j < d_i
+        const double d2j = ex * ex + ey * ey + ez * ez;
+        if (!(d2j < d2i)) continue;
+        if (!(d2j < d2i_lo)) {
+            // within rounding of d_i: the rounded distances decide (kept a
+            // branch of its own, not computed for every neighbour)
+            asm volatile("" ::: "memory");
+            if (!(sqrt(d2j) < di)) continue;
+        }
+        // closer to the ray than the best so far (the geometric conditions
+        // before the search: only a neighbour that would be taken is looked
+        // up in its list)
+        const double dot = ux * ex + uy * ey + uz * ez;
+        if (have) {
+            bool take;
+            const double l = (dot * dot) * bd2, r = bdot2 * d2j;
+            if (dot > 0.0 && bdot > 0.0 && d2j > 0.0 && l > r * (1.0 + 1e-13)) {
+                take = true;
+            } else if (dot > 0.0 && bdot > 0.0 && d2j > 0.0 && l < r * (1.0 - 1e-13)) {
+                take = false;
+            } else {
+                const double c = dot / (di * sqrt(d2j)), bc = bdot / (di * sqrt(bd2));
+                take = c > bc || (c == bc && j < bj);
             }
-            lo = b <= g ? g - b + 1 : 0u;
+            if (!take) continue;
         }
-        while (lo < hi) {
-            const unsigned mid = (lo + hi) >> 1;
-            if (kj[mid] < key) lo = mid + 1;
-            else hi = mid;
+        if (BITS) {
+            if (!(wc & bit)) continue;
+            bsl = sj;
+        } else {
+            const int f = find_key(keys + sj.x, sj.y, key, (unsigned)(place * (float)sj.y));
+            if (f < 0) continue;
+            best = (int)(sj.x + (unsigned)f);
         }
-        if (lo >= nj || kj[lo] != key) continue;
-        best = (int)(lo + lj);
+        have = true;
         bj = j;
-        bc = c;
-        bd = dj;
+        bdot = dot;
+        bd2 = d2j;
+        bdot2 = dot * dot;
+    }
+    if (BITS && have) {
+        // alpha's place in the chosen neighbour's list (present: its bit is set)
+        const int f = find_key(keys + bsl.x, bsl.y, key, (unsigned)(place * (float)bsl.y));
+        best = f >= 0 ? (int)(bsl.x + (unsigned)f) : -1;
     }
     parent[p] = best;
     if (best >= 0) {
-        acc[p] = sigma * ((di - bd) * ucm) * (0.5 * (nhi[i] + nhi[bj]));
+        acc[p] = sigma * ((di - sqrt(bd2)) * ucm) * (0.5 * (nhi[i] + nhi[bj]));
     } else {
         const unsigned r = atomicAdd(n_roots, 1u);
         roots[r] = (unsigned)p;
@@ -209,7 +396,7 @@ __global__ void __launch_bounds__(kThreads) pack_links(int64_t n_pairs, const in
 __global__ void __launch_bounds__(kThreads) jump_links(int64_t n_pairs, const Link *__restrict__ in,
                                                        Link *__restrict__ out, unsigned *__restrict__ more)
 {
-    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t p = xcd_block() * kThreads + threadIdx.x;
     if (p >= n_pairs) return;
     const Link a = in[p];
     if (a.par < 0) {
@@ -233,10 +420,13 @@ __global__ void __launch_bounds__(kThreads) unpack_acc(int64_t n_pairs, const Li
     acc[p] = in[p].acc;
 }
 
-// Gamma_i = sigma / (4 pi) sum_p L e^-tau / d_cm^2 over the pairs of i in list
-// order (eq. A2).
+// Gamma_i = sigma / (4 pi) sum_p L e^-tau / d_cm^2 over the pairs of i
+// (eq. A2).  One wave per particle: the lanes take the list's pairs in
+// strides of 64 (coalesced reads of the keys and optical depths, where a
+// thread per particle touched a line of each per pair) and add their partial
+// sums by a butterfly, a fixed order for every call.
 __global__ void __launch_bounds__(kThreads) upstream_gamma(int64_t n, const double *__restrict__ xyz,
-                                                           const unsigned *__restrict__ off,
+                                                           const uint2 *__restrict__ sl,
                                                            const uint64_t *__restrict__ keys,
                                                            const double *__restrict__ tau,
                                                            const double4 *__restrict__ mom,
@@ -244,18 +434,21 @@ __global__ void __launch_bounds__(kThreads) upstream_gamma(int64_t n, const doub
                                                            const int *__restrict__ first, double sigma, double ucm,
                                                            double *__restrict__ gamma)
 {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
+    const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+    const unsigned lane = threadIdx.x & 63u;
+    if (i >= n) return;     // whole waves leave together
     const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
     double sum = 0.0;
-    for (unsigned p = off[i]; p < off[i + 1]; ++p) {
+    const uint2 r = sl[i];
+    for (unsigned p = r.x + lane; p < r.x + r.y; p += 64u) {
         const double4 a = source_of_key(mom, src, first, keys[p]);
         const double d = dist3(x, a);
         if (d == 0.0) continue;
         const double dcm = d * ucm;
         sum += a.w * exp(-tau[p]) / (dcm * dcm);
     }
-    gamma[i] = sigma / (4.0 * M_PI) * sum;
+    for (int m = 32; m > 0; m >>= 1) sum += __shfl_xor(sum, m, 64);
+    if (lane == 0) gamma[i] = sigma / (4.0 * M_PI) * sum;
 }
 
 __global__ void __launch_bounds__(kThreads) to_u32(int64_t n, const int64_t *__restrict__ in, unsigned *__restrict__ out)
@@ -288,15 +481,19 @@ __global__ void __launch_bounds__(kThreads) to_i64(int64_t n, const unsigned *__
     if (i < n) out[i] = (int64_t)in[i];
 }
 
-// parent pair -> upstream particle index (or -1), for the export
+// parent pair -> upstream particle index (or -1), for the export, which
+// keeps the particles' lists in particle order (offsets `ooff`)
 __global__ void __launch_bounds__(kThreads) parent_particle(int64_t n_pairs, const int *__restrict__ parent,
                                                             const unsigned *__restrict__ owner,
+                                                            const uint2 *__restrict__ sl,
+                                                            const int64_t *__restrict__ ooff,
                                                             int64_t *__restrict__ out)
 {
     const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (p >= n_pairs) return;
     const int q = parent[p];
-    out[p] = q < 0 ? -1 : (int64_t)owner[q];
+    const unsigned i = owner[p];
+    out[ooff[i] + (p - (int64_t)sl[i].x)] = q < 0 ? -1 : (int64_t)owner[q];
 }
 
 }  // namespace
@@ -316,32 +513,66 @@ void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out)
     if (n > 0) to_i64<<<blocks_for(n), kThreads, 0, c->stream>>>(n, in, out);
 }
 
-void launch_neighbours(Ctx *c, const GasBins &b, int64_t n, const double *xyz, const double *h, unsigned *count,
-                       const unsigned *nb_off, unsigned *nb, unsigned *nbs)
+size_t neighbour_record_bytes() { return sizeof(NbRec); }
+
+void launch_neighbours(Ctx *c, const GasBins &b, int64_t n, const unsigned *perm, const double *xyz, const double *h,
+                       const uint2 *sl, unsigned *count, const unsigned *nb_off, void *rec)
 {
     if (n <= 0) return;
     if (!nb_off)
-        neighbours<false><<<blocks_for(n), kThreads, 0, c->stream>>>(n, xyz, h, b.box, b.delta, b.G, b.cls.K, b.start, b.pos_h,
-                                                                     b.idx, count, nullptr, nullptr, nullptr);
+        neighbours<false><<<blocks_for(n), kThreads, 0, c->stream>>>(n, perm, xyz, h, b.box, b.delta, b.G, b.cls.K,
+                                                                     b.start, b.pos_h, b.idx, sl, count, nullptr,
+                                                                     nullptr);
     else
-        neighbours<true><<<blocks_for(n), kThreads, 0, c->stream>>>(n, xyz, h, b.box, b.delta, b.G, b.cls.K, b.start, b.pos_h,
-                                                                    b.idx, nullptr, nb_off, nb, nbs);
+        neighbours<true><<<blocks_for(n), kThreads, 0, c->stream>>>(n, perm, xyz, h, b.box, b.delta, b.G, b.cls.K,
+                                                                    b.start, b.pos_h, b.idx, sl, nullptr, nb_off,
+                                                                    (NbRec *)rec);
 }
 
-void launch_pair_owner(Ctx *c, int64_t n, const unsigned *off, unsigned *owner)
+void launch_pair_owner(Ctx *c, int64_t n, const uint2 *sl, unsigned *owner)
 {
-    if (n > 0) pair_owner<<<blocks_for(n), kThreads, 0, c->stream>>>(n, off, owner);
+    if (n > 0) pair_owner<<<blocks_for(n), kThreads, 0, c->stream>>>(n, sl, owner);
+}
+
+void launch_layout_counts(Ctx *c, int64_t n, const unsigned *perm, const int64_t *counts, unsigned *lc)
+{
+    if (n > 0) layout_counts<<<blocks_for(n), kThreads, 0, c->stream>>>(n, perm, counts, lc);
+}
+
+void launch_layout_starts(Ctx *c, int64_t n, const unsigned *perm, const unsigned *lc, uint2 *sl, int64_t *st)
+{
+    if (n > 0) layout_starts<<<blocks_for(n), kThreads, 0, c->stream>>>(n, perm, lc, sl, st);
 }
 
 void launch_upstream_parent(Ctx *c, const Tree *t, int64_t n_pairs, int64_t n, const double *xyz, const double *nhi,
-                            const unsigned *off, const uint64_t *keys, const unsigned *owner, const unsigned *nb_off,
-                            const unsigned *nb, const unsigned *nbs, const double4 *pos_h, double sigma, int *parent,
-                            double *acc, unsigned *roots, unsigned *n_roots)
+                            const uint2 *sl, const uint64_t *keys, const unsigned *owner, const unsigned *nb_off,
+                            const void *rec, const unsigned *bits, unsigned W, double sigma, int *parent, double *acc,
+                            unsigned *roots, unsigned *n_roots)
 {
     if (n_pairs <= 0) return;
-    upstream_parent<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(
-        n_pairs, n, xyz, nhi, off, keys, owner, nb_off, nb, nbs, pos_h, t->mom, t->src, t->first, sigma,
-        t->box.length_unit_cm, parent, acc, roots, n_roots);
+    if (bits)
+        upstream_parent<true><<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(
+            n_pairs, n, xyz, nhi, sl, keys, owner, nb_off, (const NbRec *)rec, t->mom, t->src, t->first, t->n_nodes,
+            bits, W, sigma, t->box.length_unit_cm, parent, acc, roots, n_roots);
+    else
+        upstream_parent<false><<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(
+            n_pairs, n, xyz, nhi, sl, keys, owner, nb_off, (const NbRec *)rec, t->mom, t->src, t->first, t->n_nodes,
+            nullptr, 0u, sigma, t->box.length_unit_cm, parent, acc, roots, n_roots);
+}
+
+void launch_member_bits(Ctx *c, const Tree *t, int64_t n, int64_t n_pairs, const uint64_t *keys, const uint2 *sl,
+                        const unsigned *owner, unsigned W, unsigned *bits)
+{
+    if (n <= 0 || W == 0) return;
+    if (W <= kRowWordsLds) {
+        member_rows<<<blocks_for(n * 64), kThreads, (kThreads / 64) * W * sizeof(unsigned), c->stream>>>(
+            n, keys, sl, t->first, t->n_nodes, W, bits);
+    } else {
+        hipMemsetAsync(bits, 0, (size_t)n * W * sizeof(unsigned), c->stream);
+        if (n_pairs > 0)
+            member_bits<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, keys, owner, t->first, t->n_nodes,
+                                                                          W, bits);
+    }
 }
 
 void launch_pack_links(Ctx *c, int64_t n_pairs, const int *par, const double *acc, void *links)
@@ -360,17 +591,19 @@ void launch_unpack_acc(Ctx *c, int64_t n_pairs, const void *links, double *acc)
     if (n_pairs > 0) unpack_acc<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, (const Link *)links, acc);
 }
 
-void launch_upstream_gamma(Ctx *c, const Tree *t, int64_t n, const double *xyz, const unsigned *off,
+void launch_upstream_gamma(Ctx *c, const Tree *t, int64_t n, const double *xyz, const uint2 *sl,
                            const uint64_t *keys, const double *tau, double sigma, double *gamma)
 {
     if (n > 0)
-        upstream_gamma<<<blocks_for(n), kThreads, 0, c->stream>>>(n, xyz, off, keys, tau, t->mom, t->src, t->first,
-                                                                  sigma, t->box.length_unit_cm, gamma);
+        upstream_gamma<<<blocks_for(n * 64), kThreads, 0, c->stream>>>(n, xyz, sl, keys, tau, t->mom, t->src,
+                                                                       t->first, sigma, t->box.length_unit_cm, gamma);
 }
 
-void launch_parent_particle(Ctx *c, int64_t n_pairs, const int *parent, const unsigned *owner, int64_t *out)
+void launch_parent_particle(Ctx *c, int64_t n_pairs, const int *parent, const unsigned *owner, const uint2 *sl,
+                            const int64_t *ooff, int64_t *out)
 {
-    if (n_pairs > 0) parent_particle<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, parent, owner, out);
+    if (n_pairs > 0)
+        parent_particle<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, parent, owner, sl, ooff, out);
 }
 
 }  // namespace start

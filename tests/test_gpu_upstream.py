@@ -31,6 +31,30 @@ def cases():
             "uniform_theta0": (w1, 0.0)}
 
 
+def many_source_case():
+    # few particles, many sources: the membership table's rows exceed what a
+    # wave keeps in LDS (more than 2048 words of n_nodes + n_src bits)
+    return {"many_sources": (H.W.make_small(seed=14, n_gas=2048, n_src=70000), 1.0)}
+
+
+def membership_path(ctx, tree, n_gas, n_pairs):
+    """How the call tests a source's membership in a neighbour's list, by the
+    rule the library states: a bit table when it takes at most max(8 bytes per
+    pair, 64 MiB) (and 4 GiB), built in LDS for rows up to 2048 words;
+    otherwise searches of the sorted lists."""
+    nodes = ctx.tree_export(tree)["geo"].shape[0]
+    w = (nodes + tree.n_src + 31) // 32
+    table = n_gas * w * 4
+    if table <= max(8 * n_pairs, 64 << 20) and table <= 4 << 30:
+        return "rows" if w <= 2048 else "atomics"
+    return "search"
+
+
+EXPECTED_PATH = {"uniform": "rows", "lognormal": "rows", "emitters": "rows", "smooth": "rows",
+                 "uniform_theta0": "rows", "lognormal_2^15": "rows", "emitters_2^15": "search",
+                 "many_sources": "atomics"}
+
+
 def large_cases():
     # 2^15 particles: several grid cells of particles per kernel support, the
     # neighbour lists' full range of lengths and deep chains (the oracle's
@@ -40,9 +64,9 @@ def large_cases():
 
 
 @pytest.mark.parametrize("name", ["uniform", "lognormal", "emitters", "smooth", "uniform_theta0",
-                                  "lognormal_2^15", "emitters_2^15"])
+                                  "lognormal_2^15", "emitters_2^15", "many_sources"])
 def test_upstream_chain_matches_oracle(ctx, name):
-    w, theta = (large_cases() if name.endswith("2^15") else cases())[name]
+    w, theta = {**cases(), **large_cases(), **many_source_case()}[name]
     print(f"[case] upstream {name}: {w.n_gas} particles, {w.n_src} sources, theta {theta}", flush=True)
     dev = ctx.device
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
@@ -56,6 +80,9 @@ def test_upstream_chain_matches_oracle(ctx, name):
     ogrid = O.grid(ob, w.gas_xyz, w.gas_h, w.gas_nhi, w.grid_log2)
     want, ooffs, opar, ost = O.upstream_rates(otree, w.grid_log2, ogrid, w.gas_xyz, w.gas_h, w.gas_nhi, w.self_src,
                                               theta, w.sigma, structure=True)
+    path = membership_path(ctx, tree, w.n_gas, int(offs[-1]))
+    print(f"  membership by {path}")
+    assert path == EXPECTED_PATH[name]
     assert np.array_equal(offs, ooffs)
     assert np.array_equal(par, opar)              # the same upstream particle for every pair
     assert roots == int(ost[:, 1].sum())
