@@ -203,8 +203,8 @@ start_status start_compute_dissociation_rates(start_ctx *ctx, const start_tree *
  * list offsets; parents_out [capacity] (host or device, may be NULL) the
  * upstream particle of each pair in the order of start_interaction_lists, or
  * -1; n_roots_out (host, may be NULL) the number of pairs integrated along
- * the ray.  Synchronous; allocates its work arrays (about 40 bytes per list
- * entry, 40 bytes per neighbour pair, and a membership table of
+ * the ray.  Synchronous; allocates its work arrays (about 48 bytes per list
+ * entry, 32 bytes per neighbour pair, and a membership table of
  * n_gas * ceil((n_nodes + n_src) / 32) 32-bit words where that takes at most
  * max(8 bytes per list entry, 64 MiB) and 4 GiB; larger trees search the
  * neighbours' sorted lists instead, with the same result) for the duration of

@@ -426,7 +426,8 @@ class Context:
         cur = self._enter(xyz, h, nhi, ss, out)
         self._check(lib().start_compute_rates_upstream(self._h, tree._h, grid._h, n, _ptr(xyz), _ptr(h), _ptr(nhi),
                                                        _ptr(ss), float(theta), float(sigma), _ptr(out),
-                                                       offs.ctypes.data_as(C.c_void_p), None, 0, C.byref(roots)),
+                                                       offs.ctypes.data_as(C.c_void_p) if structure else None,
+                                                       None, 0, C.byref(roots)),
                     "start_compute_rates_upstream")
         par = None
         if structure:

@@ -682,7 +682,8 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     if (!mk || !perm || !radix_tmp || !lc || !sl || !first_pair || !kflags) return nomem();
     hipMemsetAsync(kflags, 0, sizeof(unsigned), s);
     launch_keys(tree->t.box, n, gas_xyz, nullptr, mk, perm, kflags, s);
-    radix_sort_pairs(mk, perm, n, 63, radix_tmp, s);
+    launch_coarse_keys(&c, n, mk);
+    radix_sort_pairs(mk, perm, n, 30, radix_tmp, s);
     launch_layout_counts(&c, n, perm, off64, lc);
     hipMemsetAsync(lc + n, 0, sizeof(unsigned), s);
     exclusive_scan_u32(lc, n + 1, scan_tmp, s);
@@ -695,14 +696,16 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     const size_t Eb = (size_t)(E > 0 ? E : 1);
     uint64_t *keys = (uint64_t *)alloc(Eb * sizeof(uint64_t));
     unsigned *owner = (unsigned *)alloc(Eb * sizeof(unsigned));
-    int *par = (int *)alloc(Eb * sizeof(int));
-    double *acc = (double *)alloc(Eb * sizeof(double));
-    // two arrays of 16-byte (tau, parent) records for the pointer jumping
-    char *links = (char *)alloc(2 * Eb * 16);
+    // two arrays of 16-byte (tau, parent) records: the search writes the
+    // first, pointer jumping alternates between the two
+    const size_t lb_bytes = Eb * upstream_link_bytes();
+    char *links = (char *)alloc(2 * lb_bytes);
     unsigned *roots = (unsigned *)alloc(Eb * sizeof(unsigned));
     unsigned *words = (unsigned *)alloc(256);   // [0] root count, [1] "more" flag
-    unsigned *nbc = (unsigned *)alloc((size_t)(n + 1) * sizeof(unsigned));
-    if (!keys || !owner || !par || !links || !acc || !roots || !words || !nbc) return nomem();
+    const int64_t nslots = neighbour_slots(n);
+    unsigned *nbc = (unsigned *)alloc((size_t)(nslots + 1) * sizeof(unsigned));
+    void *nb_scan_tmp = alloc(scan_temp_bytes(nslots + 1));
+    if (!keys || !owner || !links || !roots || !words || !nbc || !nb_scan_tmp) return nomem();
     // 2. the lists as sorted keys, and the owner of every pair
     r.counts = nullptr;
     r.offsets = first_pair;
@@ -714,15 +717,15 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     st = bin_gas(&c, tree->t.box, n, gas_xyz, gas_h, gas_nhi, grid->g.grid_log2, &bins);
     if (st) return done(st == START_ENOMEM && c.budget ? START_EBUDGET : st);
     have_bins = true;
-    launch_neighbours(&c, bins, n, perm, gas_xyz, gas_h, sl, nbc, nullptr, nullptr);
-    hipMemsetAsync(nbc + n, 0, sizeof(unsigned), s);
-    exclusive_scan_u32(nbc, n + 1, scan_tmp, s);
+    launch_neighbours(&c, bins, n, perm, gas_xyz, gas_h, nbc, nullptr, nullptr);
+    hipMemsetAsync(nbc + nslots, 0, sizeof(unsigned), s);
+    exclusive_scan_u32(nbc, nslots + 1, nb_scan_tmp, s);
     unsigned n_nb = 0;
-    hipMemcpyAsync(&n_nb, nbc + n, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(&n_nb, nbc + nslots, sizeof(unsigned), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "neighbour count failed"));
     void *nrec = alloc((size_t)(n_nb > 0 ? n_nb : 1) * neighbour_record_bytes());
     if (!nrec) return nomem();
-    launch_neighbours(&c, bins, n, perm, gas_xyz, gas_h, sl, nullptr, nbc, nrec);
+    launch_neighbours(&c, bins, n, perm, gas_xyz, gas_h, nullptr, nbc, nrec);
     // 4. upstream pair of every pair, its step, and the roots.  Membership of
     // a source in a neighbour's list comes from a bit table (one row of
     // n_nodes + n_src bits per particle) where that table is small beside
@@ -743,18 +746,19 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
         }
     }
     hipMemsetAsync(words, 0, 256, s);
-    launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, sl, keys, owner, nbc, nrec, bits, W, sigma_cm2, par,
-                           acc, roots, words);
+    launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, sl, keys, owner, nbc, nrec, bits, W, sigma_cm2, links,
+                           roots, words);
     unsigned n_roots = 0;
     hipMemcpyAsync(&n_roots, words, sizeof(unsigned), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "upstream search failed"));
     if (n_roots_out) *n_roots_out = n_roots;
     // 5. roots: the column along the ray
-    launch_upstream_roots(&c, &tree->t, &grid->g, n_roots, roots, keys, owner, gas_xyz, n, sigma_cm2, acc);
+    launch_upstream_roots(&c, &tree->t, &grid->g, n_roots, roots, keys, owner, gas_xyz, n, sigma_cm2, (double *)links,
+                          (int)(upstream_link_bytes() / sizeof(double)));
     // 6. sums along the chains by pointer jumping
+    void *fin = links;
     {
-        void *la = links, *lb = links + Eb * 16;
-        launch_pack_links(&c, E, par, acc, la);
+        void *la = links, *lb = links + lb_bytes;
         for (int round = 0;; ++round) {
             if (round > 40) return done(fail(ctx, START_EHIP, "upstream chains did not resolve"));
             hipMemsetAsync(words + 1, 0, sizeof(unsigned), s);
@@ -765,10 +769,10 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
             if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "pointer jumping failed"));
             if (!more) break;
         }
-        launch_unpack_acc(&c, E, la, acc);
+        fin = la;
     }
     // 7. the rates
-    launch_upstream_gamma(&c, &tree->t, n, gas_xyz, sl, keys, acc, sigma_cm2, gamma_out);
+    launch_upstream_gamma(&c, &tree->t, n, gas_xyz, sl, keys, fin, sigma_cm2, gamma_out);
     // exports
     hipError_t e = hipSuccess;
     if (offsets_out) e = hipMemcpyAsync(offsets_out, off64, (size_t)(n + 1) * sizeof(int64_t), hipMemcpyDefault, s);
@@ -776,12 +780,13 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
         if (E > capacity) return done(fail(ctx, START_ECAPACITY, "parents capacity too small"));
         int64_t *pp = (int64_t *)alloc(Eb * sizeof(int64_t));
         if (!pp) return nomem();
-        // the pair-level parent is lost to the jumping; search again
+        // the pair-level parent is lost to the jumping; search again, into
+        // the record array the rates do not read
+        char *spare = (char *)fin == links ? links + lb_bytes : links;
         hipMemsetAsync(words, 0, 256, s);
-        // (into the link arrays, which are free again)
         launch_upstream_parent(&c, &tree->t, E, n, gas_xyz, gas_nhi, sl, keys, owner, nbc, nrec, bits, W, sigma_cm2,
-                               (int *)links, (double *)(links + Eb * 16), roots, words);
-        launch_parent_particle(&c, E, (const int *)links, owner, sl, off64, pp);
+                               spare, roots, words);
+        launch_parent_particle(&c, E, spare, owner, sl, off64, pp);
         if (E > 0) e = hipMemcpyAsync(parents_out, pp, (size_t)E * sizeof(int64_t), hipMemcpyDefault, s);
     }
     if (e != hipSuccess) return done(fail(ctx, START_EHIP, hipGetErrorString(e)));

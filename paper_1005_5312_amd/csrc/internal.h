@@ -282,49 +282,54 @@ __device__ inline double4 source_of_key(const double4 *__restrict__ mom, const d
 }
 // Grid values in linear order (ix*G + iy)*G + iz (the export layout).
 void launch_grid_unpad(Ctx *c, const Grid &g, double *out);
-// acc[p] = optical depth along the ray of each root pair p (FP64 march).
+// acc[p * acc_stride] = optical depth along the ray of each root pair p
+// (FP64 march).
 void launch_upstream_roots(Ctx *c, const Tree *t, const Grid *g, int64_t n_roots, const unsigned *roots,
                            const uint64_t *keys, const unsigned *owner, const double *xyz, int64_t n, double sigma,
-                           double *acc);
+                           double *acc, int acc_stride);
 
 void launch_to_u32(Ctx *c, int64_t n, const int64_t *in, unsigned *out);
 // *total += sum of n non-negative int64 values (64-bit accumulation)
 void launch_sum_i64(Ctx *c, int64_t n, const int64_t *in, unsigned long long *total);
 void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out);
-// Neighbours within 2 h_i (particles taken in the Morton order perm): counts
-// (nb_off null) or the lists at nb_off, one record per neighbour (position,
-// index, and the place sl[j] of its own pair list) of
-// neighbour_record_bytes() bytes.
+// Neighbours within 2 h_i (particles taken in the Morton order perm), each
+// particle's search split over neighbour_slots(n) / n threads: counts per
+// slot (nb_off null) into count[neighbour_slots(n)], or, with nb_off = the
+// exclusive scan of those counts (neighbour_slots(n) + 1 entries), one
+// record per neighbour (position and index) of neighbour_record_bytes()
+// bytes; particle i's records are nb_off[i s, (i + 1) s), s = slots / n.
 size_t neighbour_record_bytes();
+int64_t neighbour_slots(int64_t n);
 void launch_neighbours(Ctx *c, const GasBins &b, int64_t n, const unsigned *perm, const double *xyz, const double *h,
-                       const uint2 *sl, unsigned *count, const unsigned *nb_off, void *rec);
+                       unsigned *count, const unsigned *nb_off, void *rec);
 // The pairs' layout: each particle's list contiguous, the lists in the
 // Morton order of their particles (perm: rank -> particle).  lc[r] = pair
 // count of rank r (to be scanned); sl[i] = (first pair, count), st[i] = first
 // pair of particle i.
+void launch_coarse_keys(Ctx *c, int64_t n, uint64_t *keys);   // keys >>= 33 (top 30 bits)
 void launch_layout_counts(Ctx *c, int64_t n, const unsigned *perm, const int64_t *counts, unsigned *lc);
 void launch_layout_starts(Ctx *c, int64_t n, const unsigned *perm, const unsigned *lc, uint2 *sl, int64_t *st);
 void launch_pair_owner(Ctx *c, int64_t n, const uint2 *sl, unsigned *owner);
 void launch_upstream_parent(Ctx *c, const Tree *t, int64_t n_pairs, int64_t n, const double *xyz, const double *nhi,
                             const uint2 *sl, const uint64_t *keys, const unsigned *owner, const unsigned *nb_off,
-                            const void *rec, const unsigned *bits, unsigned W, double sigma, int *parent, double *acc,
+                            const void *rec, const unsigned *bits, unsigned W, double sigma, void *links,
                             unsigned *roots, unsigned *n_roots);
 // Membership table of the lists: row i (W 32-bit words) has bit id(alpha)
 // set for every entry alpha of particle i's list, id = node, or n_nodes +
 // sorted source index for a bucket member; every word of the table is written.
 void launch_member_bits(Ctx *c, const Tree *t, int64_t n, int64_t n_pairs, const uint64_t *keys, const uint2 *sl,
                         const unsigned *owner, unsigned W, unsigned *bits);
-// Pointer jumping on 16-byte (tau, parent) records: pack from the two
-// arrays, one round from `in` to `out` (sets *more when a parent still has
-// a parent), and the sums back into acc.
-void launch_pack_links(Ctx *c, int64_t n_pairs, const int *par, const double *acc, void *links);
+// The pairs' 16-byte (tau, parent) records (upstream_link_bytes() each; tau
+// at double index 2p): written by the upstream search (tau = the step to the
+// parent, or left for the root march), then pointer jumping, one round from
+// `in` to `out` (sets *more when a parent still has a parent).
+size_t upstream_link_bytes();
 void launch_jump_links(Ctx *c, int64_t n_pairs, const void *in, void *out, unsigned *more);
-void launch_unpack_acc(Ctx *c, int64_t n_pairs, const void *links, double *acc);
 void launch_upstream_gamma(Ctx *c, const Tree *t, int64_t n, const double *xyz, const uint2 *sl,
-                           const uint64_t *keys, const double *tau, double sigma, double *gamma);
+                           const uint64_t *keys, const void *links, double sigma, double *gamma);
 // parent pair -> upstream particle (or -1) at the pair's place in the
-// particle-order export (offsets ooff)
-void launch_parent_particle(Ctx *c, int64_t n_pairs, const int *parent, const unsigned *owner, const uint2 *sl,
+// particle-order export (offsets ooff), from the search's records
+void launch_parent_particle(Ctx *c, int64_t n_pairs, const void *links, const unsigned *owner, const uint2 *sl,
                             const int64_t *ooff, int64_t *out);
 
 // ---- Morton keys (tree.hip) ----

@@ -1110,7 +1110,7 @@ __global__ void __launch_bounds__(256) upstream_roots(int64_t n_roots, const uns
                                                       const double *__restrict__ grid, int64_t guard, int G, int sx,
                                                       int sy, double lo0,
                                                       double lo1, double lo2, double gs, double tau_scale,
-                                                      double *__restrict__ acc)
+                                                      double *__restrict__ acc, int acc_stride)
 {
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (r >= n_roots) return;
@@ -1133,21 +1133,21 @@ __global__ void __launch_bounds__(256) upstream_roots(int64_t n_roots, const uns
     }
     const double d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
     if (!(d2 > 0.0)) {
-        acc[p] = 0.0;
+        acc[(int64_t)p * acc_stride] = 0.0;
         return;
     }
     int nc = 0;
     const unsigned e0 = (unsigned)(tb[0] * sx + tb[1] * sy + tb[2] + guard);
     const double col = march<double, false, CLAMP>(grid - guard, sx, sy, (unsigned)((G - 1) * (sx + sy + 1) + guard),
                                                    e0, fb, D, nc);
-    acc[p] = tau_scale * (col * sqrt(d2));
+    acc[(int64_t)p * acc_stride] = tau_scale * (col * sqrt(d2));
 }
 
 }  // namespace
 
 void launch_upstream_roots(Ctx *c, const Tree *t, const Grid *g, int64_t n_roots, const unsigned *roots,
                            const uint64_t *keys, const unsigned *owner, const double *xyz, int64_t n, double sigma,
-                           double *acc)
+                           double *acc, int acc_stride)
 {
     if (n_roots <= 0) return;
     const double gs = (double)g->G / t->box.size;
@@ -1156,11 +1156,11 @@ void launch_upstream_roots(Ctx *c, const Tree *t, const Grid *g, int64_t n_roots
     if (g->guard == 0)
         upstream_roots<true><<<nb, 256, 0, c->stream>>>(n_roots, roots, keys, owner, xyz, n, t->mom, t->src, t->first,
                                                         g->val, g->guard, g->G, g->sx, g->sy, t->box.lo[0],
-                                                        t->box.lo[1], t->box.lo[2], gs, tau_scale, acc);
+                                                        t->box.lo[1], t->box.lo[2], gs, tau_scale, acc, acc_stride);
     else
         upstream_roots<false><<<nb, 256, 0, c->stream>>>(n_roots, roots, keys, owner, xyz, n, t->mom, t->src,
                                                          t->first, g->val, g->guard, g->G, g->sx, g->sy, t->box.lo[0],
-                                                         t->box.lo[1], t->box.lo[2], gs, tau_scale, acc);
+                                                         t->box.lo[1], t->box.lo[2], gs, tau_scale, acc, acc_stride);
 }
 
 }  // namespace start

@@ -23,29 +23,36 @@ constexpr int kThreads = 256;
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
-// A neighbour j of a particle as the upstream search reads it: position,
-// index and the place of j's own list (one contiguous record per neighbour,
-// so that the search streams through them without dependent loads).
-struct NbRec {
+// A neighbour j of a particle as the upstream search reads it: position and
+// index (one contiguous 32-byte record per neighbour, so that the search
+// streams through them without dependent loads).
+struct __align__(16) NbRec {
     double x, y, z;
-    unsigned j, first, count, pad;
+    unsigned j, pad;
 };
 
 // Neighbours within 2 h_i, found through the particles binned by grid cell.
-// Threads take the particles in Morton order (perm), so that a wave's
-// particles search overlapping cells.  FILL = false counts, FILL = true
-// writes the records at nb_off[i].
+// kNbSub threads share a particle, each taking every kNbSub-th row of cells,
+// and the particles come in Morton order (perm), so that a wave's particles
+// search overlapping cells.  FILL = false counts into count[i kNbSub + sub];
+// FILL = true writes the records from nb_off[i kNbSub + sub] (the counts
+// scanned), so particle i's neighbours are nb_off[i kNbSub, (i + 1) kNbSub).
+// One thread per particle is the fastest measured (8 threads per particle:
+// 2.4x slower, the rows' loops diverge).
+constexpr int kNbSub = 1;
+
 template <bool FILL>
 __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const unsigned *__restrict__ perm,
                                                        const double *__restrict__ xyz,
                                                        const double *__restrict__ h, start_box box, double delta,
                                                        int G, int K, const unsigned *__restrict__ start,
                                                        const double4 *__restrict__ pos_h,
-                                                       const unsigned *__restrict__ idx, const uint2 *__restrict__ sl,
-                                                       unsigned *__restrict__ count,
+                                                       const unsigned *__restrict__ idx, unsigned *__restrict__ count,
                                                        const unsigned *__restrict__ nb_off, NbRec *__restrict__ rec)
 {
-    const int64_t rk = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t rk = g / kNbSub;
+    const int sub = (int)(g % kNbSub);
     if (rk >= n) return;
     const unsigned i = perm[rk];
     const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
@@ -60,11 +67,13 @@ __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const unsigned
         hi[k] = b < 0 ? 0 : (b > G - 1 ? G - 1 : b);
     }
     unsigned c = 0;
-    const unsigned base = FILL ? nb_off[i] : 0u;
+    const unsigned base = FILL ? nb_off[(int64_t)i * kNbSub + sub] : 0u;
     const int64_t ncell = (int64_t)G * G * G;
+    int rr = 0;
     for (int k = 0; k < K; ++k)   // every reach class of the binning
     for (int a = lo[0]; a <= hi[0]; ++a)
         for (int b = lo[1]; b <= hi[1]; ++b) {
+            if (rr++ % kNbSub != sub) continue;
             const int64_t row = k * ncell + ((int64_t)a * G + b) * G;
             const unsigned s0 = start[row + lo[2]], s1 = start[row + hi[2] + 1];
             for (unsigned s = s0; s < s1; ++s) {
@@ -74,21 +83,18 @@ __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const unsigned
                 const double ex = q.x - x[0], ey = q.y - x[1], ez = q.z - x[2];
                 if (!(ex * ex + ey * ey + ez * ez <= r2)) continue;
                 if (FILL) {
-                    const uint2 lj = sl[j];
                     NbRec o;
                     o.x = q.x;
                     o.y = q.y;
                     o.z = q.z;
                     o.j = j;
-                    o.first = lj.x;
-                    o.count = lj.y;
                     o.pad = 0u;
                     rec[base + c] = o;
                 }
                 ++c;
             }
         }
-    if (!FILL) count[i] = c;
+    if (!FILL) count[(int64_t)i * kNbSub + sub] = c;
 }
 
 __global__ void __launch_bounds__(kThreads) pair_owner(int64_t n, const uint2 *__restrict__ sl,
@@ -111,6 +117,14 @@ __global__ void __launch_bounds__(kThreads) layout_counts(int64_t n, const unsig
 {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r < n) lc[r] = (unsigned)counts[perm[r]];
+}
+
+// Morton keys cut to their top 30 bits (1024 cells per axis): order enough
+// for the layout, in four radix passes instead of eight.
+__global__ void __launch_bounds__(kThreads) coarse_keys(int64_t n, uint64_t *__restrict__ keys)
+{
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r < n) keys[r] >>= 33;
 }
 
 // sl[i] = (first pair, pair count) and st[i] = first pair (64-bit, for the
@@ -178,6 +192,16 @@ __device__ inline int64_t xcd_block()
     if (per > 0 && blk < per * 8) blk = (blk & 7) * per + (blk >> 3);
     return blk;
 }
+
+// A pair's (tau, parent) record, 16 bytes.  Pointer jumping sets tau +=
+// tau[parent] and parent = parent[parent] each round, reading the parent's
+// two values from one cache line (two separate arrays cost two lines per
+// scattered parent).
+struct __align__(16) Link {
+    double acc;
+    int par;
+    int pad;
+};
 
 // Dense index of a list entry: a node as itself, a bucket member as n_nodes
 // plus its place in the sorted sources.
@@ -253,16 +277,16 @@ __global__ void __launch_bounds__(kThreads) member_bits(int64_t n_pairs, const u
 // Membership of the source in a neighbour's list: BITS = false searches the
 // neighbour's sorted list for every neighbour that would be taken (the
 // lanes of a wave wait for each other's searches); BITS = true reads one bit
-// of the membership table, loaded a neighbour ahead with the neighbour's
-// record, and searches only the chosen neighbour's list once at the end.
+// of the membership table per neighbour and searches only the chosen
+// neighbour's list, once, at the end.
 template <bool BITS>
 __global__ void __launch_bounds__(kThreads) upstream_parent(
     int64_t n_pairs, int64_t n, const double *__restrict__ xyz, const double *__restrict__ nhi,
     const uint2 *__restrict__ sl, const uint64_t *__restrict__ keys, const unsigned *__restrict__ owner,
     const unsigned *__restrict__ nb_off, const NbRec *__restrict__ rec, const double4 *__restrict__ mom,
     const double4 *__restrict__ src, const int *__restrict__ first, int64_t n_nodes, const unsigned *__restrict__ bits,
-    unsigned W, double sigma, double ucm, int *__restrict__ parent, double *__restrict__ acc,
-    unsigned *__restrict__ roots, unsigned *__restrict__ n_roots)
+    unsigned W, double sigma, double ucm, Link *__restrict__ links, unsigned *__restrict__ roots,
+    unsigned *__restrict__ n_roots)
 {
     const int64_t p = xcd_block() * kThreads + threadIdx.x;
     if (p >= n_pairs) return;
@@ -286,37 +310,23 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
     }
     int best = -1;
     bool have = false;          // a neighbour taken
-    uint2 bsl = make_uint2(0u, 0u);
     unsigned bj = 0;
     double bdot = 0.0, bd2 = 0.0, bdot2 = 0.0;
     // the next neighbour's record is loaded one iteration ahead, so that the
-    // loads of successive neighbours overlap (BITS: two ahead, and the next
-    // neighbour's table word one ahead)
-    const unsigned t0 = nb_off[i], t1 = nb_off[i + 1];
-    NbRec qn, qm;
+    // loads of successive neighbours overlap; BITS: the neighbour's table
+    // word is loaded as its iteration starts and used after the geometric
+    // tests (loading it a neighbour ahead as well took more registers than
+    // it hid latency)
+    const unsigned t0 = nb_off[(int64_t)i * kNbSub], t1 = nb_off[(int64_t)(i + 1) * kNbSub];
+    NbRec qn;
     qn.x = qn.y = qn.z = 0.0;
-    qn.j = qn.first = qn.count = qn.pad = 0u;
-    qm = qn;
-    unsigned wn = 0;
+    qn.j = qn.pad = 0u;
     if (t0 < t1) qn = rec[t0];
-    if (BITS) {
-        if (t0 < t1) wn = bits[(size_t)qn.j * W + wo];
-        if (t0 + 1 < t1) qm = rec[t0 + 1];
-    }
     for (unsigned t = t0; t < t1; ++t) {
         const unsigned j = qn.j;
-        const uint2 sj = make_uint2(qn.first, qn.count);
         const double ex = qn.x - a.x, ey = qn.y - a.y, ez = qn.z - a.z;
-        const unsigned wc = wn;
-        if (BITS) {
-            if (t + 1 < t1) {
-                qn = qm;
-                wn = bits[(size_t)qn.j * W + wo];
-            }
-            if (t + 2 < t1) qm = rec[t + 2];
-        } else if (t + 1 < t1) {
-            qn = rec[t + 1];
-        }
+        const unsigned wc = BITS ? bits[(size_t)j * W + wo] : 0u;
+        if (t + 1 < t1) qn = rec[t + 1];
         // strictly closer to the source: d_j < d_i
         const double d2j = ex * ex + ey * ey + ez * ez;
         if (!(d2j < d2i)) continue;
@@ -345,8 +355,8 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
         }
         if (BITS) {
             if (!(wc & bit)) continue;
-            bsl = sj;
         } else {
+            const uint2 sj = sl[j];
             const int f = find_key(keys + sj.x, sj.y, key, (unsigned)(place * (float)sj.y));
             if (f < 0) continue;
             best = (int)(sj.x + (unsigned)f);
@@ -359,38 +369,21 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
     }
     if (BITS && have) {
         // alpha's place in the chosen neighbour's list (present: its bit is set)
+        const uint2 bsl = sl[bj];
         const int f = find_key(keys + bsl.x, bsl.y, key, (unsigned)(place * (float)bsl.y));
         best = f >= 0 ? (int)(bsl.x + (unsigned)f) : -1;
     }
-    parent[p] = best;
+    Link l;
+    l.par = best;
+    l.pad = 0;
+    l.acc = 0.0;                // a root's column is set by the root march
     if (best >= 0) {
-        acc[p] = sigma * ((di - sqrt(bd2)) * ucm) * (0.5 * (nhi[i] + nhi[bj]));
+        l.acc = sigma * ((di - sqrt(bd2)) * ucm) * (0.5 * (nhi[i] + nhi[bj]));
     } else {
         const unsigned r = atomicAdd(n_roots, 1u);
         roots[r] = (unsigned)p;
     }
-}
-
-// Pointer jumping on (tau, parent) records of 16 bytes: one round sets
-// acc += acc[parent] and parent = parent[parent], reading the parent's two
-// values from one cache line (the parents are scattered over the whole pair
-// array, so two separate arrays cost two lines per pair).
-struct __align__(16) Link {
-    double acc;
-    int par;
-    int pad;
-};
-
-__global__ void __launch_bounds__(kThreads) pack_links(int64_t n_pairs, const int *__restrict__ par,
-                                                       const double *__restrict__ acc, Link *__restrict__ out)
-{
-    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (p >= n_pairs) return;
-    Link l;
-    l.acc = acc[p];
-    l.par = par[p];
-    l.pad = 0;
-    out[p] = l;
+    links[p] = l;
 }
 
 __global__ void __launch_bounds__(kThreads) jump_links(int64_t n_pairs, const Link *__restrict__ in,
@@ -412,14 +405,6 @@ __global__ void __launch_bounds__(kThreads) jump_links(int64_t n_pairs, const Li
     if (b.par >= 0) *more = 1u;
 }
 
-__global__ void __launch_bounds__(kThreads) unpack_acc(int64_t n_pairs, const Link *__restrict__ in,
-                                                       double *__restrict__ acc)
-{
-    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (p >= n_pairs) return;
-    acc[p] = in[p].acc;
-}
-
 // Gamma_i = sigma / (4 pi) sum_p L e^-tau / d_cm^2 over the pairs of i
 // (eq. A2).  One wave per particle: the lanes take the list's pairs in
 // strides of 64 (coalesced reads of the keys and optical depths, where a
@@ -428,7 +413,7 @@ __global__ void __launch_bounds__(kThreads) unpack_acc(int64_t n_pairs, const Li
 __global__ void __launch_bounds__(kThreads) upstream_gamma(int64_t n, const double *__restrict__ xyz,
                                                            const uint2 *__restrict__ sl,
                                                            const uint64_t *__restrict__ keys,
-                                                           const double *__restrict__ tau,
+                                                           const Link *__restrict__ tau,
                                                            const double4 *__restrict__ mom,
                                                            const double4 *__restrict__ src,
                                                            const int *__restrict__ first, double sigma, double ucm,
@@ -445,7 +430,7 @@ __global__ void __launch_bounds__(kThreads) upstream_gamma(int64_t n, const doub
         const double d = dist3(x, a);
         if (d == 0.0) continue;
         const double dcm = d * ucm;
-        sum += a.w * exp(-tau[p]) / (dcm * dcm);
+        sum += a.w * exp(-tau[p].acc) / (dcm * dcm);
     }
     for (int m = 32; m > 0; m >>= 1) sum += __shfl_xor(sum, m, 64);
     if (lane == 0) gamma[i] = sigma / (4.0 * M_PI) * sum;
@@ -483,7 +468,7 @@ __global__ void __launch_bounds__(kThreads) to_i64(int64_t n, const unsigned *__
 
 // parent pair -> upstream particle index (or -1), for the export, which
 // keeps the particles' lists in particle order (offsets `ooff`)
-__global__ void __launch_bounds__(kThreads) parent_particle(int64_t n_pairs, const int *__restrict__ parent,
+__global__ void __launch_bounds__(kThreads) parent_particle(int64_t n_pairs, const Link *__restrict__ links,
                                                             const unsigned *__restrict__ owner,
                                                             const uint2 *__restrict__ sl,
                                                             const int64_t *__restrict__ ooff,
@@ -491,7 +476,7 @@ __global__ void __launch_bounds__(kThreads) parent_particle(int64_t n_pairs, con
 {
     const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (p >= n_pairs) return;
-    const int q = parent[p];
+    const int q = links[p].par;
     const unsigned i = owner[p];
     out[ooff[i] + (p - (int64_t)sl[i].x)] = q < 0 ? -1 : (int64_t)owner[q];
 }
@@ -514,24 +499,29 @@ void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out)
 }
 
 size_t neighbour_record_bytes() { return sizeof(NbRec); }
+int64_t neighbour_slots(int64_t n) { return n * kNbSub; }
 
 void launch_neighbours(Ctx *c, const GasBins &b, int64_t n, const unsigned *perm, const double *xyz, const double *h,
-                       const uint2 *sl, unsigned *count, const unsigned *nb_off, void *rec)
+                       unsigned *count, const unsigned *nb_off, void *rec)
 {
     if (n <= 0) return;
     if (!nb_off)
-        neighbours<false><<<blocks_for(n), kThreads, 0, c->stream>>>(n, perm, xyz, h, b.box, b.delta, b.G, b.cls.K,
-                                                                     b.start, b.pos_h, b.idx, sl, count, nullptr,
-                                                                     nullptr);
+        neighbours<false><<<blocks_for(n * kNbSub), kThreads, 0, c->stream>>>(n, perm, xyz, h, b.box, b.delta, b.G, b.cls.K,
+                                                                     b.start, b.pos_h, b.idx, count, nullptr, nullptr);
     else
-        neighbours<true><<<blocks_for(n), kThreads, 0, c->stream>>>(n, perm, xyz, h, b.box, b.delta, b.G, b.cls.K,
-                                                                    b.start, b.pos_h, b.idx, sl, nullptr, nb_off,
+        neighbours<true><<<blocks_for(n * kNbSub), kThreads, 0, c->stream>>>(n, perm, xyz, h, b.box, b.delta, b.G, b.cls.K,
+                                                                    b.start, b.pos_h, b.idx, nullptr, nb_off,
                                                                     (NbRec *)rec);
 }
 
 void launch_pair_owner(Ctx *c, int64_t n, const uint2 *sl, unsigned *owner)
 {
     if (n > 0) pair_owner<<<blocks_for(n), kThreads, 0, c->stream>>>(n, sl, owner);
+}
+
+void launch_coarse_keys(Ctx *c, int64_t n, uint64_t *keys)
+{
+    if (n > 0) coarse_keys<<<blocks_for(n), kThreads, 0, c->stream>>>(n, keys);
 }
 
 void launch_layout_counts(Ctx *c, int64_t n, const unsigned *perm, const int64_t *counts, unsigned *lc)
@@ -546,18 +536,18 @@ void launch_layout_starts(Ctx *c, int64_t n, const unsigned *perm, const unsigne
 
 void launch_upstream_parent(Ctx *c, const Tree *t, int64_t n_pairs, int64_t n, const double *xyz, const double *nhi,
                             const uint2 *sl, const uint64_t *keys, const unsigned *owner, const unsigned *nb_off,
-                            const void *rec, const unsigned *bits, unsigned W, double sigma, int *parent, double *acc,
+                            const void *rec, const unsigned *bits, unsigned W, double sigma, void *links,
                             unsigned *roots, unsigned *n_roots)
 {
     if (n_pairs <= 0) return;
     if (bits)
         upstream_parent<true><<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(
             n_pairs, n, xyz, nhi, sl, keys, owner, nb_off, (const NbRec *)rec, t->mom, t->src, t->first, t->n_nodes,
-            bits, W, sigma, t->box.length_unit_cm, parent, acc, roots, n_roots);
+            bits, W, sigma, t->box.length_unit_cm, (Link *)links, roots, n_roots);
     else
         upstream_parent<false><<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(
             n_pairs, n, xyz, nhi, sl, keys, owner, nb_off, (const NbRec *)rec, t->mom, t->src, t->first, t->n_nodes,
-            nullptr, 0u, sigma, t->box.length_unit_cm, parent, acc, roots, n_roots);
+            nullptr, 0u, sigma, t->box.length_unit_cm, (Link *)links, roots, n_roots);
 }
 
 void launch_member_bits(Ctx *c, const Tree *t, int64_t n, int64_t n_pairs, const uint64_t *keys, const uint2 *sl,
@@ -575,10 +565,7 @@ void launch_member_bits(Ctx *c, const Tree *t, int64_t n, int64_t n_pairs, const
     }
 }
 
-void launch_pack_links(Ctx *c, int64_t n_pairs, const int *par, const double *acc, void *links)
-{
-    if (n_pairs > 0) pack_links<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, par, acc, (Link *)links);
-}
+size_t upstream_link_bytes() { return sizeof(Link); }
 
 void launch_jump_links(Ctx *c, int64_t n_pairs, const void *in, void *out, unsigned *more)
 {
@@ -586,24 +573,20 @@ void launch_jump_links(Ctx *c, int64_t n_pairs, const void *in, void *out, unsig
         jump_links<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, (const Link *)in, (Link *)out, more);
 }
 
-void launch_unpack_acc(Ctx *c, int64_t n_pairs, const void *links, double *acc)
-{
-    if (n_pairs > 0) unpack_acc<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, (const Link *)links, acc);
-}
-
 void launch_upstream_gamma(Ctx *c, const Tree *t, int64_t n, const double *xyz, const uint2 *sl,
-                           const uint64_t *keys, const double *tau, double sigma, double *gamma)
+                           const uint64_t *keys, const void *links, double sigma, double *gamma)
 {
     if (n > 0)
-        upstream_gamma<<<blocks_for(n * 64), kThreads, 0, c->stream>>>(n, xyz, sl, keys, tau, t->mom, t->src,
+        upstream_gamma<<<blocks_for(n * 64), kThreads, 0, c->stream>>>(n, xyz, sl, keys, (const Link *)links, t->mom, t->src,
                                                                        t->first, sigma, t->box.length_unit_cm, gamma);
 }
 
-void launch_parent_particle(Ctx *c, int64_t n_pairs, const int *parent, const unsigned *owner, const uint2 *sl,
+void launch_parent_particle(Ctx *c, int64_t n_pairs, const void *links, const unsigned *owner, const uint2 *sl,
                             const int64_t *ooff, int64_t *out)
 {
     if (n_pairs > 0)
-        parent_particle<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, parent, owner, sl, ooff, out);
+        parent_particle<<<blocks_for(n_pairs), kThreads, 0, c->stream>>>(n_pairs, (const Link *)links, owner, sl,
+                                                                          ooff, out);
 }
 
 }  // namespace start
