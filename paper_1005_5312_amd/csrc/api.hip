@@ -718,11 +718,17 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     if (st) return done(st == START_ENOMEM && c.budget ? START_EBUDGET : st);
     have_bins = true;
     launch_neighbours(&c, bins, n, perm, gas_xyz, gas_h, nbc, nullptr, nullptr);
+    // their total in 64 bits, checked before the 32-bit scan is used
+    hipMemsetAsync(total64, 0, sizeof(unsigned long long), s);
+    launch_sum_u32(&c, nslots, nbc, total64);
+    unsigned long long nb_total = 0;
+    hipMemcpyAsync(&nb_total, total64, sizeof(nb_total), hipMemcpyDeviceToHost, s);
     hipMemsetAsync(nbc + nslots, 0, sizeof(unsigned), s);
     exclusive_scan_u32(nbc, nslots + 1, nb_scan_tmp, s);
-    unsigned n_nb = 0;
-    hipMemcpyAsync(&n_nb, nbc + nslots, sizeof(unsigned), hipMemcpyDeviceToHost, s);
     if (hipStreamSynchronize(s) != hipSuccess) return done(fail(ctx, START_EHIP, "neighbour count failed"));
+    if (!neighbour_pairs_fit(nb_total))
+        return done(fail(ctx, START_ECAPACITY, "more than 2^31 - 1 neighbour pairs"));
+    const unsigned n_nb = (unsigned)nb_total;
     void *nrec = alloc((size_t)(n_nb > 0 ? n_nb : 1) * neighbour_record_bytes());
     if (!nrec) return nomem();
     launch_neighbours(&c, bins, n, perm, gas_xyz, gas_h, nullptr, nbc, nrec);

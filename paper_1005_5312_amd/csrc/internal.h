@@ -291,6 +291,7 @@ void launch_upstream_roots(Ctx *c, const Tree *t, const Grid *g, int64_t n_roots
 void launch_to_u32(Ctx *c, int64_t n, const int64_t *in, unsigned *out);
 // *total += sum of n non-negative int64 values (64-bit accumulation)
 void launch_sum_i64(Ctx *c, int64_t n, const int64_t *in, unsigned long long *total);
+void launch_sum_u32(Ctx *c, int64_t n, const unsigned *in, unsigned long long *total);
 void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out);
 // Neighbours within 2 h_i (particles taken in the Morton order perm), each
 // particle's search split over neighbour_slots(n) / n threads: counts per

@@ -14,4 +14,9 @@ namespace start {
 constexpr uint64_t kMaxUpstreamPairs = ((uint64_t)1 << 31) - 1;
 inline bool upstream_pairs_fit(uint64_t total) { return total <= kMaxUpstreamPairs; }
 
+// The neighbour pairs (particle, neighbour within 2h) are indexed the same
+// way: their counts are summed in 64 bits and more than 2^31 - 1 refused.
+constexpr uint64_t kMaxNeighbourPairs = ((uint64_t)1 << 31) - 1;
+inline bool neighbour_pairs_fit(uint64_t total) { return total <= kMaxNeighbourPairs; }
+
 }  // namespace start

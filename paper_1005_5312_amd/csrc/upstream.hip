@@ -97,13 +97,15 @@ __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const unsigned
     if (!FILL) count[(int64_t)i * kNbSub + sub] = c;
 }
 
+// owner[p] = the particle of pair p; one wave per particle (coalesced writes)
 __global__ void __launch_bounds__(kThreads) pair_owner(int64_t n, const uint2 *__restrict__ sl,
                                                        unsigned *__restrict__ owner)
 {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+    const unsigned lane = threadIdx.x & 63u;
     if (i >= n) return;
     const uint2 r = sl[i];
-    for (unsigned k = 0; k < r.y; ++k) owner[r.x + k] = (unsigned)i;
+    for (unsigned k = lane; k < r.y; k += 64u) owner[r.x + k] = (unsigned)i;
 }
 
 // The pairs' layout: each particle's pairs stay contiguous, and the
@@ -444,8 +446,9 @@ __global__ void __launch_bounds__(kThreads) to_u32(int64_t n, const int64_t *__r
 
 // 64-bit sum of non-negative counts: a block sum (wave reductions, then one
 // 64-bit atomic per block)
-__global__ void __launch_bounds__(kThreads) sum_i64(int64_t n, const int64_t *__restrict__ in,
-                                                    unsigned long long *__restrict__ total)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) sum_counts(int64_t n, const T *__restrict__ in,
+                                                       unsigned long long *__restrict__ total)
 {
     __shared__ unsigned long long part[kThreads / 64];
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -490,7 +493,12 @@ void launch_to_u32(Ctx *c, int64_t n, const int64_t *in, unsigned *out)
 
 void launch_sum_i64(Ctx *c, int64_t n, const int64_t *in, unsigned long long *total)
 {
-    if (n > 0) sum_i64<<<blocks_for(n), kThreads, 0, c->stream>>>(n, in, total);
+    if (n > 0) sum_counts<int64_t><<<blocks_for(n), kThreads, 0, c->stream>>>(n, in, total);
+}
+
+void launch_sum_u32(Ctx *c, int64_t n, const unsigned *in, unsigned long long *total)
+{
+    if (n > 0) sum_counts<unsigned><<<blocks_for(n), kThreads, 0, c->stream>>>(n, in, total);
 }
 
 void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out)
@@ -516,7 +524,7 @@ void launch_neighbours(Ctx *c, const GasBins &b, int64_t n, const unsigned *perm
 
 void launch_pair_owner(Ctx *c, int64_t n, const uint2 *sl, unsigned *owner)
 {
-    if (n > 0) pair_owner<<<blocks_for(n), kThreads, 0, c->stream>>>(n, sl, owner);
+    if (n > 0) pair_owner<<<blocks_for(n * 64), kThreads, 0, c->stream>>>(n, sl, owner);
 }
 
 void launch_coarse_keys(Ctx *c, int64_t n, uint64_t *keys)

@@ -1,7 +1,7 @@
 """Host-side size guards of the C-ABI library (csrc/limits.h), compiled on
-their own with the host compiler: the upstream chain's pair total is refused
-above 2^31 - 1, including totals that a 32-bit sum would wrap to a small
-value."""
+their own with the host compiler: the upstream chain's pair total and its
+neighbour-pair total are refused above 2^31 - 1, including totals that a
+32-bit sum would wrap to a small value."""
 import os
 import subprocess
 
@@ -31,6 +31,12 @@ int main(void)
     unsigned long long total = 0;
     for (int i = 0; i < 65536; ++i) total += 65537ull;
     if (upstream_pairs_fit(total) || (unsigned)total == total) { printf("sum\n"); bad = 1; }
+    /* the neighbour pairs: the same limit */
+    for (unsigned k = 0; k < sizeof(cases) / sizeof(cases[0]); ++k)
+        if ((int)start::neighbour_pairs_fit(cases[k][0]) != (int)cases[k][1]) {
+            printf("neighbours: wrong for %llu\n", cases[k][0]);
+            bad = 1;
+        }
     return bad;
 }
 """
