@@ -702,7 +702,7 @@ start_status start_compute_rates_upstream(start_ctx *ctx, const start_tree *tree
     char *links = (char *)alloc(2 * lb_bytes);
     unsigned *roots = (unsigned *)alloc(Eb * sizeof(unsigned));
     unsigned *words = (unsigned *)alloc(256);   // [0] root count, [1] "more" flag
-    const int64_t nslots = neighbour_slots(n);
+    const int64_t nslots = n;   // one neighbour count per particle
     unsigned *nbc = (unsigned *)alloc((size_t)(nslots + 1) * sizeof(unsigned));
     void *nb_scan_tmp = alloc(scan_temp_bytes(nslots + 1));
     if (!keys || !owner || !links || !roots || !words || !nbc || !nb_scan_tmp) return nomem();

@@ -293,14 +293,11 @@ void launch_to_u32(Ctx *c, int64_t n, const int64_t *in, unsigned *out);
 void launch_sum_i64(Ctx *c, int64_t n, const int64_t *in, unsigned long long *total);
 void launch_sum_u32(Ctx *c, int64_t n, const unsigned *in, unsigned long long *total);
 void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out);
-// Neighbours within 2 h_i (particles taken in the Morton order perm), each
-// particle's search split over neighbour_slots(n) / n threads: counts per
-// slot (nb_off null) into count[neighbour_slots(n)], or, with nb_off = the
-// exclusive scan of those counts (neighbour_slots(n) + 1 entries), one
-// record per neighbour (position and index) of neighbour_record_bytes()
-// bytes; particle i's records are nb_off[i s, (i + 1) s), s = slots / n.
+// Neighbours within 2 h_i (one wave per particle, the particles taken in the
+// Morton order perm): counts (nb_off null) into count[n], or, with nb_off =
+// the exclusive scan of those counts (n + 1 entries), one record per
+// neighbour (position and index) of neighbour_record_bytes() bytes.
 size_t neighbour_record_bytes();
-int64_t neighbour_slots(int64_t n);
 void launch_neighbours(Ctx *c, const GasBins &b, int64_t n, const unsigned *perm, const double *xyz, const double *h,
                        unsigned *count, const unsigned *nb_off, void *rec);
 // The pairs' layout: each particle's list contiguous, the lists in the

@@ -32,15 +32,13 @@ struct __align__(16) NbRec {
 };
 
 // Neighbours within 2 h_i, found through the particles binned by grid cell.
-// kNbSub threads share a particle, each taking every kNbSub-th row of cells,
-// and the particles come in Morton order (perm), so that a wave's particles
-// search overlapping cells.  FILL = false counts into count[i kNbSub + sub];
-// FILL = true writes the records from nb_off[i kNbSub + sub] (the counts
-// scanned), so particle i's neighbours are nb_off[i kNbSub, (i + 1) kNbSub).
-// One thread per particle is the fastest measured (8 threads per particle:
-// 2.4x slower, the rows' loops diverge).
-constexpr int kNbSub = 1;
-
+// One wave per particle (the particles taken in Morton order, perm): its
+// lanes take one row of cells each (per reach class, x and y of the search
+// box), cut to the cells that the sphere of radius 2h reaches, and step
+// through their rows' particles together; a ballot of the
+// ones within 2h gives each its place, so the records come out in a fixed
+// order (row chunk, step, lane).  FILL = false writes the count to count[i];
+// FILL = true writes the records from nb_off[i] (the counts scanned).
 template <bool FILL>
 __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const unsigned *__restrict__ perm,
                                                        const double *__restrict__ xyz,
@@ -50,11 +48,10 @@ __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const unsigned
                                                        const unsigned *__restrict__ idx, unsigned *__restrict__ count,
                                                        const unsigned *__restrict__ nb_off, NbRec *__restrict__ rec)
 {
-    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const int64_t rk = g / kNbSub;
-    const int sub = (int)(g % kNbSub);
-    if (rk >= n) return;
-    const unsigned i = perm[rk];
+    const int64_t w = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+    const unsigned lane = threadIdx.x & 63u;
+    if (w >= n) return;         // whole waves leave together
+    const unsigned i = perm[w];
     const double x[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
     const double r = 2.0 * h[i];
     const double r2 = r * r;
@@ -66,35 +63,64 @@ __global__ void __launch_bounds__(kThreads) neighbours(int64_t n, const unsigned
         lo[k] = a < 0 ? 0 : (a > G - 1 ? G - 1 : a);
         hi[k] = b < 0 ? 0 : (b > G - 1 ? G - 1 : b);
     }
-    unsigned c = 0;
-    const unsigned base = FILL ? nb_off[(int64_t)i * kNbSub + sub] : 0u;
+    const int nb = hi[1] - lo[1] + 1;
+    const int per_class = (hi[0] - lo[0] + 1) * nb;
+    const int rows = K * per_class;
     const int64_t ncell = (int64_t)G * G * G;
-    int rr = 0;
-    for (int k = 0; k < K; ++k)   // every reach class of the binning
-    for (int a = lo[0]; a <= hi[0]; ++a)
-        for (int b = lo[1]; b <= hi[1]; ++b) {
-            if (rr++ % kNbSub != sub) continue;
-            const int64_t row = k * ncell + ((int64_t)a * G + b) * G;
-            const unsigned s0 = start[row + lo[2]], s1 = start[row + hi[2] + 1];
-            for (unsigned s = s0; s < s1; ++s) {
-                const unsigned j = idx[s];
-                if (j == i) continue;
-                const double4 q = pos_h[s];
-                const double ex = q.x - x[0], ey = q.y - x[1], ez = q.z - x[2];
-                if (!(ex * ex + ey * ey + ez * ez <= r2)) continue;
-                if (FILL) {
-                    NbRec o;
-                    o.x = q.x;
-                    o.y = q.y;
-                    o.z = q.z;
-                    o.j = j;
-                    o.pad = 0u;
-                    rec[base + c] = o;
-                }
-                ++c;
+    const unsigned base = FILL ? nb_off[i] : 0u;
+    unsigned total = 0;         // the same in every lane
+    for (int r0 = 0; r0 < rows; r0 += 64) {
+        const int rw = r0 + (int)lane;
+        unsigned s0 = 0, len = 0;
+        if (rw < rows) {
+            const int k = rw / per_class, rem = rw - k * per_class;
+            const int a = lo[0] + rem / nb, b = lo[1] + rem % nb;
+            // the row's cells, widened by eps, against the sphere of radius
+            // 2h: skip a row that misses it, and keep only the cells of the
+            // chord through it (eps = 1e-6 cell covers the rounding of the
+            // binning's floor((x - lo) G / size))
+            const double eps = 1e-6 * delta;
+            const double ax = box.lo[0] + a * delta, by = box.lo[1] + b * delta;
+            const double dx = fmax(0.0, fmax(ax - eps - x[0], x[0] - (ax + delta + eps)));
+            const double dy = fmax(0.0, fmax(by - eps - x[1], x[1] - (by + delta + eps)));
+            const double dxy = dx * dx + dy * dy;
+            if (dxy <= r2) {
+                const double hz = sqrt(r2 - dxy);
+                int z0 = (int)floor((x[2] - hz - eps - box.lo[2]) / delta);
+                int z1 = (int)floor((x[2] + hz + eps - box.lo[2]) / delta);
+                z0 = z0 < 0 ? 0 : (z0 > G - 1 ? G - 1 : z0);
+                z1 = z1 < 0 ? 0 : (z1 > G - 1 ? G - 1 : z1);
+                const int64_t row = k * ncell + ((int64_t)a * G + b) * G;
+                s0 = start[row + z0];
+                len = start[row + z1 + 1] - s0;
             }
         }
-    if (!FILL) count[(int64_t)i * kNbSub + sub] = c;
+        unsigned steps = len;
+        for (int d = 32; d > 0; d >>= 1) steps = max(steps, (unsigned)__shfl_xor((int)steps, d, 64));
+        for (unsigned t = 0; t < steps; ++t) {
+            bool take = false;
+            unsigned j = 0;
+            double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (t < len) {
+                j = idx[s0 + t];
+                q = pos_h[s0 + t];
+                const double ex = q.x - x[0], ey = q.y - x[1], ez = q.z - x[2];
+                take = j != i && ex * ex + ey * ey + ez * ez <= r2;
+            }
+            const uint64_t m = __ballot(take);
+            if (FILL && take) {
+                NbRec o;
+                o.x = q.x;
+                o.y = q.y;
+                o.z = q.z;
+                o.j = j;
+                o.pad = 0u;
+                rec[base + total + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = o;
+            }
+            total += (unsigned)__popcll(m);
+        }
+    }
+    if (!FILL && lane == 0) count[i] = total;
 }
 
 // owner[p] = the particle of pair p; one wave per particle (coalesced writes)
@@ -319,7 +345,7 @@ __global__ void __launch_bounds__(kThreads) upstream_parent(
     // word is loaded as its iteration starts and used after the geometric
     // tests (loading it a neighbour ahead as well took more registers than
     // it hid latency)
-    const unsigned t0 = nb_off[(int64_t)i * kNbSub], t1 = nb_off[(int64_t)(i + 1) * kNbSub];
+    const unsigned t0 = nb_off[i], t1 = nb_off[i + 1];
     NbRec qn;
     qn.x = qn.y = qn.z = 0.0;
     qn.j = qn.pad = 0u;
@@ -507,17 +533,16 @@ void launch_to_i64(Ctx *c, int64_t n, const unsigned *in, int64_t *out)
 }
 
 size_t neighbour_record_bytes() { return sizeof(NbRec); }
-int64_t neighbour_slots(int64_t n) { return n * kNbSub; }
 
 void launch_neighbours(Ctx *c, const GasBins &b, int64_t n, const unsigned *perm, const double *xyz, const double *h,
                        unsigned *count, const unsigned *nb_off, void *rec)
 {
     if (n <= 0) return;
     if (!nb_off)
-        neighbours<false><<<blocks_for(n * kNbSub), kThreads, 0, c->stream>>>(n, perm, xyz, h, b.box, b.delta, b.G, b.cls.K,
+        neighbours<false><<<blocks_for(n * 64), kThreads, 0, c->stream>>>(n, perm, xyz, h, b.box, b.delta, b.G, b.cls.K,
                                                                      b.start, b.pos_h, b.idx, count, nullptr, nullptr);
     else
-        neighbours<true><<<blocks_for(n * kNbSub), kThreads, 0, c->stream>>>(n, perm, xyz, h, b.box, b.delta, b.G, b.cls.K,
+        neighbours<true><<<blocks_for(n * 64), kThreads, 0, c->stream>>>(n, perm, xyz, h, b.box, b.delta, b.G, b.cls.K,
                                                                     b.start, b.pos_h, b.idx, nullptr, nb_off,
                                                                     (NbRec *)rec);
 }
