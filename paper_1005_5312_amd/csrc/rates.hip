@@ -118,6 +118,24 @@ __device__ inline bool accept(const int4 g, const double u[3], double theta2)
 
 __device__ inline int clampi(int v, int G) { return v < 0 ? 0 : (v >= G ? G - 1 : v); }
 
+// Tree records at a wave-uniform index, read through the scalar cache (the
+// walk's node pointer is the same in every lane, and the tree is read-only
+// while a kernel runs): a generic load would take a vector load per lane
+// and wait on the LDS counter as well.
+using CI = const __attribute__((address_space(4))) int;
+using CU = const __attribute__((address_space(4))) unsigned;
+using CD = const __attribute__((address_space(4))) double;
+__device__ inline int4 uni_int4(const int4 *a, int i)
+{
+    CI *p = (CI *)a + 4 * (int64_t)i;
+    return make_int4(p[0], p[1], p[2], p[3]);
+}
+__device__ inline int uni_int(const int *a, int64_t i) { return ((CI *)a)[i]; }
+__device__ inline unsigned uni_u32(const unsigned *a, int64_t i) { return ((CU *)a)[i]; }
+// the luminosity (.w) of a double4 or uint4 record
+__device__ inline double uni_w(const double4 *a, int64_t i) { return ((CD *)a)[4 * i + 3]; }
+__device__ inline unsigned uni_w(const uint4 *a, int64_t i) { return ((CU *)a)[4 * i + 3]; }
+
 // Orders LDS traffic between the lanes of one wavefront (no block barrier:
 // the waves of a block are independent).
 __device__ inline void wave_sync()
@@ -374,28 +392,32 @@ __global__ void __launch_bounds__(kThreads) list_kernel(const Item *__restrict__
     const int n_nodes = (int)P.n_nodes;
     while (node < n_nodes) {
         node = __builtin_amdgcn_readfirstlane(node);
-        const int4 g = P.geo[node];
+        const int4 g = uni_int4(P.geo, node);
         const int kind = g.w >> 8;
         const bool active = valid && node >= resume;
         if (kind == kKindLeaf) {
-            if (active && (int64_t)P.ref[node] != self)
-                emit(-(int64_t)P.ref[node] - 1, (uint64_t)node << 32, P.mom[node].w);
+            const int ref = uni_int(P.ref, node);
+            if (active && (int64_t)ref != self) emit(-(int64_t)ref - 1, (uint64_t)node << 32, uni_w(P.mom, node));
             node += 1;
             continue;
         }
-        const int sk = P.skip[node];
+        const int sk = uni_int(P.skip, node);
         const bool acc = active && accept(g, u, P.theta2);
         if (acc) {
-            emit(node, (uint64_t)node << 32, P.mom[node].w);
+            emit(node, (uint64_t)node << 32, uni_w(P.mom, node));
             resume = sk;
         }
         const bool open = active && !acc;
         if (kind == kKindBucket) {
-            if (open)
-                for (int q = P.first[node]; q < P.first[node] + P.count[node]; ++q)
-                    if ((int64_t)P.perm[q] != self)
-                        emit(-(int64_t)P.perm[q] - 1, (uint64_t)node << 32 | (uint64_t)(q - P.first[node] + 1),
-                             P.src[q].w);
+            if (__any(open)) {
+                const int f = uni_int(P.first, node), cnt = uni_int(P.count, node);
+                for (int q = f; q < f + cnt; ++q) {
+                    const unsigned pq = uni_u32(P.perm, q);
+                    const double lq = uni_w(P.src, q);
+                    if (open && (int64_t)pq != self)
+                        emit(-(int64_t)pq - 1, (uint64_t)node << 32 | (uint64_t)(q - f + 1), lq);
+                }
+            }
             node += 1;
             continue;
         }
@@ -532,6 +554,17 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
     const T col_scale = (T)P.col_scale;
     const int sh = 32 - gl;
 
+    // the node and source arrays of the item, read once per tile (the item
+    // is the same for the whole wave): each march then selects its record's
+    // address between two registers instead of loading the array pointer,
+    // and reads it as global memory (a generic load would also wait on LDS)
+    using GD = const __attribute__((address_space(1))) double;
+    using GU = const __attribute__((address_space(1))) unsigned;
+    GD *const mom = (GD *)P.mom;
+    GD *const src = (GD *)P.src;
+    GU *const momq = (GU *)P.momq;
+    GU *const srcq = (GU *)P.srcq;
+
     // March one item: the term L e^-tau / d^2 (d in cells) of ring slot `slot`.
     auto march_item = [&](int slot, T &term, int &nc) {
         const int code = L.code[slot];
@@ -560,7 +593,8 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
         int ab[3];
         T w;
         if (PREC == START_FP64) {
-            const double4 m = code >= 0 ? P.mom[code] : P.src[-code - 1];
+            GD *const r = code >= 0 ? mom + 4 * (int64_t)code : src + 4 * (int64_t)(-code - 1);
+            const double4 m = make_double4(r[0], r[1], r[2], r[3]);
             const double A[3] = {(m.x - P.lo[0]) * P.gs, (m.y - P.lo[1]) * P.gs, (m.z - P.lo[2]) * P.gs};
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -573,7 +607,8 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
         } else {
             // centre as 32-bit fixed point of the box: the top g bits are the
             // cell, the rest the fraction inside it (exact in FP64)
-            const uint4 m = code >= 0 ? P.momq[code] : P.srcq[-code - 1];
+            GU *const r = code >= 0 ? momq + 4 * (int64_t)code : srcq + 4 * (int64_t)(-code - 1);
+            const uint4 m = make_uint4(r[0], r[1], r[2], r[3]);
             const unsigned q[3] = {m.x, m.y, m.z};
             const unsigned fmask = (1u << sh) - 1u;
 #pragma unroll
@@ -667,31 +702,31 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
     const int n_nodes = (int)P.n_nodes;
     while (node < n_nodes) {
         node = __builtin_amdgcn_readfirstlane(node);
-        const int4 g = P.geo[node];
+        const int4 g = uni_int4(P.geo, node);
         const int kind = g.w >> 8;
         const bool active = valid && node >= resume;
         if (kind == kKindLeaf) {
-            const float lw = fp32 ? __uint_as_float(P.momq[node].w) : (float)(P.mom[node].w > 0.0);
-            push(active && P.ref[node] != self && lw > 0.f, node);
+            const float lw = fp32 ? __uint_as_float(uni_w(P.momq, node)) : (float)(uni_w(P.mom, node) > 0.0);
+            push(active && uni_int(P.ref, node) != self && lw > 0.f, node);
             node += 1;
             continue;
         }
-        const int sk = P.skip[node];
+        const int sk = uni_int(P.skip, node);
         bool acc_node = false;
         if (active) {
             if (STATS) st_test++;
             acc_node = accept(g, u, P.theta2);
         }
         if (acc_node) resume = sk;
-        const float lw = fp32 ? __uint_as_float(P.momq[node].w) : (float)(P.mom[node].w > 0.0);
+        const float lw = fp32 ? __uint_as_float(uni_w(P.momq, node)) : (float)(uni_w(P.mom, node) > 0.0);
         push(acc_node && lw > 0.f, node);
         const bool open = active && !acc_node;
         if (kind == kKindBucket) {
             if (__any(open)) {
-                const int f = P.first[node], cnt = P.count[node];
+                const int f = uni_int(P.first, node), cnt = uni_int(P.count, node);
                 for (int q = f; q < f + cnt; ++q) {
-                    const float qw = fp32 ? __uint_as_float(P.srcq[q].w) : (float)(P.src[q].w > 0.0);
-                    push(open && (int)P.perm[q] != self && qw > 0.f, -q - 1);
+                    const float qw = fp32 ? __uint_as_float(uni_w(P.srcq, q)) : (float)(uni_w(P.src, q) > 0.0);
+                    push(open && (int)uni_u32(P.perm, q) != self && qw > 0.f, -q - 1);
                 }
             }
             node += 1;
