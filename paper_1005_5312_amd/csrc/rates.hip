@@ -564,6 +564,11 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
     GD *const src = (GD *)P.src;
     GU *const momq = (GU *)P.momq;
     GU *const srcq = (GU *)P.srcq;
+    // the item's scalars, also read once per tile
+    const double frac_scale = P.frac_scale, gs = P.gs;
+    const double lo[3] = {P.lo[0], P.lo[1], P.lo[2]};
+    const int sx = P.sx, sy = P.sy, channel = P.channel;
+    const T *const grid_base = (PREC == START_FP64 ? (const T *)P.grid : (const T *)P.gridf) - guard;
 
     // March one item: the term L e^-tau / d^2 (d in cells) of ring slot `slot`.
     auto march_item = [&](int slot, T &term, int &nc) {
@@ -584,7 +589,7 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             for (int k = 0; k < 3; ++k) {
                 const unsigned q = L.tfrac[tl][k];
                 tb[k] = (int)(q >> sh);
-                fb[k] = (double)(q & fmask) * P.frac_scale;
+                fb[k] = (double)(q & fmask) * frac_scale;
             }
         }
         // the ray runs from the (virtual) source (t = 0) to the target (t = 1):
@@ -595,7 +600,7 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
         if (PREC == START_FP64) {
             GD *const r = code >= 0 ? mom + 4 * (int64_t)code : src + 4 * (int64_t)(-code - 1);
             const double4 m = make_double4(r[0], r[1], r[2], r[3]);
-            const double A[3] = {(m.x - P.lo[0]) * P.gs, (m.y - P.lo[1]) * P.gs, (m.z - P.lo[2]) * P.gs};
+            const double A[3] = {(m.x - lo[0]) * gs, (m.y - lo[1]) * gs, (m.z - lo[2]) * gs};
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 // a source on the top face sits in the last cell at fraction 1
@@ -614,22 +619,21 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 ab[k] = (int)(q[k] >> sh);
-                fa[k] = (double)(q[k] & fmask) * P.frac_scale;
+                fa[k] = (double)(q[k] & fmask) * frac_scale;
                 D[k] = (double)(tb[k] - ab[k]) + (fb[k] - fa[k]);
             }
             w = (T)__uint_as_float(m.w);
         }
         const double d2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
         if (d2 > 0.0) {
-            const unsigned e0 = (unsigned)(ab[0] * P.sx + ab[1] * P.sy + ab[2] + guard);
-            const T *base = (PREC == START_FP64 ? (const T *)P.grid : (const T *)P.gridf) - guard;
-            const T col = march<T, STATS, CLAMP>(base, P.sx, P.sy, (unsigned)(last + guard), e0, fa, D, nc);
+            const unsigned e0 = (unsigned)(ab[0] * sx + ab[1] * sy + ab[2] + guard);
+            const T col = march<T, STATS, CLAMP>(grid_base, sx, sy, (unsigned)(last + guard), e0, fa, D, nc);
             // FP32C: the term from the hardware square root, exp2 and
             // reciprocal (each ~1 ulp; the argument of exp2 is rounded to
             // ~6e-8 relative, i.e. 6e-8 tau of the term), FP64 as written
             const T dist = PREC == START_FP64 ? (T)sqrt(d2) : (T)__builtin_amdgcn_sqrtf((float)d2);   // grid units
             const T c = col_scale * (col * dist);
-            if (P.channel == 0)                                // c = tau
+            if (channel == 0)                                  // c = tau
                 term = PREC == START_FP64 ? w * exp(-c) / (T)d2
                                           : (T)(w * __builtin_amdgcn_exp2f((float)c * -1.44269504f) *
                                                 __builtin_amdgcn_rcpf((float)d2));
