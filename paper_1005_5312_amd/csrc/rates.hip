@@ -702,35 +702,47 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
     };
 
     const bool fp32 = PREC == START_FP32C;
+    // the tree's arrays and the opening angle, read once per tile
+    const int4 *const t_geo = P.geo;
+    const int *const t_skip = P.skip;
+    const int *const t_ref = P.ref;
+    const int *const t_first = P.first;
+    const int *const t_count = P.count;
+    const unsigned *const t_perm = P.perm;
+    const double4 *const t_mom = P.mom;
+    const double4 *const t_src = P.src;
+    const uint4 *const t_momq = P.momq;
+    const uint4 *const t_srcq = P.srcq;
+    const double theta2 = P.theta2;
     int resume = 0, node = 0;
     const int n_nodes = (int)P.n_nodes;
     while (node < n_nodes) {
         node = __builtin_amdgcn_readfirstlane(node);
-        const int4 g = uni_int4(P.geo, node);
+        const int4 g = uni_int4(t_geo, node);
         const int kind = g.w >> 8;
         const bool active = valid && node >= resume;
         if (kind == kKindLeaf) {
-            const float lw = fp32 ? __uint_as_float(uni_w(P.momq, node)) : (float)(uni_w(P.mom, node) > 0.0);
-            push(active && uni_int(P.ref, node) != self && lw > 0.f, node);
+            const float lw = fp32 ? __uint_as_float(uni_w(t_momq, node)) : (float)(uni_w(t_mom, node) > 0.0);
+            push(active && uni_int(t_ref, node) != self && lw > 0.f, node);
             node += 1;
             continue;
         }
-        const int sk = uni_int(P.skip, node);
+        const int sk = uni_int(t_skip, node);
         bool acc_node = false;
         if (active) {
             if (STATS) st_test++;
-            acc_node = accept(g, u, P.theta2);
+            acc_node = accept(g, u, theta2);
         }
         if (acc_node) resume = sk;
-        const float lw = fp32 ? __uint_as_float(uni_w(P.momq, node)) : (float)(uni_w(P.mom, node) > 0.0);
+        const float lw = fp32 ? __uint_as_float(uni_w(t_momq, node)) : (float)(uni_w(t_mom, node) > 0.0);
         push(acc_node && lw > 0.f, node);
         const bool open = active && !acc_node;
         if (kind == kKindBucket) {
             if (__any(open)) {
-                const int f = uni_int(P.first, node), cnt = uni_int(P.count, node);
+                const int f = uni_int(t_first, node), cnt = uni_int(t_count, node);
                 for (int q = f; q < f + cnt; ++q) {
-                    const float qw = fp32 ? __uint_as_float(uni_w(P.srcq, q)) : (float)(uni_w(P.src, q) > 0.0);
-                    push(open && (int)uni_u32(P.perm, q) != self && qw > 0.f, -q - 1);
+                    const float qw = fp32 ? __uint_as_float(uni_w(t_srcq, q)) : (float)(uni_w(t_src, q) > 0.0);
+                    push(open && (int)uni_u32(t_perm, q) != self && qw > 0.f, -q - 1);
                 }
             }
             node += 1;
