@@ -388,32 +388,42 @@ __global__ void __launch_bounds__(kThreads) list_kernel(const Item *__restrict__
         if (MODE == kKeys) P.entries[out_base + n_entries] = (int64_t)key;
         ++n_entries;
     };
+    const int4 *const t_geo = P.geo;
+    const int *const t_skip = P.skip;
+    const int *const t_ref = P.ref;
+    const int *const t_first = P.first;
+    const int *const t_count = P.count;
+    const unsigned *const t_perm = P.perm;
+    const double4 *const t_mom = P.mom;
+    const double4 *const t_src = P.src;
+    const double theta2 = P.theta2;
     int resume = 0, node = 0;
     const int n_nodes = (int)P.n_nodes;
     while (node < n_nodes) {
         node = __builtin_amdgcn_readfirstlane(node);
-        const int4 g = uni_int4(P.geo, node);
+        const int4 g = uni_int4(t_geo, node);
+        const int sk = uni_int(t_skip, node);
+        const double lw = uni_w(t_mom, node);
+        const int ref = uni_int(t_ref, node);
         const int kind = g.w >> 8;
         const bool active = valid && node >= resume;
         if (kind == kKindLeaf) {
-            const int ref = uni_int(P.ref, node);
-            if (active && (int64_t)ref != self) emit(-(int64_t)ref - 1, (uint64_t)node << 32, uni_w(P.mom, node));
+            if (active && (int64_t)ref != self) emit(-(int64_t)ref - 1, (uint64_t)node << 32, lw);
             node += 1;
             continue;
         }
-        const int sk = uni_int(P.skip, node);
-        const bool acc = active && accept(g, u, P.theta2);
+        const bool acc = active && accept(g, u, theta2);
         if (acc) {
-            emit(node, (uint64_t)node << 32, uni_w(P.mom, node));
+            emit(node, (uint64_t)node << 32, lw);
             resume = sk;
         }
         const bool open = active && !acc;
         if (kind == kKindBucket) {
             if (__any(open)) {
-                const int f = uni_int(P.first, node), cnt = uni_int(P.count, node);
+                const int f = uni_int(t_first, node), cnt = uni_int(t_count, node);
                 for (int q = f; q < f + cnt; ++q) {
-                    const unsigned pq = uni_u32(P.perm, q);
-                    const double lq = uni_w(P.src, q);
+                    const unsigned pq = uni_u32(t_perm, q);
+                    const double lq = uni_w(t_src, q);
                     if (open && (int64_t)pq != self)
                         emit(-(int64_t)pq - 1, (uint64_t)node << 32 | (uint64_t)(q - f + 1), lq);
                 }
@@ -718,23 +728,25 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
     const int n_nodes = (int)P.n_nodes;
     while (node < n_nodes) {
         node = __builtin_amdgcn_readfirstlane(node);
+        // the node's record, subtree end, luminosity and source index are
+        // read together (one wait for all four scalar loads)
         const int4 g = uni_int4(t_geo, node);
+        const int sk = uni_int(t_skip, node);
+        const float lw = fp32 ? __uint_as_float(uni_w(t_momq, node)) : (float)(uni_w(t_mom, node) > 0.0);
+        const int rf = uni_int(t_ref, node);
         const int kind = g.w >> 8;
         const bool active = valid && node >= resume;
         if (kind == kKindLeaf) {
-            const float lw = fp32 ? __uint_as_float(uni_w(t_momq, node)) : (float)(uni_w(t_mom, node) > 0.0);
-            push(active && uni_int(t_ref, node) != self && lw > 0.f, node);
+            push(active && rf != self && lw > 0.f, node);
             node += 1;
             continue;
         }
-        const int sk = uni_int(t_skip, node);
         bool acc_node = false;
         if (active) {
             if (STATS) st_test++;
             acc_node = accept(g, u, theta2);
         }
         if (acc_node) resume = sk;
-        const float lw = fp32 ? __uint_as_float(uni_w(t_momq, node)) : (float)(uni_w(t_mom, node) > 0.0);
         push(acc_node && lw > 0.f, node);
         const bool open = active && !acc_node;
         if (kind == kKindBucket) {
