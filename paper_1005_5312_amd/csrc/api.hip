@@ -1351,9 +1351,13 @@ size_t start_estimate_bytes(int64_t n_t, int64_t n_s, int64_t n_gas, int grid_lo
     const int64_t G = (int64_t)1 << grid_log2, pad = (G >= 64 && G <= 512) ? 16 : 0;
     const size_t span = (size_t)((G - 1) * (G * (G + pad) + pad) + (G - 1) * (G + pad) + G);   // padded grid
     // tree: persistent (keys, perm, sources, 2 n_s nodes) + build temporaries
-    const size_t tree = (size_t)n_s * (8 + 4 + 32 + 16) + (size_t)2 * n_s * (16 + 16 + 32 + 16) +
+    const size_t tree = (size_t)n_s * (8 + 4 + 32 + 16) + (size_t)2 * n_s * (16 + 16 + 32 + 16 + 32) +
                         radix_temp_bytes(2 * n_s) + (size_t)n_s * 48 + (size_t)2 * n_s * 45 + 65536;
-    const size_t grid = span * 12 + (size_t)n_gas * 56 + radix_temp_bytes(n_gas) + G3 * 4 * kMaxReachClasses + 65536;
+    // both grid copies with their guard bands (G <= 512)
+    const int64_t sy = G + pad, sx = G * sy + pad;
+    const size_t guard = G <= 512 ? (size_t)(6 * (sx + sy + 1)) : 0;
+    const size_t grid = (span + 2 * guard) * 12 + (size_t)n_gas * 56 + radix_temp_bytes(n_gas) +
+                        G3 * 4 * kMaxReachClasses + 65536;
     const size_t rates = (batch_scratch_bytes(n_t, 1, n_t) * 5) / 4 + 65536;   // up to one tile per target
     return tree + grid + rates;
 }

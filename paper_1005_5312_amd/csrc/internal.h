@@ -77,6 +77,7 @@ struct Tree {
     int64_t n_src = 0;
     int64_t n_nodes = 0;
     int4 *geo = nullptr;       // (cx, cy, cz, level | kind << 8)
+    double4 *bnd = nullptr;    // the cube in normalised units: lower corner (c 2^-level) and side 2^-level
     int *skip = nullptr;       // index of the first node after the subtree
     int *first = nullptr;      // range of the cell in sorted source order
     int *count = nullptr;

@@ -44,6 +44,7 @@ struct Item {
     int64_t n_nodes;
     int64_t n_src;
     const int4 *geo;
+    const double4 *bnd;
     const int *skip;
     const int *first;
     const int *count;
@@ -116,6 +117,24 @@ __device__ inline bool accept(const int4 g, const double u[3], double theta2)
     return l * l <= theta2 * d2;
 }
 
+// The same test from the cube's stored corner and side (b = (lo x, lo y, lo z,
+// side), the exact values of c 2^-n and 2^-n; lo + side = (c + 1) 2^-n is
+// exact too), so it decides as accept() does, bit for bit.
+__device__ inline bool accept_box(const double4 b, const double u[3], double theta2)
+{
+    const double lo[3] = {b.x, b.y, b.z};
+    double d[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double a = lo[k] - u[k];
+        const double c = u[k] - (lo[k] + b.w);
+        const double m = a > c ? a : c;
+        d[k] = m > 0.0 ? m : 0.0;
+    }
+    const double d2 = fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+    return b.w * b.w <= theta2 * d2;
+}
+
 __device__ inline int clampi(int v, int G) { return v < 0 ? 0 : (v >= G ? G - 1 : v); }
 
 // Tree records at a wave-uniform index, read through the scalar cache (the
@@ -132,6 +151,11 @@ __device__ inline int4 uni_int4(const int4 *a, int i)
 }
 __device__ inline int uni_int(const int *a, int64_t i) { return ((CI *)a)[i]; }
 __device__ inline unsigned uni_u32(const unsigned *a, int64_t i) { return ((CU *)a)[i]; }
+__device__ inline double4 uni_d4(const double4 *a, int i)
+{
+    CD *p = (CD *)a + 4 * (int64_t)i;
+    return make_double4(p[0], p[1], p[2], p[3]);
+}
 // the luminosity (.w) of a double4 or uint4 record
 __device__ inline double uni_w(const double4 *a, int64_t i) { return ((CD *)a)[4 * i + 3]; }
 __device__ inline unsigned uni_w(const uint4 *a, int64_t i) { return ((CU *)a)[4 * i + 3]; }
@@ -714,6 +738,7 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
     const bool fp32 = PREC == START_FP32C;
     // the tree's arrays and the opening angle, read once per tile
     const int4 *const t_geo = P.geo;
+    const double4 *const t_bnd = P.bnd;
     const int *const t_skip = P.skip;
     const int *const t_ref = P.ref;
     const int *const t_first = P.first;
@@ -744,7 +769,7 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
         bool acc_node = false;
         if (active) {
             if (STATS) st_test++;
-            acc_node = accept(g, u, theta2);
+            acc_node = accept_box(uni_d4(t_bnd, node), u, theta2);
         }
         if (acc_node) resume = sk;
         push(acc_node && lw > 0.f, node);
@@ -996,6 +1021,7 @@ Item make_item(const RateSpec &r, const BatchScratch &bs, int64_t off)
     I.n_nodes = t->n_nodes;
     I.n_src = t->n_src;
     I.geo = t->geo;
+    I.bnd = t->bnd;
     I.skip = t->skip;
     I.first = t->first;
     I.count = t->count;

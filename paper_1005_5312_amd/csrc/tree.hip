@@ -172,7 +172,8 @@ __global__ void __launch_bounds__(kThreads) emit_items(int n, const int *lo, con
 __global__ void __launch_bounds__(kThreads) fill_nodes(int n, int64_t m, const uint64_t *k, const unsigned *perm,
                                                        const int *lo, const int *hi, const int *delta,
                                                        const unsigned *item_code, const unsigned *pos_start,
-                                                       int4 *geo, int *skip, int *first, int *count, int *ref)
+                                                       int4 *geo, int *skip, int *first, int *count, int *ref,
+                                                       double4 *bnd)
 {
     const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (p >= m) return;
@@ -197,8 +198,11 @@ __global__ void __launch_bounds__(kThreads) fill_nodes(int n, int64_t m, const u
         r = (int)perm[f];
     }
     const uint64_t prefix = level > 0 ? (k[f] >> (3 * (kMaxLevel - level))) : 0ull;
-    geo[p] = make_int4((int)compact3(prefix >> 2), (int)compact3(prefix >> 1), (int)compact3(prefix),
-                       level | (kind << 8));
+    const int cx = (int)compact3(prefix >> 2), cy = (int)compact3(prefix >> 1), cz = (int)compact3(prefix);
+    geo[p] = make_int4(cx, cy, cz, level | (kind << 8));
+    // the cube's lower corner and side in normalised units (exact: c < 2^21)
+    bnd[p] = make_double4(ldexp((double)cx, -level), ldexp((double)cy, -level), ldexp((double)cz, -level),
+                          ldexp(1.0, -level));
     skip[p] = (int)pos_start[f + c];
     first[p] = f;
     count[p] = c;
@@ -571,7 +575,8 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     // persistent arrays
     size_t persist = al(n * sizeof(uint64_t)) + al(n * sizeof(unsigned)) + al(n * sizeof(double4)) +
                      al(n * sizeof(uint4)) + al(max_items * sizeof(int4)) + 4 * al(max_items * sizeof(int)) +
-                     al(max_items * sizeof(double4)) + al(max_items * sizeof(uint4)) + al(sizeof(double));
+                     al(max_items * sizeof(double4)) + al(max_items * sizeof(uint4)) + al(sizeof(double)) +
+                     al(max_items * sizeof(double4));
     char *pm = nullptr;
     if (dmalloc(c, (void **)&pm, persist) != hipSuccess) return START_ENOMEM;
     t->bytes = persist;
@@ -589,6 +594,7 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     t->mom = (double4 *)take(max_items * sizeof(double4));
     t->momq = (uint4 *)take(max_items * sizeof(uint4));
     t->lscale = (double *)take(sizeof(double));
+    t->bnd = (double4 *)take(max_items * sizeof(double4));
 
     // temporaries
     size_t tmp_bytes = al(radix_temp_bytes(max_items)) + 6 * al(n * sizeof(int)) + 2 * al(n * sizeof(unsigned)) +
@@ -672,7 +678,7 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     radix_sort_pairs(item_key, item_code, m, bits, radix_tmp, s);
     exclusive_scan_u32(first_count, n + 1, scan_tmp, s);   // pos_start[i] = items with first < i
     fill_nodes<<<blocks_for(m), kThreads, 0, s>>>(ni, m, t->keys, t->perm, blo, bhi, bdelta, item_code, first_count,
-                                                  t->geo, t->skip, t->first, t->count, t->ref);
+                                                  t->geo, t->skip, t->first, t->count, t->ref, t->bnd);
     node_levels<<<blocks_for(m), kThreads, 0, s>>>(m, t->geo, lvl);
     for (int lv = 0; lv <= kMaxLevel; ++lv)
         moments_level<<<blocks_for(m), kThreads, 0, s>>>(m, lv, lvl, t->geo, t->skip, t->first, t->count, t->src,
