@@ -97,29 +97,9 @@ struct Item {
 // Eq. (12): l^2 <= theta^2 d^2 in normalised units, d the distance to the
 // closest point of the cube [c 2^-n, (c+1) 2^-n].  Written as the same FP64
 // operations as the oracle (explicit fma, no contraction) so that the lists
-// agree bit for bit.
-__device__ inline bool accept(const int4 g, const double u[3], double theta2)
-{
-    const int level = g.w & 0xFF;
-    const double l = ldexp(1.0, -level);
-    const int c[3] = {g.x, g.y, g.z};
-    double d[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double lo = ldexp((double)c[k], -level);
-        const double hi = ldexp((double)(c[k] + 1), -level);
-        const double a = lo - u[k];
-        const double b = u[k] - hi;
-        const double m = a > b ? a : b;
-        d[k] = m > 0.0 ? m : 0.0;
-    }
-    const double d2 = fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
-    return l * l <= theta2 * d2;
-}
-
-// The same test from the cube's stored corner and side (b = (lo x, lo y, lo z,
-// side), the exact values of c 2^-n and 2^-n; lo + side = (c + 1) 2^-n is
-// exact too), so it decides as accept() does, bit for bit.
+// agree bit for bit.  b = (lo x, lo y, lo z, side): the cube's corner c 2^-n
+// and side 2^-n stored at the tree build (exact, c < 2^21), and lo + side =
+// (c + 1) 2^-n is exact too.
 __device__ inline bool accept_box(const double4 b, const double u[3], double theta2)
 {
     const double lo[3] = {b.x, b.y, b.z};
@@ -413,6 +393,7 @@ __global__ void __launch_bounds__(kThreads) list_kernel(const Item *__restrict__
         ++n_entries;
     };
     const int4 *const t_geo = P.geo;
+    const double4 *const t_bnd = P.bnd;
     const int *const t_skip = P.skip;
     const int *const t_ref = P.ref;
     const int *const t_first = P.first;
@@ -436,7 +417,7 @@ __global__ void __launch_bounds__(kThreads) list_kernel(const Item *__restrict__
             node += 1;
             continue;
         }
-        const bool acc = active && accept(g, u, theta2);
+        const bool acc = active && accept_box(uni_d4(t_bnd, node), u, theta2);
         if (acc) {
             emit(node, (uint64_t)node << 32, lw);
             resume = sk;
