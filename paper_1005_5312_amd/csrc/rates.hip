@@ -472,14 +472,21 @@ __device__ inline unsigned fixed32(double x, double lo, double inv)
     return q >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned)q;
 }
 
+// A node's record in the ring: the first slot (absolute) of its items and
+// the lanes that took it, side by side so that one LDS read fetches both.
+struct __align__(16) NodeRec {
+    int start;
+    int pad;
+    uint64_t mask;
+};
+
 // TF: the target's fraction inside its cell in FP64 for the FP64 path; for
 // the FP32 path its 32-bit box fixed-point coordinates (fixed32; tcell is
 // then unused).
 template <typename T, typename TF>
 struct WaveLds {
-    uint64_t rec_mask[kRing];     // per node: lanes that took it
+    NodeRec rec[kRing];           // per node: first slot, lanes that took it
     int code[kRing];              // node index, or -(sorted source index)-1
-    int rec_start[kRing];         // per node: first slot (absolute) of its items
     T term[kRing];
     unsigned tcell[kWave];        // target cell, linear index
     TF tfrac[kWave][3];           // target fraction inside its cell (FP64), or fixed32 coordinates
@@ -672,9 +679,12 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
         wave_sync();
         const int end = head + nb_items;
         while (rhead < rtail) {
-            const int rs = __builtin_amdgcn_readfirstlane(L.rec_start[rhead & (kRing - 1)]);
+            // the whole record in one read (start in .x, the mask in .z, .w)
+            const uint4 r = *reinterpret_cast<const uint4 *>(&L.rec[rhead & (kRing - 1)]);
+            const int rs = __builtin_amdgcn_readfirstlane((int)r.x);
+            const uint64_t m = ((uint64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)r.w) << 32) |
+                               (uint64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)r.z);
             if (rs >= end) break;
-            const uint64_t m = L.rec_mask[rhead & (kRing - 1)];
             if ((m >> lane) & 1ull) {
                 const int s = rs + lanes_below(m);
                 if (s >= head && s < end) {
@@ -707,8 +717,11 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             if (STATS) st_entries++;
         }
         if (lane == 0) {
-            L.rec_start[rtail & (kRing - 1)] = tail;
-            L.rec_mask[rtail & (kRing - 1)] = m;
+            NodeRec r;
+            r.start = tail;
+            r.pad = 0;
+            r.mask = m;
+            L.rec[rtail & (kRing - 1)] = r;
         }
         ++rtail;
         tail += __popcll(m);
