@@ -678,13 +678,16 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
         if (STATS) lds_ncell[slot] = nc;
         wave_sync();
         const int end = head + nb_items;
+        // each record in one read (start in .x, the mask in .z, .w), the next
+        // one read while this one's terms are added
+        uint4 r = make_uint4(0u, 0u, 0u, 0u);
+        if (rhead < rtail) r = *reinterpret_cast<const uint4 *>(&L.rec[rhead & (kRing - 1)]);
         while (rhead < rtail) {
-            // the whole record in one read (start in .x, the mask in .z, .w)
-            const uint4 r = *reinterpret_cast<const uint4 *>(&L.rec[rhead & (kRing - 1)]);
             const int rs = __builtin_amdgcn_readfirstlane((int)r.x);
             const uint64_t m = ((uint64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)r.w) << 32) |
                                (uint64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)r.z);
             if (rs >= end) break;
+            if (rhead + 1 < rtail) r = *reinterpret_cast<const uint4 *>(&L.rec[(rhead + 1) & (kRing - 1)]);
             if ((m >> lane) & 1ull) {
                 const int s = rs + lanes_below(m);
                 if (s >= head && s < end) {
