@@ -485,12 +485,17 @@ struct __align__(16) NodeRec {
 // then unused).
 template <typename T, typename TF>
 struct WaveLds {
+    static constexpr bool kFp64 = sizeof(TF) == 8;
     NodeRec rec[kRing];           // per node: first slot, lanes that took it
-    int code[kRing];              // node index, or -(sorted source index)-1
+    // FP32 path: the item whole (code, then the target's fixed32
+    // coordinates), so that a march reads it in one access
+    uint4 qitem[kFp64 ? 1 : kRing];
+    // FP64 path: the item as code and target lane
+    int code[kFp64 ? kRing : 1];  // node index, or -(sorted source index)-1
     T term[kRing];
-    unsigned tcell[kWave];        // target cell, linear index
-    TF tfrac[kWave][3];           // target fraction inside its cell (FP64), or fixed32 coordinates
-    unsigned char lane[kRing];    // target lane of the item
+    unsigned tcell[kWave];        // FP64 path: target cell, linear index
+    TF tfrac[kFp64 ? kWave : 1][3];   // FP64 path: target fraction inside its cell
+    unsigned char lane[kFp64 ? kRing : 1];   // FP64 path: target lane of the item
 };
 
 
@@ -539,6 +544,7 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
     double u[3] = {0.0, 0.0, 0.0};
     unsigned orig = 0;
     int self = -1;   // source indices fit in 31 bits (n_s <= 2^30)
+    unsigned tq[3] = {0u, 0u, 0u};   // FP32 path: this lane's target as fixed32 box coordinates
     {
         int bi[3] = {0, 0, 0};
         double fb[3] = {0.0, 0.0, 0.0};
@@ -564,9 +570,9 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             L.tfrac[lane][2] = fb[2];
         } else {
             const double4 p = valid ? P.tgt[it] : make_double4(P.lo[0], P.lo[1], P.lo[2], 0.0);
-            L.tfrac[lane][0] = fixed32(p.x, P.lo[0], P.inv_size);
-            L.tfrac[lane][1] = fixed32(p.y, P.lo[1], P.inv_size);
-            L.tfrac[lane][2] = fixed32(p.z, P.lo[2], P.inv_size);
+            tq[0] = fixed32(p.x, P.lo[0], P.inv_size);
+            tq[1] = fixed32(p.y, P.lo[1], P.inv_size);
+            tq[2] = fixed32(p.z, P.lo[2], P.inv_size);
         }
     }
 
@@ -594,8 +600,18 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
 
     // March one item: the term L e^-tau / d^2 (d in cells) of ring slot `slot`.
     auto march_item = [&](int slot, T &term, int &nc) {
-        const int code = L.code[slot];
-        const int tl = L.lane[slot];
+        int code, tl = 0;
+        unsigned qt[3] = {0u, 0u, 0u};
+        if constexpr (PREC == START_FP64) {
+            code = L.code[slot];
+            tl = L.lane[slot];
+        } else {
+            const uint4 q = L.qitem[slot];
+            code = (int)q.x;
+            qt[0] = q.y;
+            qt[1] = q.z;
+            qt[2] = q.w;
+        }
         int tb[3];
         double fb[3];
         if constexpr (PREC == START_FP64) {
@@ -609,9 +625,8 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             const unsigned fmask = (1u << sh) - 1u;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const unsigned q = L.tfrac[tl][k];
-                tb[k] = (int)(q >> sh);
-                fb[k] = (double)(q & fmask) * frac_scale;
+                tb[k] = (int)(qt[k] >> sh);
+                fb[k] = (double)(qt[k] & fmask) * frac_scale;
             }
         }
         // the ray runs from the (virtual) source (t = 0) to the target (t = 1):
@@ -715,8 +730,12 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
         if (m == 0) return;
         if (want) {
             const int s = (tail + lanes_below(m)) & (kRing - 1);
-            L.code[s] = code;
-            L.lane[s] = (unsigned char)lane;
+            if constexpr (PREC == START_FP64) {
+                L.code[s] = code;
+                L.lane[s] = (unsigned char)lane;
+            } else {
+                L.qitem[s] = make_uint4((unsigned)code, tq[0], tq[1], tq[2]);
+            }
             if (STATS) st_entries++;
         }
         if (lane == 0) {
