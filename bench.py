@@ -8,8 +8,12 @@ marches that produces Gamma for every particle.  value = particles / step time.
 
 Also measured in the same run: the rate call alone with tree and grid
 resident (FP32C and FP64), the walk kernel's duration from HIP events on the
-library's stream (roofline against HBM bandwidth with the algorithmic byte
-model), and the CPU FP64 oracle on a bounded sample (cpu_baseline).
+library's stream (roofline: the algorithmic byte model against the HBM peak,
+the bound and issue fractions from the committed counter summaries), the
+CPU FP64 oracle on the whole workload (cpu_baseline), and the other
+configurations: batching and rate plans, the served request mix, the
+opening-angle sweep, the shadowing configuration, the equilibrium loops,
+H2 photodissociation and the upstream-particle chain.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload diffuse]
 """
