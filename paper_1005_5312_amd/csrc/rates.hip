@@ -169,29 +169,32 @@ __device__ inline int lanes_below(uint64_t m)
 // the 2e-4 target.  TV is the type of the grid values (FP32 or
 // FP64); the sum is FP64 in both cases.  Returns sum n_c dt.
 //
-// The step is branch-free: the next crossing is the minimum m of the three
-// plane parameters, every axis whose parameter equals m moves to its next
-// plane (two at once where the ray passes exactly through an edge, which
-// only skips a chord of zero length), and the cell offset moves by the
-// strides of those axes.  The cell sequence depends on the geometry only,
-// so the loads run ahead of the sum: three cells ahead in the rate kernels
-// (three gathers in flight per lane hide most of the L1 / L2 latency: 7%
-// faster in FP32 and 16% in FP64 than one), one ahead in the counter pass,
-// which has no registers to spare.  FP32 cells are addressed by 32-bit byte
-// offset from the grid base (below 2^32 for G <= 1024), which the hardware
-// adds to the base in the load itself.  The hot loop is L1- and
-// latency-bound: one gather per step and lane, about 22 VALU instructions
-// per step.
+// The step has no branch: the next crossing is the minimum m of the three
+// plane parameters, the first axis whose parameter equals m moves to its next
+// plane, and the cell offset moves by that axis's stride (where the ray
+// passes exactly through an edge or a corner, the other axes at m follow in
+// the next steps with chords of length 0, which add exactly nothing).  The
+// cell sequence depends on the geometry only, so the loads run ahead of the
+// sum: three cells ahead in the rate kernels (three gathers in flight per
+// lane hide most of the L1 / L2 latency: 7% faster in FP32 and 16% in FP64
+// than one), one ahead in the counter pass, which has no registers to spare.
+// Cells are addressed by a 32-bit byte offset from the grid base, which the
+// hardware adds to the base in the load itself (below 2^32 for FP32 cells at
+// G <= 1024 and for FP64 cells at G <= 512, the grids with guard bands;
+// FP64 cells of the largest grid take an element index).  The hot loop is
+// L1- and VALU-bound: one gather and 14 VALU instructions per step and lane
+// in FP32C, 13 in FP64.
 //
-// The loop ends: each step moves at least one axis whose parameter is below
-// 1, by a_k >= 1 / (2 G) (|D| is below 2G for points in the box; the step is
-// exact since a_k is far above the spacing of doubles below 1), so after at
-// most 2G + 2 steps per axis every parameter is >= 1.  A NaN parameter is
-// never the minimum (v_min_f64 returns the other operand), an all-NaN state
-// exits at once, and +inf never steps (the FP32 march's t = min(m, 1)
-// reaches 1 at the same step, and at once for NaN).  Positions reaching the kernel are
-// finite and inside the box (checked on entry), so no extra step counter is
-// kept: one costs 4-8% here, as it changes how the loop is scheduled.
+// The loop ends: each step moves an axis whose parameter equals m, by a_k >=
+// 1 / (2 G) (|D| is below 2G for points in the box; the step is exact since
+// a_k is far above the spacing of doubles below 1), so after at most
+// 3 (2G + 2) steps every parameter is >= 1.  Positions reaching the kernel
+// are finite and inside the box (checked on entry), so the parameters are
+// finite.  Were m NaN, it would not equal any parameter and z would step
+// while t = min(m, 1) is 1 (v_min_f64 returns the non-NaN operand): the
+// rate march ends with its turn, three steps on, and the counter pass at
+// once.  No extra step counter is kept: one costs 4-8% here, as it changes
+// how the loop is scheduled.
 // ---------------------------------------------------------------------------
 // 1 / d for d > 0 to full FP64 precision: hardware reciprocal and two Newton
 // steps (the inputs are finite, normal magnitudes: ray components in cells).
@@ -231,15 +234,47 @@ __device__ inline double fsh(double x)
 
 typedef const __attribute__((address_space(1))) char gchar_t;
 
-// cell value at a byte offset (FP32) or an index (FP64) from the grid base
-__device__ inline float load_cell(const float *grid, unsigned off)
+// cell value at an offset from the grid base: in bytes (S = 1 byte per unit),
+// which the hardware adds to the SGPR base in the load itself, or as an
+// element index (S = the cell size, one address computation per load)
+template <unsigned S, typename TV>
+__device__ inline TV load_cell(const TV *grid, unsigned off)
 {
-    return *(const __attribute__((address_space(1))) float *)((gchar_t *)grid + off);
+    if constexpr (S == 1)
+        return *(const __attribute__((address_space(1))) TV *)((gchar_t *)grid + off);
+    else
+        return *((const __attribute__((address_space(1))) TV *)grid + off);
 }
 
-__device__ inline double load_cell(const double *grid, unsigned idx)
+// One step of the march: the first axis (x, then y, then z) whose plane
+// parameter equals the minimum m moves to its next plane, and the cell offset
+// by that axis's stride.  Where the ray passes exactly through an edge or a
+// corner the other axes at m follow in the next steps, each with a chord of
+// length 0 (which adds exactly nothing).  The three moves run under lane
+// masks (exec set from the two comparisons), so each is one add per axis
+// instead of a select and an add for every axis: 8 vector instructions per
+// step for the comparisons and moves against 14.  The masks come from the
+// active lanes only and exec is restored at the end of the block.
+__device__ inline void step_axis(double tn[3], const double a[3], const int ds[3], double m, unsigned &off)
 {
-    return *((const __attribute__((address_space(1))) double *)grid + idx);
+    const uint64_t m0 = __builtin_amdgcn_ballot_w64(tn[0] == m);
+    const uint64_t m1 = __builtin_amdgcn_ballot_w64(tn[1] == m);
+    uint64_t sv, tmp;
+    asm volatile(
+        "s_and_saveexec_b64 %[sv], %[m0]\n\t"
+        "v_add_f64 %[t0], %[t0], %[a0]\n\t"
+        "v_add_u32 %[off], %[off], %[d0]\n\t"
+        "s_andn2_b64 exec, %[m1], %[m0]\n\t"
+        "v_add_f64 %[t1], %[t1], %[a1]\n\t"
+        "v_add_u32 %[off], %[off], %[d1]\n\t"
+        "s_or_b64 %[tmp], %[m0], %[m1]\n\t"
+        "s_andn2_b64 exec, %[sv], %[tmp]\n\t"
+        "v_add_f64 %[t2], %[t2], %[a2]\n\t"
+        "v_add_u32 %[off], %[off], %[d2]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [t0] "+v"(tn[0]), [t1] "+v"(tn[1]), [t2] "+v"(tn[2]), [off] "+v"(off), [sv] "=&s"(sv), [tmp] "=&s"(tmp)
+        : [m0] "s"(m0), [m1] "s"(m1), [a0] "v"(a[0]), [a1] "v"(a[1]), [a2] "v"(a[2]), [d0] "v"(ds[0]),
+          [d1] "v"(ds[1]), [d2] "v"(ds[2]));
 }
 
 template <typename TV, bool STATS, bool CLAMP>
@@ -249,7 +284,10 @@ __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned
     // Axis k crosses its next plane at tn_k and every 1/|D_k| after it.  In
     // FP64 stepping tn_k by a_k drifts by ~1 ulp per step: over the <= 3G
     // steps of a ray that is ~1e-11 cell, far inside every tolerance.
-    constexpr unsigned kScale = sizeof(TV) == 4 ? 4u : 1u;   // offset units per cell
+    // offset units per cell: bytes, except for FP64 cells on a grid without
+    // guard bands (G = 1024), whose bytes can pass 2^32
+    constexpr unsigned kScale = sizeof(TV) == 8 && CLAMP ? 1u : (unsigned)sizeof(TV);
+    constexpr unsigned kUnit = kScale == 1 ? (unsigned)sizeof(TV) : 1u;   // bytes per offset unit
     const int stride[3] = {sx, sy, 1};
     double a[3], tn[3];
     int ds[3];
@@ -284,13 +322,9 @@ __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned
     // leave the current cell (t = m) for the next one and load its value
     auto advance = [&](TV &vnext) {
         t = m;
-        const bool s0 = tn[0] == m, s1 = tn[1] == m, s2 = tn[2] == m;
-        tn[0] = fma(s0 ? 1.0 : 0.0, a[0], tn[0]);
-        tn[1] = fma(s1 ? 1.0 : 0.0, a[1], tn[1]);
-        tn[2] = fma(s2 ? 1.0 : 0.0, a[2], tn[2]);
-        off += (s0 ? (unsigned)ds[0] : 0u) + (s1 ? (unsigned)ds[1] : 0u) + (s2 ? (unsigned)ds[2] : 0u);
+        step_axis(tn, a, ds, m, off);
         if (CLAMP) off = off > off_max ? off_max : off;   // also catches a step below 0
-        vnext = load_cell(grid, off);
+        vnext = load_cell<kUnit>(grid, off);
         m = min3(tn[0], tn[1], tn[2]);
     };
     if constexpr (!STATS) {
@@ -304,21 +338,17 @@ __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned
         // length 0) enters with the same three loads in flight, so no wait
         // for all of them.  Each step is kept in place by a scheduling
         // barrier so that its load is issued within it.
-        TV vB = load_cell(grid, off);
-        TV vC = load_cell(grid, off);
-        TV vA = load_cell(grid, off);
+        TV vB = load_cell<kUnit>(grid, off);
+        TV vC = load_cell<kUnit>(grid, off);
+        TV vA = load_cell<kUnit>(grid, off);
         double lA = 0.0, lB = 0.0, lC = 0.0;
         auto leave = [&](double &len, TV &vnext) {
             const double mc = vmin(m, 1.0);   // a NaN m gives 1: the lane ends
             len = mc - t;
             t = mc;
-            const bool s0 = tn[0] == m, s1 = tn[1] == m, s2 = tn[2] == m;
-            tn[0] = fma(s0 ? 1.0 : 0.0, a[0], tn[0]);
-            tn[1] = fma(s1 ? 1.0 : 0.0, a[1], tn[1]);
-            tn[2] = fma(s2 ? 1.0 : 0.0, a[2], tn[2]);
-            off += (s0 ? (unsigned)ds[0] : 0u) + (s1 ? (unsigned)ds[1] : 0u) + (s2 ? (unsigned)ds[2] : 0u);
+            step_axis(tn, a, ds, m, off);
             if (CLAMP) off = off > off_max ? off_max : off;   // also catches a step below 0
-            vnext = load_cell(grid, off);
+            vnext = load_cell<kUnit>(grid, off);
             m = min3(tn[0], tn[1], tn[2]);
         };
         for (;;) {
@@ -338,7 +368,7 @@ __device__ inline TV march(const TV *__restrict__ grid, int sx, int sy, unsigned
         return (TV)sum;
     } else {
         // the counter pass: one load ahead
-        TV v = load_cell(grid, off);
+        TV v = load_cell<kUnit>(grid, off);
         // two steps per turn (no register copies between them)
         for (;;) {
             if (!(m < 1.0)) break;
