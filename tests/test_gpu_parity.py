@@ -528,6 +528,48 @@ def test_rays_ending_on_faces_edges_and_planes(ctx, grid_log2):
             assert rel <= tol and ab <= H.ABS_FLOOR
 
 
+@pytest.mark.parametrize("grid_log2", [4, 6])
+def test_rays_through_grid_edges_and_corners(ctx, grid_log2):
+    """Sources and targets on grid vertices of a box of side 8, exact in both
+    precisions' coordinates, so that the rays between them pass exactly
+    through grid edges and corners: two or three plane parameters are equal
+    at many crossings (at every one along the (1, 1, 0) and (1, 1, 1)
+    diagonals), where the march moves one axis per step and the others
+    follow with chords of length 0 (a reading of the paper's ray
+    integration: the exact integral is unchanged).  Theta 0 and 1, both
+    precisions, against the oracle, which sorts all crossings."""
+    import dataclasses
+    G = 1 << grid_log2
+    side = 8.0
+    print(f"[case] rays through grid edges and corners, G = {G}", flush=True)
+    w0 = H.W.make_clumpy(seed=60 + grid_log2, n_gas=4096, n_src=8)
+    k = side / w0.box_size
+    w = dataclasses.replace(w0, box_size=side, gas_xyz=w0.gas_xyz * k, gas_h=w0.gas_h * k)
+    rng = np.random.default_rng(70 + grid_log2)
+    d = side / G
+    src = rng.integers(1, G, (3, 12)).astype(np.float64) * d
+    lum = 10.0 ** rng.uniform(47.0, 50.0, src.shape[1])
+    dirs = np.array([[1, 1, 0], [1, 1, 1], [1, -1, 2], [2, 2, 1], [-1, 1, 1], [0, 1, 1]], np.float64)
+    tg = [src[:, j] + m * v * d for j in range(4) for v in dirs for m in (1, 2, 3)]
+    tg = [p for p in tg if np.all(p >= 0.0) and np.all(p <= side)]
+    tgt = np.concatenate([np.array(tg).T, rng.integers(0, G + 1, (3, 64)).astype(np.float64) * d], axis=1)
+    tgt = np.ascontiguousarray(tgt)
+    box, obox = H.box_of(w), H.obox_of(w)
+    tree = ctx.build_source_tree(box, dev(src), dev(lum))
+    grid = ctx.build_gas_grid(box, dev(w.gas_xyz), dev(w.gas_h), dev(w.gas_nhi), grid_log2)
+    ot = O.Tree(obox, src, lum)
+    og = O.grid(obox, w.gas_xyz, w.gas_h, w.gas_nhi, grid_log2)
+    for theta in (0.0, 1.0):
+        want = O.rates(ot, grid_log2, og, tgt, None, theta, w.sigma)
+        assert np.count_nonzero(want > H.FLOOR) > tgt.shape[1] // 2
+        for prec, tol in (("fp64", H.TOL_FP64), ("fp32c", H.TOL_FP32C)):
+            got = ctx.compute_rates(tree, grid, dev(tgt), None, theta, w.sigma, prec)
+            ctx.synchronize()
+            rel, ab, _ = H.rel_errors(got.cpu().numpy(), want)
+            print(f"  theta {theta} {prec}: max rel {rel:.2e}", flush=True)
+            assert rel <= tol and ab <= H.ABS_FLOOR
+
+
 def test_largest_grids(ctx):
     """The largest grids: G = 512 (the largest with a guard band) against the
     oracle, on a sparse field (65536 particles with kernels of 0.6 cells, so
