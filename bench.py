@@ -899,6 +899,10 @@ def main():
     valu_frac = cnt_p["SQ_INSTS_VALU"] / cyc if cnt_p else None
     l1_rate = cnt_p["TCP_TOTAL_CACHE_ACCESSES_sum"] / cyc if cnt_p else None
     hbm_frac = traffic / t_k / (HBM_PEAK_GBS * 1e9) if traffic else None
+    # the texture addresser (vector memory address path) busy share from the
+    # same counter pass as the L1 accesses (GRBM_GUI_ACTIVE sums the 8 XCDs)
+    ta_frac = (cnt_p["TA_BUSY_avr"] / (cnt_p["GRBM_GUI_ACTIVE_pass_b"] / 8.0)
+               if cnt_p and "TA_BUSY_avr" in cnt_p and cnt_p.get("GRBM_GUI_ACTIVE_pass_b") else None)
     if valu_frac is not None:
         bound = "alu" if valu_frac >= (hbm_frac or 0.0) else "hbm"
     else:
@@ -911,6 +915,7 @@ def main():
                               "'traffic'",
                 "valu_issue_frac": round(valu_frac, 4) if valu_frac is not None else None,
                 "l1_accesses_per_cu_cycle": round(l1_rate, 4) if l1_rate is not None else None,
+                "ta_busy_frac": round(ta_frac, 4) if ta_frac is not None else None,
                 "hbm_traffic_frac": round(hbm_frac, 4) if hbm_frac is not None else None,
                 "counters": "profiles/rates_kernel_fp32c_{}_sq_tcp_counters.txt".format(args.workload)
                 if cnt_p else None,
