@@ -175,9 +175,10 @@ __device__ inline int lanes_below(uint64_t m)
 // passes exactly through an edge or a corner, the other axes at m follow in
 // the next steps with chords of length 0, which add exactly nothing).  The
 // cell sequence depends on the geometry only, so the loads run ahead of the
-// sum: three cells ahead in the rate kernels (three gathers in flight per
-// lane hide most of the L1 / L2 latency: 7% faster in FP32 and 16% in FP64
-// than one), one ahead in the counter pass, which has no registers to spare.
+// sum: three cells ahead in the rate kernels, four for FP64 cells (gathers
+// in flight per lane hide most of the L1 / L2 latency: three are 7% faster
+// in FP32 and 16% in FP64 than one), one ahead in the counter pass, which
+// has no registers to spare.
 // Cells are addressed by a 32-bit byte offset from the grid base, which the
 // hardware adds to the base in the load itself (below 2^32 for FP32 cells at
 // G <= 1024 and for FP64 cells at G <= 512, the grids with guard bands;
@@ -192,8 +193,8 @@ __device__ inline int lanes_below(uint64_t m)
 // are finite and inside the box (checked on entry), so the parameters are
 // finite.  Were m NaN, it would not equal any parameter and z would step
 // while t = min(m, 1) is 1 (v_min_f64 returns the non-NaN operand): the
-// rate march ends with its turn, three steps on, and the counter pass at
-// once.  No extra step counter is kept: one costs 4-8% here, as it changes
+// rate march ends with its turn (three or four steps on) and the counter
+// pass at once.  No extra step counter is kept: one costs 4-8% here, as it changes
 // how the loop is scheduled.
 // ---------------------------------------------------------------------------
 // 1 / d for d > 0 to full FP64 precision: hardware reciprocal and two Newton
