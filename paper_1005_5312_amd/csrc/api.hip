@@ -300,6 +300,19 @@ start_status start_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
         return START_ENOMEM;
     }
     hipMemset(ctx->c.d_flags, 0, 256);
+    // the builds' readback words (two builds: start_build_scene runs the grid
+    // on a helper context beside the tree); without them the builds copy
+    // their counts back one by one
+    if (hipHostMalloc((void **)&ctx->c.rb, 2 * kReadbackWords * sizeof(unsigned),
+                      hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
+        if (hipHostGetDevicePointer((void **)&ctx->c.rb_dev, ctx->c.rb, 0) != hipSuccess) {
+            hipHostFree(ctx->c.rb);
+            ctx->c.rb = nullptr;
+            ctx->c.rb_dev = nullptr;
+        }
+    } else {
+        ctx->c.rb = nullptr;
+    }
     // this device's address of the fixed scratch of start_compute_rates_noalloc
     // (a failed lookup only disables that entry point, which then says so)
     (void)noalloc_init(device);
@@ -325,6 +338,7 @@ void start_ctx_destroy(start_ctx *ctx)
     for (hipEvent_t ev : ctx->c.ev_pool) hipEventDestroy(ev);
     if (ctx->c.stage_ev) hipEventDestroy(ctx->c.stage_ev);
     if (ctx->c.host_stage) hipHostFree(ctx->c.host_stage);
+    if (ctx->c.rb) hipHostFree(ctx->c.rb);
     hipFree(ctx->c.d_flags);
     if (ctx->c.own_stream) hipStreamDestroy(ctx->c.stream);
     delete ctx;
@@ -507,6 +521,10 @@ start_status start_build_scene(start_ctx *ctx, const start_box *box, int64_t n_s
     side.stream = c.stream2;
     side.d_flags = c.d_flags + 2;
     side.mem_owner = &c;
+    if (c.rb) {
+        side.rb = c.rb + kReadbackWords;
+        side.rb_dev = c.rb_dev + kReadbackWords;
+    }
     start_status gst = START_OK;
     std::thread worker([&]() {
         // no exception may leave the thread (it would end the process)

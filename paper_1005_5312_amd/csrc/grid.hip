@@ -97,6 +97,21 @@ __global__ void __launch_bounds__(kThreads) grid_keys(start_box box, double gs, 
 
 // Class-major keys: class * G^3 + cell; top.{x,y,z} are the last bins of
 // classes 0..2 (kBins where the class is unused).
+// The validation word, the reach histogram and the largest reach bits,
+// copied by one block into the context's pinned readback words (one host
+// wait for all three).
+__global__ void grid_readback(const unsigned *bflags, const unsigned *hist, const unsigned long long *hmax,
+                              unsigned *rb)
+{
+    for (int k = threadIdx.x; k < kBins; k += blockDim.x) rb[1 + k] = hist[k];
+    if (threadIdx.x == 0) {
+        rb[0] = *bflags;
+        const unsigned long long v = *hmax;
+        rb[1 + kBins] = (unsigned)v;
+        rb[2 + kBins] = (unsigned)(v >> 32);
+    }
+}
+
 __global__ void __launch_bounds__(kThreads) class_keys(int64_t n, const double *h, double gs, int64_t ncell,
                                                        int4 top, uint64_t *keys)
 {
@@ -460,10 +475,21 @@ start_status bin_gas(Ctx *c, const start_box &box, int64_t n, const double *xyz,
     unsigned flags = 0;
     unsigned long long hbits = 0;
     unsigned hh[kBins];
-    hipMemcpyAsync(&flags, bflags, sizeof(unsigned), hipMemcpyDeviceToHost, s);
-    hipMemcpyAsync(hh, hist, sizeof(hh), hipMemcpyDeviceToHost, s);
-    hipMemcpyAsync(&hbits, hmax, sizeof(hbits), hipMemcpyDeviceToHost, s);
+    static_assert(kBins + 3 <= kReadbackWords, "readback words");
+    if (c->rb) {
+        grid_readback<<<1, kBins, 0, s>>>(bflags, hist, hmax, c->rb_dev);
+    } else {
+        hipMemcpyAsync(&flags, bflags, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(hh, hist, sizeof(hh), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(&hbits, hmax, sizeof(hbits), hipMemcpyDeviceToHost, s);
+    }
     hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess && c->rb) {
+        const volatile unsigned *rb = c->rb;
+        flags = rb[0];
+        for (int k = 0; k < kBins; ++k) hh[k] = rb[1 + k];
+        hbits = (unsigned long long)rb[1 + kBins] | ((unsigned long long)rb[2 + kBins] << 32);
+    }
     if (e != hipSuccess || flags) {
         free_bins(c, b);
         if (e != hipSuccess) { c->err = hipGetErrorString(e); return START_EHIP; }

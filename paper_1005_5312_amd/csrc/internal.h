@@ -28,6 +28,8 @@ constexpr unsigned kFlagEqInput = 16u;    // equilibrium: n_H, Gamma or x out of
 
 constexpr size_t kPoolMaxBytes = (size_t)8 << 30;
 
+constexpr int kReadbackWords = 512;   // per build: flags, counts, the 256-bin reach histogram
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -62,6 +64,11 @@ struct Ctx {
     // a helper context (the second build of start_build_scene) allocates
     // through its owner: one budget, one pool
     Ctx *mem_owner = nullptr;
+    // pinned, device-visible words that the builds' own kernels fill with the
+    // counts and flags the host reads back mid-build (one host wait, no copy
+    // call): kReadbackWords per build, the owner's first, a helper's second
+    unsigned *rb = nullptr;       // host address
+    unsigned *rb_dev = nullptr;   // the same words as the device sees them
     // second stream and its event, for the concurrent scene builds
     hipStream_t stream2 = nullptr;
     hipEvent_t ev2 = nullptr;

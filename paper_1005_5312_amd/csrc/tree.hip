@@ -133,6 +133,20 @@ __global__ void __launch_bounds__(kThreads) radix_tree_kernel(const uint64_t *k,
 // Items of the octree: canonical cells (internal binary nodes whose octal
 // level is deeper than their parent's) and single-source leaves.  The sort key
 // (first << 5 | level) gives depth-first order; leaves take level 22.
+// The counts the host needs mid-build (internal nodes and leaves: the last
+// scanned position plus the last flag of each array) and the validation
+// word, written by one lane into the context's pinned readback words.
+__global__ void tree_readback(int n, const unsigned *pos_int, const unsigned *flag_int, const unsigned *pos_leaf,
+                              const unsigned *flag_leaf, const unsigned *bflags, unsigned *rb)
+{
+    if (threadIdx.x != 0) return;
+    rb[0] = n > 1 ? pos_int[n - 2] : 0u;
+    rb[1] = n > 1 ? flag_int[n - 2] : 0u;
+    rb[2] = pos_leaf[n - 1];
+    rb[3] = flag_leaf[n - 1];
+    rb[4] = *bflags;
+}
+
 __global__ void __launch_bounds__(kThreads) mark_items(const uint64_t *k, int n, const int *lo, const int *delta,
                                                        const int *parent_int, unsigned *flag_int,
                                                        unsigned *flag_leaf)
@@ -642,15 +656,24 @@ start_status build_tree(Ctx *c, const start_box &box, int64_t n, const double *x
     if (n > 1) exclusive_scan_u32(pos_int, n - 1, scan_tmp, s);
     exclusive_scan_u32(pos_leaf, n, scan_tmp, s);
     unsigned h[4] = {0, 0, 0, 0};
-    if (n > 1) {
-        hipMemcpyAsync(&h[0], pos_int + (n - 2), sizeof(unsigned), hipMemcpyDeviceToHost, s);
-        hipMemcpyAsync(&h[1], flag_int + (n - 2), sizeof(unsigned), hipMemcpyDeviceToHost, s);
-    }
-    hipMemcpyAsync(&h[2], pos_leaf + (n - 1), sizeof(unsigned), hipMemcpyDeviceToHost, s);
-    hipMemcpyAsync(&h[3], flag_leaf + (n - 1), sizeof(unsigned), hipMemcpyDeviceToHost, s);
     unsigned flags = 0;
-    hipMemcpyAsync(&flags, bflags, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    if (c->rb) {
+        tree_readback<<<1, 64, 0, s>>>(ni, pos_int, flag_int, pos_leaf, flag_leaf, bflags, c->rb_dev);
+    } else {
+        if (n > 1) {
+            hipMemcpyAsync(&h[0], pos_int + (n - 2), sizeof(unsigned), hipMemcpyDeviceToHost, s);
+            hipMemcpyAsync(&h[1], flag_int + (n - 2), sizeof(unsigned), hipMemcpyDeviceToHost, s);
+        }
+        hipMemcpyAsync(&h[2], pos_leaf + (n - 1), sizeof(unsigned), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(&h[3], flag_leaf + (n - 1), sizeof(unsigned), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(&flags, bflags, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    }
     hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess && c->rb) {
+        const volatile unsigned *rb = c->rb;
+        for (int k = 0; k < 4; ++k) h[k] = rb[k];
+        flags = rb[4];
+    }
     if (e != hipSuccess) {
         c->err = hipGetErrorString(e);
         dfree(c, tm, tmp_bytes);
