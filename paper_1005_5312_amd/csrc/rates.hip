@@ -656,8 +656,8 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             qt[1] = q.z;
             qt[2] = q.w;
         }
-        int tb[3];
-        double fb[3];
+        int tb[3] = {0, 0, 0};
+        double fb[3] = {0.0, 0.0, 0.0};
         if constexpr (PREC == START_FP64) {
             const unsigned tcell = L.tcell[tl];
             tb[0] = (int)(tcell >> (2 * gl));
@@ -665,13 +665,6 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             tb[2] = (int)(tcell & (unsigned)(G - 1));
 #pragma unroll
             for (int k = 0; k < 3; ++k) fb[k] = L.tfrac[tl][k];
-        } else {
-            const unsigned fmask = (1u << sh) - 1u;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                tb[k] = (int)(qt[k] >> sh);
-                fb[k] = (double)(qt[k] & fmask) * frac_scale;
-            }
         }
         // the ray runs from the (virtual) source (t = 0) to the target (t = 1):
         // D = target - source, the march starts in the source's cell
@@ -692,7 +685,9 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             w = (T)m.w;
         } else {
             // centre as 32-bit fixed point of the box: the top g bits are the
-            // cell, the rest the fraction inside it (exact in FP64)
+            // cell, the rest the fraction inside it (exact in FP64); D is the
+            // difference of the two fixed-point coordinates in cells, exact
+            // (both below 2^32, scaled by a power of two)
             GU *const r = code >= 0 ? momq + 4 * (int64_t)code : srcq + 4 * (int64_t)(-code - 1);
             const uint4 m = make_uint4(r[0], r[1], r[2], r[3]);
             const unsigned q[3] = {m.x, m.y, m.z};
@@ -701,7 +696,7 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             for (int k = 0; k < 3; ++k) {
                 ab[k] = (int)(q[k] >> sh);
                 fa[k] = (double)(q[k] & fmask) * frac_scale;
-                D[k] = (double)(tb[k] - ab[k]) + (fb[k] - fa[k]);
+                D[k] = ((double)qt[k] - (double)q[k]) * frac_scale;
             }
             w = (T)__uint_as_float(m.w);
         }
