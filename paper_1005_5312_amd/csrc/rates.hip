@@ -108,8 +108,9 @@ __device__ inline bool accept_box(const double4 b, const double u[3], double the
     for (int k = 0; k < 3; ++k) {
         const double a = lo[k] - u[k];
         const double c = u[k] - (lo[k] + b.w);
-        const double m = a > c ? a : c;
-        d[k] = m > 0.0 ? m : 0.0;
+        // max(0, a, c) as two v_max_f64 (the operands are finite, so the
+        // value is the same as with compares and selects)
+        d[k] = fmax(fmax(a, c), 0.0);
     }
     const double d2 = fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
     return b.w * b.w <= theta2 * d2;
@@ -524,9 +525,8 @@ struct __align__(16) NodeRec {
     uint64_t mask;
 };
 
-// TF: the target's fraction inside its cell in FP64 for the FP64 path; for
-// the FP32 path its 32-bit box fixed-point coordinates (fixed32; tcell is
-// then unused).
+// TF: the target's position in cells (FP64) for the FP64 path; for the FP32
+// path its 32-bit box fixed-point coordinates (fixed32), kept in the items.
 template <typename T, typename TF>
 struct WaveLds {
     static constexpr bool kFp64 = sizeof(TF) == 8;
@@ -537,8 +537,7 @@ struct WaveLds {
     // FP64 path: the item as code and target lane
     int code[kFp64 ? kRing : 1];  // node index, or -(sorted source index)-1
     T term[kRing];
-    unsigned tcell[kWave];        // FP64 path: target cell, linear index
-    TF tfrac[kFp64 ? kWave : 1][3];   // FP64 path: target fraction inside its cell
+    TF tpos[kFp64 ? kWave : 1][3];    // FP64 path: target position in cells
     unsigned char lane[kFp64 ? kRing : 1];   // FP64 path: target lane of the item
 };
 
@@ -590,8 +589,7 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
     int self = -1;   // source indices fit in 31 bits (n_s <= 2^30)
     unsigned tq[3] = {0u, 0u, 0u};   // FP32 path: this lane's target as fixed32 box coordinates
     {
-        int bi[3] = {0, 0, 0};
-        double fb[3] = {0.0, 0.0, 0.0};
+        double B[3] = {0.0, 0.0, 0.0};
         if (valid) {
             const double4 p = P.tgt[it];
             const double x[3] = {p.x, p.y, p.z};
@@ -601,17 +599,15 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             for (int k = 0; k < 3; ++k) {
                 const double v = (x[k] - P.lo[k]) * P.inv_size;
                 u[k] = v > 1.0 ? 1.0 : (v < 0.0 ? 0.0 : v);
-                const double B = (x[k] - P.lo[k]) * P.gs;
-                // a target on the top face sits in the last cell at fraction 1
-                bi[k] = clampi((int)floor(B), G);
-                fb[k] = B - (double)bi[k];
+                // the position in cells: its floor (the last cell for a target
+                // on the top face) plus the fraction, both exact, sum to it
+                B[k] = (x[k] - P.lo[k]) * P.gs;
             }
         }
-        L.tcell[lane] = (unsigned)((bi[0] * G + bi[1]) * G + bi[2]);
         if constexpr (PREC == START_FP64) {
-            L.tfrac[lane][0] = fb[0];
-            L.tfrac[lane][1] = fb[1];
-            L.tfrac[lane][2] = fb[2];
+            L.tpos[lane][0] = B[0];
+            L.tpos[lane][1] = B[1];
+            L.tpos[lane][2] = B[2];
         } else {
             const double4 p = valid ? P.tgt[it] : make_double4(P.lo[0], P.lo[1], P.lo[2], 0.0);
             tq[0] = fixed32(p.x, P.lo[0], P.inv_size);
@@ -656,15 +652,10 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
             qt[1] = q.z;
             qt[2] = q.w;
         }
-        int tb[3] = {0, 0, 0};
-        double fb[3] = {0.0, 0.0, 0.0};
+        double tp[3] = {0.0, 0.0, 0.0};
         if constexpr (PREC == START_FP64) {
-            const unsigned tcell = L.tcell[tl];
-            tb[0] = (int)(tcell >> (2 * gl));
-            tb[1] = (int)((tcell >> gl) & (unsigned)(G - 1));
-            tb[2] = (int)(tcell & (unsigned)(G - 1));
 #pragma unroll
-            for (int k = 0; k < 3; ++k) fb[k] = L.tfrac[tl][k];
+            for (int k = 0; k < 3; ++k) tp[k] = L.tpos[tl][k];
         }
         // the ray runs from the (virtual) source (t = 0) to the target (t = 1):
         // D = target - source, the march starts in the source's cell
@@ -680,7 +671,7 @@ __device__ __forceinline__ void rates_tile(const Item &P, const int4 tile, WaveL
                 // a source on the top face sits in the last cell at fraction 1
                 ab[k] = clampi((int)floor(A[k]), G);
                 fa[k] = A[k] - (double)ab[k];
-                D[k] = ((double)tb[k] + fb[k]) - A[k];
+                D[k] = tp[k] - A[k];
             }
             w = (T)m.w;
         } else {
