@@ -248,15 +248,20 @@ def serve_bench(rates, window_s=15.0, max_requests=2000, n_scenes=32, seed=5, au
         th = threading.Thread(target=client)
         th.start()
         th.join()
+        errors = []
         for f in futs:
-            f.result(timeout=600)
+            try:
+                f.result(timeout=600)
+            except Exception as e:   # a failed request is counted, not fatal to the run
+                errors.append(repr(e))
         srv.drain()
         srv.close()
         st = srv.latency_stats()
         rps = st["requests"] / st["span_s"] if st.get("span_s") else None
         st.update({"arrival_rate_per_s": lam, "requests_asked": n_req, "requests_per_s": rps,
                    "saturated": bool(rps is not None and rps < 0.9 * lam),
-                   "scene_builds": srv.builds, "scene_evictions": srv.evictions, "hbm_budget_bytes": bud})
+                   "scene_builds": srv.builds, "scene_evictions": srv.evictions, "hbm_budget_bytes": bud,
+                   "failed_requests": len(errors), "first_error": errors[0] if errors else None})
         return st
 
     out = [run(lam, budget) for lam in rates]

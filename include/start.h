@@ -245,7 +245,11 @@ start_status start_compute_rates_batched(start_ctx *ctx, int n_items, const star
  * Trees, grids, self_src and outputs must stay allocated, at the same
  * addresses and sizes, until start_rates_plan_free.  A plan is used with the
  * context that made it; launches of one plan on one stream run in order.
- * Create and free synchronise the context stream; launch is asynchronous. */
+ * Create and free synchronise the context stream; launch is asynchronous.
+ * Create captures the context stream (thread-local capture mode): another
+ * host thread that frees device memory or synchronises the whole device
+ * while it runs invalidates the capture, and create then returns
+ * START_EHIP; callers with such threads serialise them with plan creation. */
 typedef struct start_plan start_plan;
 start_status start_rates_plan_create(start_ctx *ctx, int n_items, const start_item *items, start_plan **out);
 start_status start_rates_plan_launch(start_ctx *ctx, start_plan *plan);

@@ -200,6 +200,12 @@ class GpuExecutor(Executor):
         self.stage = [None] * n_slots    # pinned staging of targets per slot
         self.plans = plans
         self.plan_cache = [dict() for _ in range(n_slots)]   # (scene key, prec, theta, sigma) -> (plan, out)
+        # A plan's creation captures its slot stream into a HIP graph; device
+        # memory freed (or the device synchronised) by another thread during
+        # the capture would invalidate it.  Builds and frees, which run on
+        # the builder thread, and plan creation and release therefore hold
+        # this lock (taken with no scheduler lock held by its other users).
+        self.mm_lock = threading.Lock()
 
     def _est(self, n_t, n_s, n_gas, grid_log2, prec):
         return self.binding.estimate_bytes(n_t, n_s, n_gas, grid_log2, prec)
@@ -218,23 +224,26 @@ class GpuExecutor(Executor):
         t = self.torch
         c = self.build_ctx
         d = lambda a: t.from_numpy(np.ascontiguousarray(a)).to(self.dev)  # noqa: E731
-        with t.cuda.stream(c.stream):
-            gas = d(scene.gas_xyz)
-            ss = None if scene.self_src is None else d(np.asarray(scene.self_src, dtype=np.int64))
-            tree, grid = c.build_scene(scene.box, d(scene.src_xyz), d(scene.src_lum), gas, d(scene.gas_h),
-                                       d(scene.gas_nhi), scene.grid_log2)
-        c.stream.synchronize()
+        with self.mm_lock:
+            with t.cuda.stream(c.stream):
+                gas = d(scene.gas_xyz)
+                ss = None if scene.self_src is None else d(np.asarray(scene.self_src, dtype=np.int64))
+                tree, grid = c.build_scene(scene.box, d(scene.src_xyz), d(scene.src_lum), gas, d(scene.gas_h),
+                                           d(scene.gas_nhi), scene.grid_log2)
+            c.stream.synchronize()
         return tree, grid, gas, ss
 
     def free_scene(self, handle):
         tree, grid = handle[0], handle[1]
-        tree.free()
-        grid.free()
+        with self.mm_lock:
+            tree.free()
+            grid.free()
 
     def forget_scene(self, key):
-        for slot, cache in enumerate(self.plan_cache):
-            for k in [k for k in cache if k[0] == key]:
-                cache.pop(k)[0].free()
+        with self.mm_lock:
+            for slot, cache in enumerate(self.plan_cache):
+                for k in [k for k in cache if k[0] == key]:
+                    cache.pop(k)[0].free()
 
     def launch(self, slot, batch, scenes):
         t = self.torch
@@ -258,8 +267,9 @@ class GpuExecutor(Executor):
                     entry = self.plan_cache[slot].get(key)
                     if entry is None:   # created (and run once) on first use
                         out = t.empty(r.n_t, dtype=dt, device=self.dev)
-                        plan = ctx.rates_plan([dict(tree=tree, grid=grid, tgt_xyz=gas, self_src=gss, theta=r.theta,
-                                                    sigma=r.sigma, prec=r.prec, out=out)])
+                        with self.mm_lock:
+                            plan = ctx.rates_plan([dict(tree=tree, grid=grid, tgt_xyz=gas, self_src=gss,
+                                                        theta=r.theta, sigma=r.sigma, prec=r.prec, out=out)])
                         self.plan_cache[slot][key] = (plan, out)
                     else:
                         plan, out = entry
