@@ -95,8 +95,6 @@ __global__ void __launch_bounds__(kThreads) grid_keys(start_box box, double gs, 
         if (lh[t]) atomicAdd(&hist[t], lh[t]);
 }
 
-// Class-major keys: class * G^3 + cell; top.{x,y,z} are the last bins of
-// classes 0..2 (kBins where the class is unused).
 // The validation word, the reach histogram and the largest reach bits,
 // copied by one block into the context's pinned readback words (one host
 // wait for all three).
@@ -112,6 +110,8 @@ __global__ void grid_readback(const unsigned *bflags, const unsigned *hist, cons
     }
 }
 
+// Class-major keys: class * G^3 + cell; top.{x,y,z} are the last bins of
+// classes 0..2 (kBins where the class is unused).
 __global__ void __launch_bounds__(kThreads) class_keys(int64_t n, const double *h, double gs, int64_t ncell,
                                                        int4 top, uint64_t *keys)
 {

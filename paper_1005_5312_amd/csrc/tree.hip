@@ -130,9 +130,6 @@ __global__ void __launch_bounds__(kThreads) radix_tree_kernel(const uint64_t *k,
     if (hi != gamma + 1) parent_int[gamma + 1] = i;
 }
 
-// Items of the octree: canonical cells (internal binary nodes whose octal
-// level is deeper than their parent's) and single-source leaves.  The sort key
-// (first << 5 | level) gives depth-first order; leaves take level 22.
 // The counts the host needs mid-build (internal nodes and leaves: the last
 // scanned position plus the last flag of each array) and the validation
 // word, written by one lane into the context's pinned readback words.
@@ -147,6 +144,9 @@ __global__ void tree_readback(int n, const unsigned *pos_int, const unsigned *fl
     rb[4] = *bflags;
 }
 
+// Items of the octree: canonical cells (internal binary nodes whose octal
+// level is deeper than their parent's) and single-source leaves.  The sort key
+// (first << 5 | level) gives depth-first order; leaves take level 22.
 __global__ void __launch_bounds__(kThreads) mark_items(const uint64_t *k, int n, const int *lo, const int *delta,
                                                        const int *parent_int, unsigned *flag_int,
                                                        unsigned *flag_leaf)
